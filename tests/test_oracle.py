@@ -1,0 +1,355 @@
+"""Pins for the FP64 oracle: things the geometry and the paper fix, none of which
+re-types the oracle's own formulas.
+
+* lattice closed forms (cubes, truncated octahedra, rhombic dodecahedra);
+* volume conservation, neighbour symmetry, Euler's formula, the pyramid identity;
+* Meijering's mean face count for a Poisson process (the paper's section 3 quotes
+  the vertex/face statistics of Poisson tessellations);
+* an independent Qhull tessellation (scipy.spatial, the library the paper
+  itself builds on) of a periodically tiled point set;
+* exhaustive half-space vertex enumeration for tiny bounded sets;
+* exact-recovery and conservation properties of the gradient, grid and adjoint.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1601_06429_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- lattices
+@pytest.mark.parametrize("n_side", [4, 8])
+def test_sc_lattice_cubes(oracle, n_side):
+    p = wl.lattice("sc", n_side)
+    a = 1.0 / n_side
+    c = oracle.cells(p, 0.0, 1.0)
+    assert np.all(c.nnb == 6)
+    np.testing.assert_allclose(c.volume, a ** 3, rtol=1e-14)
+    assert np.all(c.topo[:, :3] == [8, 12, 6])
+    for q in range(0, len(p), 7):
+        A, C, d = c.faces(q)
+        np.testing.assert_allclose(A, a * a, rtol=1e-13)
+        np.testing.assert_allclose(d, a, rtol=1e-14)
+        # face centroids sit half a spacing along the axes
+        np.testing.assert_allclose(np.sort(np.abs(C).max(axis=1)), a / 2, rtol=1e-13)
+        # the six neighbours are the +-axis lattice neighbours
+        d_vec = np.mod(p[c.neighbours(q)] - p[q] + 0.5, 1.0) - 0.5
+        assert sorted(map(tuple, np.rint(d_vec / a).astype(int))) == sorted(
+            [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)])
+
+
+def test_sc_lattice_large_box(oracle):
+    p = wl.lattice("sc", 4, length=100.0)
+    c = oracle.cells(p, 0.0, 100.0)
+    assert np.all(c.nnb == 6)
+    np.testing.assert_allclose(c.volume, 25.0 ** 3, rtol=1e-14)
+
+
+def test_bcc_truncated_octahedra(oracle):
+    n = 4
+    a = 1.0 / n
+    c = oracle.cells(wl.lattice("bcc", n), 0.0, 1.0)
+    assert np.all(c.nnb == 14)
+    np.testing.assert_allclose(c.volume, a ** 3 / 2, rtol=1e-14)
+    assert np.all(c.topo[:, :3] == [24, 36, 14])
+    assert np.all(c.topo[:, 3] == 3)
+    for q in range(0, c.volume.size, 11):
+        A, _, d = c.faces(q)
+        hexa = np.isclose(d, a * math.sqrt(3) / 2)
+        sq = np.isclose(d, a)
+        assert hexa.sum() == 8 and sq.sum() == 6
+        np.testing.assert_allclose(A[hexa], 3 * math.sqrt(3) * a * a / 16, rtol=1e-13)
+        np.testing.assert_allclose(A[sq], a * a / 8, rtol=1e-13)
+
+
+def test_fcc_rhombic_dodecahedra(oracle):
+    n = 4
+    a = 1.0 / n
+    c = oracle.cells(wl.lattice("fcc", n), 0.0, 1.0)
+    assert np.all(c.nnb == 12)
+    np.testing.assert_allclose(c.volume, a ** 3 / 4, rtol=1e-14)
+    assert np.all(c.topo[:, :3] == [14, 24, 12])
+    assert np.all(c.topo[:, 3] == 4)  # the six 4-valent vertices of the rhombic dodecahedron
+    for q in range(0, c.volume.size, 13):
+        A, _, d = c.faces(q)
+        np.testing.assert_allclose(d, a / math.sqrt(2), rtol=1e-14)
+        np.testing.assert_allclose(A, math.sqrt(2) * a * a / 8, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- random sets
+@pytest.fixture(scope="module")
+def uniform_cells(oracle):
+    w = wl.workload1()
+    return w, oracle.cells(w.pos, w.box_lo, w.box_hi)
+
+
+def test_volume_conservation(uniform_cells):
+    w, c = uniform_cells
+    assert abs(c.volume.sum() - 1.0) < 1e-12
+    assert np.all(c.volume > 0)
+    assert np.all(c.flags == 0)
+
+
+def test_euler_and_simple_vertices(uniform_cells):
+    _, c = uniform_cells
+    v, e, f, deg = c.topo[:, 0], c.topo[:, 1], c.topo[:, 2], c.topo[:, 3]
+    assert np.all(v - e + f == 2)
+    assert np.all(deg == 3)
+    assert np.all(v == 2 * f - 4)
+    assert np.all(c.nnb == f)
+
+
+def test_neighbour_symmetry(uniform_cells):
+    w, c = uniform_cells
+    L = 1.0
+    faces = {}
+    for q in range(w.n):
+        A, C, _ = c.faces(q)
+        for j, a, cc in zip(c.neighbours(q), A, C):
+            faces[(q, int(j))] = (a, w.pos[q] + cc)
+    for (i, j), (a, cen) in faces.items():
+        assert (j, i) in faces, (i, j)
+        a2, cen2 = faces[(j, i)]
+        assert abs(a - a2) <= 1e-12 * max(a, 1e-300) + 1e-15
+        dc = np.mod(cen - cen2 + 0.5 * L, L) - 0.5 * L
+        assert np.all(np.abs(dc) < 1e-12)
+
+
+def test_pyramid_identity(uniform_cells):
+    w, c = uniform_cells
+    for q in range(w.n):
+        A, _, d = c.faces(q)
+        assert abs((A * d).sum() / 6.0 - c.volume[q]) <= 1e-12 * c.volume[q]
+
+
+def test_meijering_mean_faces(uniform_cells):
+    # Poisson-Voronoi mean face count 2 + 48 pi^2 / 35 (Meijering 1953)
+    _, c = uniform_cells
+    assert abs(c.nnb.mean() - (2 + 48 * math.pi ** 2 / 35)) < 0.15
+
+
+def test_meijering_on_larger_box(oracle):
+    w = wl.uniform_box(20000, length=3.0, seed=7)
+    c = oracle.cells(w.pos, w.box_lo, w.box_hi, query=np.arange(0, w.n, 2))
+    se = c.nnb.std() / math.sqrt(c.nnb.size)
+    assert abs(c.nnb.mean() - (2 + 48 * math.pi ** 2 / 35)) < 4 * se
+
+
+def test_against_qhull_periodic_tiling(oracle):
+    """scipy's Qhull Voronoi of the 27-fold tiled set must give the same facets and volumes."""
+    from scipy.spatial import ConvexHull, Voronoi
+
+    rng = np.random.default_rng(11)
+    n = 400
+    L = 2.5
+    p = rng.random((n, 3)) * L
+    shifts = np.array(list(itertools.product((-1, 0, 1), repeat=3)), dtype=float) * L
+    tiled = (p[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    centre = int(np.flatnonzero(np.all(shifts == 0, axis=1))[0])
+    vor = Voronoi(tiled)
+    c = oracle.cells(p, 0.0, L)
+    nb = [set() for _ in range(n)]
+    for a, b in vor.ridge_points:
+        if a // n == centre:
+            nb[a % n].add(int(b % n))
+        if b // n == centre:
+            nb[b % n].add(int(a % n))
+    for i in range(n):
+        assert set(c.neighbours(i).tolist()) == nb[i], i
+        region = vor.regions[vor.point_region[centre * n + i]]
+        assert -1 not in region
+        vol = ConvexHull(vor.vertices[region]).volume
+        assert abs(vol - c.volume[i]) <= 1e-9 * vol
+
+
+def _exhaustive_cell(p, i, lo, hi):
+    """All vertices of the bounded cell by brute-force plane-triple enumeration."""
+    planes = []
+    for j in range(len(p)):
+        if j == i:
+            continue
+        nvec = p[j] - p[i]
+        planes.append((nvec, 0.5 * (p[j] @ p[j] - p[i] @ p[i]), j))
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = 1.0
+        planes.append((e, hi[ax], -1))
+        planes.append((-e, -lo[ax], -1))
+    N = np.array([pl[0] for pl in planes])
+    D = np.array([pl[1] for pl in planes])
+    verts = []
+    for a, b, cidx in itertools.combinations(range(len(planes)), 3):
+        M = N[[a, b, cidx]]
+        if abs(np.linalg.det(M)) < 1e-12:
+            continue
+        y = np.linalg.solve(M, D[[a, b, cidx]])
+        if np.all(N @ y <= D + 1e-10):
+            verts.append(y)
+    verts = np.array(verts)
+    facets = set()
+    for k, (nvec, d, tag) in enumerate(planes):
+        if tag < 0:
+            continue
+        on = verts[np.abs(verts @ nvec - d) <= 1e-9 * np.linalg.norm(nvec)]
+        if len(on) >= 3:
+            q = on - on.mean(axis=0)
+            if np.linalg.svd(q, compute_uv=False)[1] > 1e-9:
+                facets.add(tag)
+    return verts, facets
+
+
+def test_exhaustive_tiny_bounded_sets(oracle):
+    from scipy.spatial import ConvexHull
+
+    rng = np.random.default_rng(5)
+    lo, hi = np.zeros(3), np.ones(3)
+    for trial in range(4):
+        p = rng.random((12, 3))
+        c = oracle.cells(p, lo, hi, periodic=False)
+        for i in range(len(p)):
+            verts, facets = _exhaustive_cell(p, i, lo, hi)
+            vol = ConvexHull(verts).volume
+            assert abs(vol - c.volume[i]) <= 1e-10 * vol
+            assert set(c.neighbours(i).tolist()) == facets
+        assert abs(c.volume.sum() - 1.0) < 1e-12
+
+
+def test_bounded_world_flags(oracle):
+    rng = np.random.default_rng(3)
+    p = rng.random((600, 3))
+    c = oracle.cells(p, 0.0, 1.0, periodic=False)
+    assert abs(c.volume.sum() - 1.0) < 1e-12
+    ball_out = np.any((p - 2 * c.rmax[:, None] < 0) | (p + 2 * c.rmax[:, None] > 1), axis=1)
+    assert np.array_equal((c.flags & oracle.FLAG_INCOMPLETE) != 0, ball_out)
+    # a cell that still touches a wall is necessarily flagged incomplete
+    wall = (c.flags & oracle.FLAG_WALL) != 0
+    assert wall.any() and np.all(ball_out[wall])
+
+
+def test_density_definition(uniform_cells, oracle):
+    w, c = uniform_cells
+    np.testing.assert_allclose(oracle.density(c.volume, c.volume), 1.0, rtol=0)
+    np.testing.assert_allclose(oracle.density(w.mass, c.volume) * c.volume, w.mass, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- gradient
+def test_gradient_recovers_linear_field(oracle):
+    rng = np.random.default_rng(9)
+    p = rng.random((800, 3))
+    c = oracle.cells(p, 0.0, 1.0, periodic=False)
+    off, ids = c.csr()
+    g = np.array([0.7, -1.3, 2.1])
+    rho = 5.0 + p @ g
+    grad = oracle.gradient(p, 0.0, 1.0, False, off, ids, rho)
+    np.testing.assert_allclose(grad, np.broadcast_to(g, grad.shape), atol=1e-10)
+    grad0 = oracle.gradient(p, 0.0, 1.0, False, off, ids, np.full(len(p), 3.0))
+    assert np.abs(grad0).max() == 0.0
+
+
+def test_gradient_zero_on_lattice(oracle):
+    p = wl.lattice("bcc", 4)
+    c = oracle.cells(p, 0.0, 1.0)
+    off, ids = c.csr()
+    rho = oracle.density(np.ones(len(p)), c.volume)
+    grad = oracle.gradient(p, 0.0, 1.0, True, off, ids, rho)
+    assert np.abs(grad).max() < 1e-9
+
+
+# ---------------------------------------------------------------- grid
+def test_grid_mass_conservation_and_unit_field(oracle, uniform_cells):
+    w, c = uniform_cells
+    rng = np.random.default_rng(2)
+    m = rng.uniform(0.5, 2.0, w.n)
+    rho = oracle.density(m, c.volume)
+    dims = (16, 16, 16)
+    g = oracle.grid(w.pos, 0.0, 1.0, True, rho, dims)
+    assert abs(g.sum() / np.prod(dims) - m.sum()) <= 1e-12 * m.sum()
+    ones = oracle.grid(w.pos, 0.0, 1.0, True, np.ones(w.n), dims)
+    np.testing.assert_allclose(ones, 1.0, atol=1e-12)
+
+
+def test_grid_aligned_lattice_exact(oracle):
+    # cube cells of side 2h centred on even voxel corners cover exactly 2x2x2 voxels
+    nv = 8
+    h = 1.0 / nv
+    k = np.arange(nv // 2) * 2 * h
+    p = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(4)
+    val = rng.uniform(1.0, 3.0, len(p))
+    g = oracle.grid(p, 0.0, 1.0, True, val, (nv, nv, nv))
+    for idx, v in enumerate(val):
+        a, b, cc = np.rint(p[idx] / h).astype(int)
+        for da, db, dc in itertools.product((-1, 0), repeat=3):
+            assert abs(g[(a + da) % nv, (b + db) % nv, (cc + dc) % nv] - v) < 1e-13
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_matches_finite_differences(oracle):
+    rng = np.random.default_rng(21)
+    n = 300
+    p = rng.random((n, 3))
+    c = oracle.cells(p, 0.0, 1.0)
+    gw = rng.normal(size=n)  # dL/dV for L = sum g_i V_i
+    adj = oracle.adjoint(c, gw)
+    h = 1e-6
+    for k in rng.choice(n, 6, replace=False):
+        for ax in range(3):
+            pp = p.copy()
+            pm = p.copy()
+            pp[k, ax] += h
+            pm[k, ax] -= h
+            vp = oracle.cells(pp, 0.0, 1.0).volume
+            vm = oracle.cells(pm, 0.0, 1.0).volume
+            fd = (gw * (vp - vm)).sum() / (2 * h)
+            assert abs(fd - adj[k, ax]) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_adjoint_invariants(oracle, uniform_cells):
+    w, c = uniform_cells
+    # translation invariance: sum over all particles of dV_i/dx_k = 0 for every i;
+    # volume conservation: sum_i dV_i/dx_k = 0 for every k  (both with g = e_i / ones)
+    ones = oracle.adjoint(c, np.ones(w.n))
+    assert np.abs(ones).max() < 1e-13
+    for q in range(0, w.n, 97):
+        A, C, d = c.faces(q)
+        ids = c.neighbours(q)
+        D = np.mod(w.pos[ids] - w.pos[q] + 0.5, 1.0) - 0.5
+        self_term = ((A / d)[:, None] * C).sum(0)
+        other = ((A / d)[:, None] * (D - C)).sum(0)
+        assert np.abs(self_term + other).max() < 1e-14
+
+
+def test_adjoint_sc_closed_form(oracle):
+    n_side = 4
+    a = 1.0 / n_side
+    p = wl.lattice("sc", n_side)
+    c = oracle.cells(p, 0.0, 1.0)
+    for q in range(0, len(p), 5):
+        A, C, d = c.faces(q)
+        ids = c.neighbours(q)
+        D = np.mod(p[ids] - p[q] + 0.5, 1.0) - 0.5
+        dVi_dxj = (A / d)[:, None] * (D - C)
+        np.testing.assert_allclose(dVi_dxj, (a * a / 2) * D / a, atol=1e-15)
+
+
+# ---------------------------------------------------------------- paper fixture
+def test_buffer_width_worked_example():
+    with open(os.path.join(GOLDEN, "ghost_width.json")) as f:
+        ex = json.load(f)
+    w = wl.ghost_width(ex["border_factor"], ex["inter_particle_distance"])
+    assert round(w, ex["printed_decimals"]) == ex["buffer_thickness"]
+
+
+def test_workload_shapes():
+    w1 = wl.workload1()
+    assert w1.pos.shape == (4096, 3) and w1.pos.dtype == np.float64
+    assert wl.duplicate_rows(w1.pos).size == 0
+    w5 = wl.workload5(n=4096)
+    assert w5.pos.dtype == np.float32 and np.all((w5.pos >= 0) & (w5.pos < 1))
+    assert wl.duplicate_rows(w5.pos).size == 0
