@@ -1,0 +1,207 @@
+/*
+ * vt.h -- C ABI of the MI355X Voronoi tessellation engine (libvt.so).
+ *
+ * The engine computes, for every owned particle of a periodic box or of a
+ * bounded sub-volume with its buffer ("ghost") particles, the quantities the
+ * paper lists per particle: the immediate-neighbour list, the Voronoi cell
+ * volume, the Voronoi density (mass / volume), the density gradient, and the
+ * average density on a regular grid (abstract; section 2, post-processing
+ * paragraph).  Neighbours are the particles that share a facet with the cell
+ * (section 2); outputs come back in input order with neighbour ids replaced by
+ * the callers' global ids (section 2, gather paragraph).  Periodic boundary
+ * conditions are supported (abstract; section 4).  The volume adjoint
+ * (vt_backward) is an extension for gradient-based use; it is not in the paper.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device pointers owned by the caller;
+ *     the library never frees them.  Pointers marked "host" are read before
+ *     the call returns.
+ *   - Every call except vt_query, vt_destroy and vt_status_string only
+ *     enqueues work on `stream` (a hipStream_t passed as void*; NULL is the
+ *     default stream) and returns; results are ready when the stream is.
+ *   - Argument errors are returned synchronously and nothing is enqueued.
+ *     Errors found on the device (duplicate particles, a cell that reaches its
+ *     own periodic image, a capacity overflow) are recorded in a device status
+ *     word that vt_query returns; outputs are undefined after such an error.
+ *   - Per-cell soft conditions are reported in cell_status (VT_CELL_* bits).
+ *   - The context owns all scratch memory.  vt_build allocates it on first use
+ *     and reuses it when called again on the same context with sizes that fit,
+ *     so repeated builds of the same shape allocate nothing.
+ *   - Calls on one context must be serialised by the caller (same stream).
+ */
+#ifndef VT_H
+#define VT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vt_ctx vt_ctx;
+
+typedef enum {
+    VT_OK = 0,
+    VT_ERR_ARG = 1,           /* invalid argument (returned synchronously) */
+    VT_ERR_HIP = 2,           /* a HIP runtime call failed */
+    VT_ERR_OOM = 3,           /* device allocation failed */
+    VT_ERR_DUPLICATE = 4,     /* two particles of one world coincide exactly */
+    VT_ERR_BOX_TOO_SMALL = 5, /* a periodic cell reaches a second image (2R >= L/2) */
+    VT_ERR_CAPACITY = 6,      /* a cell exceeds the largest kernel capacity, or nbr_cap is too small */
+    VT_ERR_STATE = 7,         /* call order violated (e.g. vt_backward without faces) */
+    VT_ERR_TOPOLOGY = 8       /* inconsistent clipping decision (should not happen) */
+} vt_status;
+
+typedef enum { VT_F32 = 0, VT_F64 = 1 } vt_dtype;
+
+typedef enum {
+    VT_PREC_FP64 = 0,  /* every step in FP64 */
+    VT_PREC_MIXED = 1  /* FP32 clipping with FP64 fallback predicates; FP64 geometry */
+} vt_precision;
+
+/* per-cell status bits (cell_status output) */
+#define VT_CELL_OK 0
+#define VT_CELL_INCOMPLETE 1   /* bounded world: ball(x, 2R) leaves the box, or a wall face survived */
+#define VT_CELL_RETRIED 2      /* computed by the large-capacity kernel */
+#define VT_CELL_FAILED 4       /* could not be computed (see vt_query status) */
+
+/*
+ * One world ("item").  Its particles are pos[offset .. offset + n_owned) (cells
+ * are computed for these) followed by pos[offset + n_owned .. + n_ghost) (buffer
+ * particles that only clip).  Items must be packed back to back in item order:
+ * items[0].offset == 0 and items[b+1].offset == items[b].offset + n_owned + n_ghost.
+ *   periodic = 1: the box [lo, hi) is periodic; it must be a cube, every
+ *                 particle must lie in it, and n_ghost must be 0.
+ *   periodic = 0: the box [lo, hi] bounds the world; its walls are the initial
+ *                 cell (the buffer zone of section 2: cells that the walls still
+ *                 touch, or whose security ball leaves the box, are flagged
+ *                 VT_CELL_INCOMPLETE).
+ * Owned outputs are dense over items: the owned particle k of item b is output
+ * row sum_{b' < b} n_owned(b') + k.
+ */
+typedef struct {
+    int64_t offset;
+    int64_t n_owned;
+    int64_t n_ghost;
+    int32_t periodic;
+    int32_t reserved;
+    double lo[3];
+    double hi[3];
+} vt_item;
+
+/* Options; a zero field selects the default. */
+typedef struct {
+    int32_t precision;     /* vt_precision, default VT_PREC_FP64 */
+    int32_t want_faces;    /* keep facet areas and centroids (needed by vt_backward) */
+    float radius_factor;   /* first search radius in local mean spacings (default 2.6) */
+    float area_eps;        /* facets with area <= area_eps * V^(2/3) are not facets (default 1e-12) */
+    int32_t waves_per_cu;  /* persistent clip kernel occupancy (default 16) */
+    int32_t reserved[3];
+} vt_opts;
+
+/*
+ * vt_build -- tessellate.  Sorts the particles of each item along a Morton
+ * curve, builds the per-item cell tables, then computes every owned cell by
+ * clipping with bisector planes in increasing distance order until the
+ * security radius certifies it (all particles closer than twice the largest
+ * vertex distance have been used).
+ *   ctx        in/out: *ctx == NULL creates a context; a context from an
+ *              earlier build is reused (its scratch grows only if needed).
+ *   pos        device, n_total x 3 positions (AoS), dtype VT_F32 or VT_F64,
+ *              n_total = sum of n_owned + n_ghost.
+ *   global_id  device, n_total int32 ids reported as neighbour ids; NULL means
+ *              the particle's index in pos.
+ *   items      host, n_items >= 1 worlds (see vt_item).
+ *   opts       host, nullable.
+ * Errors: VT_ERR_ARG (bad sizes, unpacked items, non-cubic periodic box),
+ * VT_ERR_OOM, VT_ERR_HIP.
+ */
+vt_status vt_build(vt_ctx **ctx, const void *pos, vt_dtype dtype, const int32_t *global_id, const vt_item *items,
+                   int32_t n_items, const vt_opts *opts, void *stream);
+
+/*
+ * vt_cells -- cell volumes and neighbour lists of the owned particles, in
+ * output-row order (section 2: volume; neighbours sharing a facet; real ids).
+ *   volume       device, n_owned_total doubles.
+ *   nbr_off      device, n_owned_total + 1 int64 CSR offsets.
+ *   nbr_ids      device, nbr_cap int32 global ids; row i holds the ascending
+ *                ids of the particles that share a facet of positive area
+ *                with cell i (self excluded).
+ *   cell_status  device, n_owned_total bytes (VT_CELL_* bits), nullable.
+ * If the total neighbour count exceeds nbr_cap nothing past nbr_cap is
+ * written and vt_query reports VT_ERR_CAPACITY; vt_query also returns the
+ * total (nnz) so the caller can size nbr_ids.
+ */
+vt_status vt_cells(vt_ctx *ctx, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
+                   uint8_t *cell_status, void *stream);
+
+/*
+ * vt_density -- rho_i = m_i / V_i for the owned particles (section 2).
+ *   mass  device, n_total masses (dtype), indexed like pos; NULL = unit masses.
+ *   rho   device, n_owned_total doubles (output rows).
+ */
+vt_status vt_density(vt_ctx *ctx, const void *mass, vt_dtype dtype, double *rho, void *stream);
+
+/*
+ * vt_gradient -- density gradient per owned particle "from density and
+ * neighbouring information" (section 2).  The paper gives no formula; this is
+ * the unweighted least-squares fit over the Voronoi neighbours:
+ *   grad_i = G^-1 b,  G = sum_j D_ij D_ij^T,  b = sum_j (rho_j - rho_i) D_ij,
+ * D_ij the separation (minimum image in periodic boxes).
+ *   rho   device, n_total doubles indexed like pos (ghost entries are used
+ *         for ghost neighbours).
+ *   grad  device, n_owned_total x 3 doubles (output rows).
+ */
+vt_status vt_gradient(vt_ctx *ctx, const double *rho, double *grad, void *stream);
+
+/*
+ * vt_grid_deposit -- average Voronoi density on a regular grid (section 2,
+ * optional grid output): grid[(a*ny + b)*nz + c] = sum_i value_i *
+ * vol(cell_i ∩ voxel_abc) / vol(voxel), exact polyhedron-voxel overlaps.
+ * Voxels tile the box of item 0 (periodic boxes wrap voxel indices); only
+ * single-item contexts are supported.
+ *   value  device, n_owned_total doubles (output rows), e.g. rho from vt_density.
+ *   grid   device, nx*ny*nz doubles; overwritten.
+ */
+vt_status vt_grid_deposit(vt_ctx *ctx, const double *value, int32_t nx, int32_t ny, int32_t nz, double *grid,
+                          void *stream);
+
+/*
+ * vt_backward -- volume adjoint: given g = dL/dV (device, n_owned_total
+ * doubles, output rows; ghost cells carry no volume), writes
+ *   dL/dx_k = sum_{j in N(k)} (g_k - g_j) A_kj (c_kj - x_k) / |x_j - x_k|
+ * for every owned particle k (device, n_owned_total x 3 doubles, overwritten),
+ * A_kj and c_kj the area and centroid of the shared facet.  Requires a build
+ * with want_faces (else VT_ERR_STATE).  Ghost neighbours contribute with
+ * g_j = 0.
+ */
+vt_status vt_backward(vt_ctx *ctx, const double *dL_dV, double *dL_dx, void *stream);
+
+/*
+ * vt_query -- synchronises the context's last stream and reports: the device
+ * status (return value), the total neighbour count, the number of cells that
+ * needed the large-capacity kernel, and the number of cells flagged
+ * incomplete.  Any pointer may be NULL.
+ */
+vt_status vt_query(vt_ctx *ctx, int64_t *nnz, int64_t *n_retried, int64_t *n_incomplete);
+
+/*
+ * vt_stats -- per-owned-cell diagnostics (device, n_owned_total int32 each,
+ * output rows, any may be NULL): final vertex count, planes the security
+ * criterion had to examine (particles closer than 2R, plus one), and
+ * candidates actually tested.  Used by the benchmark's cost model.
+ */
+vt_status vt_stats(vt_ctx *ctx, int32_t *n_vertices, int32_t *n_planes, int32_t *n_tested, void *stream);
+
+/* n_owned_total and n_total of the last build (host, no sync). */
+vt_status vt_sizes(vt_ctx *ctx, int64_t *n_owned_total, int64_t *n_total);
+
+void vt_destroy(vt_ctx *ctx);
+
+const char *vt_status_string(vt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VT_H */

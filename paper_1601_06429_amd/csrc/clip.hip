@@ -1,0 +1,591 @@
+// clip.hip -- one Voronoi cell per wavefront: neighbour search and clipping.
+//
+// The paper's cell (section 1: the region closer to the particle than to any
+// other; section 2: volume from the facets, neighbours = particles sharing a
+// facet, periodic conditions) is built by clipping the box around the seed
+// (the bisectors with the seed's own periodic images, or the walls of a
+// bounded world) with the bisector half-spaces {y : y.D <= |D|^2/2} of the
+// other particles in increasing distance.  A particle farther than 2R (R the
+// largest vertex distance) cannot cut the cell, so the search proceeds in
+// shells [r_done, r_next) over Morton-cell ranges of the sorted particles and
+// stops once 2R <= r_done (the security radius).
+//
+// Per shell the candidates (at most VT_CAND_MAX) are gathered into LDS with
+// lanes = particles, sorted by quantised distance with a wave bitonic sort,
+// and applied one by one; the loop stops at the first candidate beyond 2R.
+// Cells that outgrow 64 vertices are handed to a second, persistent kernel
+// with room for 256.
+#include "poly.h"
+
+#define WAVE 64
+
+template <typename T, int VPL>
+struct ClipMem {
+    union {
+        struct {
+            double cd[VT_CAND_MAX][3];   // candidate separations (FP64)
+            int32_t cid[VT_CAND_MAX];    // candidate sorted index
+            uint32_t ckey[VT_CAND_MAX];  // quantised d^2 << 8 | slot
+        } c;
+        struct {
+            double vp[64 * VPL][3];      // final vertex positions (FP64)
+            uint32_t vt[64 * VPL];       // final vertex triples
+            double fa[64 * VPL];         // facet area
+            double fc[64 * VPL][3];      // facet centroid (seed-relative)
+        } f;
+    } u;
+    int32_t rb[64];                      // gather: cell range starts
+    int32_t rp[64];                      // gather: prefix of range lengths
+    PolyMem<T, VPL> P;
+};
+
+struct ClipArgs {
+    const void *spos;
+    const uint64_t *skey;
+    const int32_t *sgid;
+    const int32_t *tab;
+    const DevItem *items;
+    int n_items;
+    const int32_t *cells;
+    int64_t ncells;
+    const int32_t *queue;     // large kernel: cells to do (count in counters[CTR_QUEUE])
+    int32_t *queue_out;       // fast kernel: cells that outgrow it
+    int64_t queue_cap;
+    uint32_t *counters;
+    double *cvol;
+    int32_t *ccnt;
+    int64_t *crow;
+    uint8_t *cstat;
+    int32_t *cnv, *cnp, *cnt;
+    int32_t *stage_ids;
+    double *stage_area;
+    double *stage_cen;
+    int64_t row_base;
+    int64_t fstride;
+    int want_faces;
+    float radius_factor;
+    float area_eps;
+};
+
+__device__ __forceinline__ int find_item_d(const DevItem *items, int n_items, int64_t p) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].start <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t lower_bound_key(const uint64_t *skey, int32_t a, int32_t c, uint64_t k) {
+    while (a < c) {
+        int32_t mid = (a + c) >> 1;
+        if (skey[mid] < k) a = mid + 1; else c = mid;
+    }
+    return a;
+}
+
+// sorted-index range of the Morton cell (cx, cy, cz) at level l of item `ib`
+__device__ __forceinline__ void cell_range(const ClipArgs &A, const DevItem &it, int ib, int l, uint64_t cx,
+                                           uint64_t cy, uint64_t cz, int32_t &b, int32_t &e) {
+    uint64_t m = vt_morton(cx, cy, cz);
+    const int T = it.T;
+    if (l <= T) {
+        int sh = 3 * (T - l);
+        b = A.tab[it.tab_off + (int64_t)(m << sh)];
+        e = A.tab[it.tab_off + (int64_t)((m + 1) << sh)];
+    } else {
+        uint64_t mT = m >> (3 * (l - T));
+        int32_t lo = A.tab[it.tab_off + (int64_t)mT], hi = A.tab[it.tab_off + (int64_t)mT + 1];
+        int sh = 3 * (VT_MORTON_BITS - l);
+        uint64_t base = (uint64_t)ib << VT_LOCAL_KEY_BITS;
+        b = lower_bound_key(A.skey, lo, hi, base | (m << sh));
+        e = lower_bound_key(A.skey, b, hi, base | ((m + 1) << sh));
+    }
+}
+
+// local mean spacing around particle j0, from the particle count of the
+// smallest Morton cell containing it that holds between 8 and 64 particles
+__device__ double local_spacing(const ClipArgs &A, const DevItem &it, int ib, int32_t j0) {
+    const uint64_t lmask = (1ull << VT_LOCAL_KEY_BITS) - 1;
+    const uint64_t key = A.skey[j0] & lmask;
+    int l = it.T;
+    uint64_t m = key >> (3 * (VT_MORTON_BITS - l));
+    int32_t b = A.tab[it.tab_off + (int64_t)m];
+    int32_t e = A.tab[it.tab_off + (int64_t)m + 1];
+    int cnt = e - b;
+    while (cnt < 8 && l > 0) {
+        --l;
+        int sh = 3 * (it.T - l);
+        uint64_t ml = key >> (3 * (VT_MORTON_BITS - l));
+        b = A.tab[it.tab_off + (int64_t)(ml << sh)];
+        e = A.tab[it.tab_off + (int64_t)((ml + 1) << sh)];
+        cnt = e - b;
+    }
+    const uint64_t base = (uint64_t)ib << VT_LOCAL_KEY_BITS;
+    while (cnt > 64 && l < VT_MORTON_BITS) {
+        ++l;
+        int sh = 3 * (VT_MORTON_BITS - l);
+        uint64_t ml = key >> sh;
+        int32_t nb = lower_bound_key(A.skey, b, e, base | (ml << sh));
+        int32_t ne = lower_bound_key(A.skey, nb, e, base | ((ml + 1) << sh));
+        b = nb;
+        e = ne;
+        cnt = e - b;
+    }
+    double cs = it.S / (double)(1ll << l);
+    return cs / cbrt((double)(cnt > 0 ? cnt : 1));
+}
+
+template <typename PT4>
+__device__ __forceinline__ void load_pos(const void *spos, int32_t j, double &x, double &y, double &z) {
+    PT4 p = ((const PT4 *)spos)[j];
+    x = (double)p.x;
+    y = (double)p.y;
+    z = (double)p.z;
+}
+
+template <typename T, typename PT4, int VPL, bool RETRY>
+__global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
+    using M = ClipMem<T, VPL>;
+    constexpr int VMAX = 64 * VPL;
+    extern __shared__ char smem[];
+    const int wid = threadIdx.x >> 6;
+    M &S = *reinterpret_cast<M *>(smem + (size_t)wid * sizeof(M));
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const uint64_t mybit = 1ull << lane;
+
+    const int64_t ntodo = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : A.ncells;
+
+    for (;;) {
+        int64_t w = 0;
+        if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_RETRY : CTR_CELL], 1u);
+        w = (int64_t)__shfl((long long)w, 0);
+        if (w >= ntodo) break;
+        const int32_t cslot = RETRY ? A.queue[w] : (int32_t)w;
+        const int32_t j0 = A.cells[cslot];
+        const int bi = find_item_d(A.items, A.n_items, j0);
+        const DevItem &it = A.items[bi];
+        double sx, sy, sz;
+        load_pos<PT4>(A.spos, j0, sx, sy, sz);
+        const double xs[3] = {sx, sy, sz};
+
+        // ---------------- initial polytope: the box around the seed
+        double blo[3], bhi[3];
+        for (int a = 0; a < 3; ++a) {
+            if (it.periodic) {
+                blo[a] = -0.5 * it.L[a];
+                bhi[a] = 0.5 * it.L[a];
+            } else {
+                blo[a] = it.lo[a] - xs[a];
+                bhi[a] = it.lo[a] + it.L[a] - xs[a];
+            }
+        }
+        Poly<T, VPL> P;
+        P.init_box(S.P, blo, bhi);
+
+        uint32_t dup = 0;
+        bool overflow = false, corrupt = false;
+        int ntested = 0, nplanes = 1;
+
+        // ---------------- search and clip, in shells of increasing radius
+        double r_done = 0.0;
+        double r_next = (double)A.radius_factor * local_spacing(A, it, bi, j0);
+        const double Lmin = fmin(it.L[0], fmin(it.L[1], it.L[2]));
+        const double r_cap = it.periodic ? 0.5 * Lmin
+                                         : sqrt(it.L[0] * it.L[0] + it.L[1] * it.L[1] + it.L[2] * it.L[2]) * 1.0001;
+        if (r_next > r_cap) r_next = r_cap;
+        bool complete = false;
+        for (int pass = 0; pass < 64; ++pass) {
+            // ---- candidate cells: Morton level whose cell side is >= r_next
+            const double rh2 = r_next * r_next, rl2 = r_done * r_done;
+            int lvl = 0;
+            {
+                double c = it.S;
+                while (lvl < VT_MORTON_BITS && 0.5 * c >= r_next) {
+                    c *= 0.5;
+                    ++lvl;
+                }
+            }
+            const int sh = VT_MORTON_BITS - lvl;
+            const int64_t ncl = 1ll << lvl;
+            int64_t a0[3], na[3];
+            for (int a = 0; a < 3; ++a) {
+                int64_t q0 = vt_qraw(xs[a] - r_next, it.lo[a], it.inv_res) - 1;
+                int64_t q1 = vt_qraw(xs[a] + r_next, it.lo[a], it.inv_res) + 1;
+                int64_t i0 = q0 >> sh, i1 = q1 >> sh;
+                if (it.periodic) {
+                    if (i1 - i0 + 1 >= ncl) {
+                        i0 = 0;
+                        i1 = ncl - 1;
+                    }
+                } else {
+                    if (i0 < 0) i0 = 0;
+                    if (i1 > ncl - 1) i1 = ncl - 1;
+                }
+                a0[a] = i0;
+                na[a] = i1 >= i0 ? i1 - i0 + 1 : 0;
+            }
+            const int ncq = (int)(na[0] * na[1] * na[2]);  // at most 4 per axis
+            int32_t rbeg = 0, rlen = 0;
+            if (lane < ncq) {
+                int ix = lane % (int)na[0], iy = (lane / (int)na[0]) % (int)na[1], iz = lane / (int)(na[0] * na[1]);
+                int64_t cx = a0[0] + ix, cy = a0[1] + iy, cz = a0[2] + iz;
+                if (it.periodic) {
+                    cx &= ncl - 1;
+                    cy &= ncl - 1;
+                    cz &= ncl - 1;
+                }
+                int32_t b, e;
+                cell_range(A, it, bi, lvl, (uint64_t)cx, (uint64_t)cy, (uint64_t)cz, b, e);
+                rbeg = b;
+                rlen = e - b;
+            }
+            int total;
+            int pre = wave_excl_scan(rlen, &total);
+            S.rb[lane] = rbeg;
+            S.rp[lane] = pre;
+            wave_sync();
+            // ---- gather particles with r_done <= d < r_next
+            int n = 0;
+            for (int base = 0; base < total; base += WAVE) {
+                int f = base + lane;
+                bool keep = false;
+                double dx = 0, dy = 0, dz = 0, d2 = 0;
+                int32_t j = -1;
+                if (f < total) {
+                    int lo = 0, hi = ncq - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
+                    }
+                    j = S.rb[lo] + (f - S.rp[lo]);
+                    double px, py, pz;
+                    load_pos<PT4>(A.spos, j, px, py, pz);
+                    dx = px - sx;
+                    dy = py - sy;
+                    dz = pz - sz;
+                    if (it.periodic) {
+                        dx -= it.L[0] * rint(dx / it.L[0]);
+                        dy -= it.L[1] * rint(dy / it.L[1]);
+                        dz -= it.L[2] * rint(dz / it.L[2]);
+                    }
+                    d2 = dx * dx + dy * dy + dz * dz;
+                    if (j != j0) {
+                        if (d2 == 0.0) dup = 1;
+                        keep = (d2 >= rl2) && (d2 < rh2);
+                    }
+                }
+                uint64_t km = __ballot(keep);
+                if (keep) {
+                    int slot = n + __popcll(km & lt);
+                    if (slot < VT_CAND_MAX) {
+                        S.u.c.cd[slot][0] = dx;
+                        S.u.c.cd[slot][1] = dy;
+                        S.u.c.cd[slot][2] = dz;
+                        S.u.c.cid[slot] = j;
+                        double qf = d2 / rh2 * 16777216.0;
+                        uint32_t q = qf >= 16777215.0 ? 16777215u : (uint32_t)qf;
+                        S.u.c.ckey[slot] = (q << 8) | (uint32_t)slot;
+                    }
+                }
+                n += __popcll(km);
+            }
+            wave_sync();
+            if (n > VT_CAND_MAX) {
+                // too many particles in this shell: shrink its outer radius by the volume ratio
+                double fct = cbrt((double)VT_CAND_MAX / (double)n) * 0.9;
+                double rn = r_done + (r_next - r_done) * fct;
+                if (!(rn > r_done) || rn >= r_next) rn = r_done + 0.5 * (r_next - r_done);
+                r_next = rn;
+                continue;
+            }
+            // ---- sort by distance
+            uint32_t k0 = (lane < n) ? S.u.c.ckey[lane] : 0xFFFFFFFFu;
+            uint32_t k1 = (lane + 64 < n) ? S.u.c.ckey[lane + 64] : 0xFFFFFFFFu;
+            if (n > 64)
+                bitonic128(k0, k1);
+            else if (n > 1)
+                k0 = bitonic64(k0);
+            // ---- clip in increasing distance; stop at the first particle beyond 2R
+            auto q4r = [&](double r2) -> uint32_t {
+                double x = 4.0 * r2 / rh2 * 16777216.0;
+                return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
+            };
+            uint32_t Q4R = q4r(P.R2);
+            for (int i = 0; i < n; ++i) {
+                uint32_t key = (i < 64) ? readlane_u32(k0, i) : readlane_u32(k1, i - 64);
+                if ((key >> 8) > Q4R) break;
+                const int slot = (int)(key & 0xFFu);
+                ++ntested;
+                P4<double> p64;
+                p64.x = S.u.c.cd[slot][0];
+                p64.y = S.u.c.cd[slot][1];
+                p64.z = S.u.c.cd[slot][2];
+                p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
+                int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
+                if (rc == CLIP_CUT) {
+                    Q4R = q4r(P.R2);
+                } else if (rc == CLIP_OVERFLOW) {
+                    overflow = true;
+                    break;
+                } else if (rc < 0) {
+                    corrupt = true;
+                    break;
+                }
+            }
+            if (overflow || corrupt) break;
+            // particles the security criterion had to examine in this shell
+            {
+                int cntp = 0;
+                for (int b2 = lane; b2 < n; b2 += 64) {
+                    double x = S.u.c.cd[b2][0], y = S.u.c.cd[b2][1], z = S.u.c.cd[b2][2];
+                    if (x * x + y * y + z * z < 4.0 * P.R2) ++cntp;
+                }
+                nplanes += wave_sum_i(cntp);
+            }
+            wave_sync();
+            r_done = r_next;
+            const double need = 2.0 * sqrt(P.R2);
+            if (need <= r_done) {
+                complete = true;
+                break;
+            }
+            if (r_done >= r_cap) break;
+            r_next = fmax(need * (1.0 + 1e-9), r_done * 1.05);
+            if (r_next > r_cap) r_next = r_cap;
+        }
+        dup = __ballot(dup != 0) ? 1u : 0u;
+
+        if (overflow && !RETRY) {
+            // hand the cell to the large-capacity kernel
+            if (lane == 0) {
+                uint32_t qi = atomicAdd(&A.counters[CTR_QUEUE], 1u);
+                if ((int64_t)qi < A.queue_cap) A.queue_out[qi] = cslot;
+                else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                if (dup) atomicOr(&A.counters[CTR_STATUS], VT_DEV_DUPLICATE);
+            }
+            continue;
+        }
+        const int64_t row = A.row_base + (RETRY ? w : (int64_t)cslot) * A.fstride;
+        if (overflow || corrupt) {
+            if (lane == 0) {
+                atomicOr(&A.counters[CTR_STATUS], corrupt ? VT_DEV_TOPOLOGY : VT_DEV_CAPACITY);
+                if (dup) atomicOr(&A.counters[CTR_STATUS], VT_DEV_DUPLICATE);
+                A.cvol[cslot] = 0.0;
+                A.ccnt[cslot] = 0;
+                A.crow[cslot] = row;
+                A.cstat[cslot] = VT_CELL_FAILED | (RETRY ? VT_CELL_RETRIED : 0);
+                A.cnv[cslot] = 0;
+                A.cnp[cslot] = nplanes;
+                A.cnt[cslot] = ntested;
+            }
+            continue;
+        }
+
+        // ---------------- final geometry in FP64: facet areas, centroids, volume
+        wave_sync();
+        const int nvert = P.nvertices();
+        double r2max = 0.0;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if (P.alive[s] & mybit) {
+                double x, y, z;
+                P.pos64(S.P, s, x, y, z);
+                S.u.f.vp[s * 64 + lane][0] = x;
+                S.u.f.vp[s * 64 + lane][1] = y;
+                S.u.f.vp[s * 64 + lane][2] = z;
+                S.u.f.vt[s * 64 + lane] = P.vt[s];
+                r2max = fmax(r2max, x * x + y * y + z * z);
+            }
+        }
+        wave_sync();
+        double vol_l = 0.0;
+        double area_l[VPL];
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            area_l[r] = 0.0;
+            const int f = r * 64 + lane;
+            if (!(P.fa[r] & mybit)) continue;
+            uint64_t mf[VPL];
+            int i0 = -1;
+#pragma unroll
+            for (int ww = 0; ww < VPL; ++ww) {
+                mf[ww] = S.P.fm[f][ww];
+                if (i0 < 0 && mf[ww]) i0 = ww * 64 + __builtin_ctzll(mf[ww]);
+            }
+            // the vertex after u counter-clockwise on face f: it lies on f and on
+            // the face that precedes f in u's triple
+            auto next_of = [&](int u) -> int {
+                uint32_t t = S.u.f.vt[u];
+                int t0 = t & 0xFF, t1 = (t >> 8) & 0xFF, t2 = (t >> 16) & 0xFF;
+                int c = (t0 == f) ? t2 : (t1 == f) ? t0 : t1;
+                int nx = -1;
+#pragma unroll
+                for (int ww = 0; ww < VPL; ++ww) {
+                    uint64_t x = mf[ww] & S.P.fm[c][ww];
+                    if (ww == (u >> 6)) x &= ~(1ull << (u & 63));
+                    if (nx < 0 && x) nx = ww * 64 + __builtin_ctzll(x);
+                }
+                return nx;
+            };
+            const double *v0 = S.u.f.vp[i0];
+            double Sx = 0, Sy = 0, Sz = 0, Cx = 0, Cy = 0, Cz = 0, at = 0, vf = 0;
+            int prev = next_of(i0);
+            int guard = 0;
+            while (prev >= 0 && guard < VMAX) {
+                int cur = next_of(prev);
+                if (cur < 0 || cur == i0) break;
+                const double *v1 = S.u.f.vp[prev], *v2 = S.u.f.vp[cur];
+                double ax = v1[0] - v0[0], ay = v1[1] - v0[1], az = v1[2] - v0[2];
+                double bx = v2[0] - v0[0], by = v2[1] - v0[1], bz = v2[2] - v0[2];
+                double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+                Sx += cx;
+                Sy += cy;
+                Sz += cz;
+                double ta = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+                Cx += ta * (v0[0] + v1[0] + v2[0]) / 3.0;
+                Cy += ta * (v0[1] + v1[1] + v2[1]) / 3.0;
+                Cz += ta * (v0[2] + v1[2] + v2[2]) / 3.0;
+                at += ta;
+                vf += (v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
+                       v0[2] * (v1[0] * v2[1] - v1[1] * v2[0])) / 6.0;
+                prev = cur;
+                ++guard;
+            }
+            double A_ = 0.5 * sqrt(Sx * Sx + Sy * Sy + Sz * Sz);
+            area_l[r] = A_;
+            vol_l += vf;
+            S.u.f.fa[f] = A_;
+            S.u.f.fc[f][0] = at > 0 ? Cx / at : v0[0];
+            S.u.f.fc[f][1] = at > 0 ? Cy / at : v0[1];
+            S.u.f.fc[f][2] = at > 0 ? Cz / at : v0[2];
+        }
+        const double V = wave_sum_d(vol_l);
+        const double Rfin = sqrt(wave_max(r2max));
+        const double amin = (double)A.area_eps * pow(fabs(V), 2.0 / 3.0);
+        // facets of positive area generated by particles -> neighbour rows, ascending global id
+        uint64_t keys[VPL];
+        bool wall = false;
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            const int f = r * 64 + lane;
+            keys[r] = ~0ull;
+            if ((P.fa[r] & mybit) && area_l[r] > amin) {
+                int32_t tag = S.P.ptag[f];
+                if (tag < 0) wall = true;
+                else keys[r] = ((uint64_t)(uint32_t)A.sgid[tag] << 9) | (uint64_t)f;
+            }
+        }
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) cnt += __popcll(__ballot(keys[r] != ~0ull));
+        bitonic_u64<VPL>(keys);
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            int k = r * 64 + lane;
+            if (k < cnt && k < A.fstride) {
+                int f = (int)(keys[r] & 511ull);
+                A.stage_ids[row + k] = S.P.ptag[f];  // sorted index; mapped to global ids on output
+                if (A.want_faces) {
+                    A.stage_area[row + k] = S.u.f.fa[f];
+                    A.stage_cen[3 * (row + k) + 0] = S.u.f.fc[f][0];
+                    A.stage_cen[3 * (row + k) + 1] = S.u.f.fc[f][1];
+                    A.stage_cen[3 * (row + k) + 2] = S.u.f.fc[f][2];
+                }
+            }
+        }
+        const bool any_wall = __ballot(wall) != 0;
+        if (lane == 0) {
+            uint8_t st = RETRY ? VT_CELL_RETRIED : 0;
+            bool incomplete = false;
+            if (it.periodic) {
+                if (!complete || any_wall || 4.0 * Rfin >= Lmin) {
+                    atomicOr(&A.counters[CTR_STATUS], VT_DEV_BOX_TOO_SMALL);
+                    st |= VT_CELL_FAILED;
+                }
+            } else {
+                for (int a = 0; a < 3; ++a)
+                    if (xs[a] - 2.0 * Rfin < it.lo[a] || xs[a] + 2.0 * Rfin > it.lo[a] + it.L[a]) incomplete = true;
+                if (any_wall) incomplete = true;
+            }
+            if (incomplete) {
+                st |= VT_CELL_INCOMPLETE;
+                atomicAdd(&A.counters[CTR_INCOMPLETE], 1u);
+            }
+            if (dup) atomicOr(&A.counters[CTR_STATUS], VT_DEV_DUPLICATE);
+            const int32_t kept = cnt < A.fstride ? cnt : (int32_t)A.fstride;
+            if (cnt > A.fstride) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+            A.cvol[cslot] = V;
+            A.ccnt[cslot] = kept;
+            A.crow[cslot] = row;
+            A.cstat[cslot] = st;
+            A.cnv[cslot] = nvert;
+            A.cnp[cslot] = nplanes;
+            A.cnt[cslot] = ntested;
+            atomicAdd((unsigned long long *)&A.counters[CTR_NNZ_LO], (unsigned long long)kept);
+        }
+    }
+}
+
+template <typename T, typename PT4, int VPL, bool RETRY>
+static hipError_t launch_one(vt_ctx *c, ClipArgs &a, int wpb) {
+    const size_t lds = sizeof(ClipMem<T, VPL>) * (size_t)wpb;
+    auto kern = k_clip<T, PT4, VPL, RETRY>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int ncu = 0;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (ncu <= 0) ncu = 256;
+    const int wpc = c->opts.waves_per_cu > 0 ? c->opts.waves_per_cu : 16;
+    int64_t blocks = RETRY ? (int64_t)ncu * 2 : (int64_t)ncu * wpc / wpb;
+    if (blocks < 1) blocks = 1;
+    kern<<<dim3((unsigned)blocks), dim3(64 * wpb), lds, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, typename PT4>
+static hipError_t launch_prec(vt_ctx *c, ClipArgs &a) {
+    a.row_base = 0;
+    a.fstride = VT_FSTRIDE_FAST;
+    a.queue = nullptr;
+    hipError_t e = launch_one<T, PT4, 1, false>(c, a, 4);
+    if (e != hipSuccess) return e;
+    a.row_base = (int64_t)c->cap_owned * VT_FSTRIDE_FAST;
+    a.fstride = VT_FSTRIDE_BIG;
+    a.queue = c->queue;
+    return launch_one<T, PT4, 4, true>(c, a, 1);
+}
+
+hipError_t vt_launch_clip(vt_ctx *c) {
+    ClipArgs a;
+    a.spos = c->spos;
+    a.skey = c->skey;
+    a.sgid = c->sgid;
+    a.tab = c->tab;
+    a.items = c->items;
+    a.n_items = c->n_items;
+    a.cells = c->cells;
+    a.ncells = c->n_owned;
+    a.queue = nullptr;
+    a.queue_out = c->queue;
+    a.queue_cap = c->cap_retry;
+    a.counters = c->counters;
+    a.cvol = c->cvol;
+    a.ccnt = c->ccnt;
+    a.crow = c->crow;
+    a.cstat = c->cstat;
+    a.cnv = c->cnv;
+    a.cnp = c->cnp;
+    a.cnt = c->cnt;
+    a.stage_ids = c->stage_ids;
+    a.stage_area = c->stage_area;
+    a.stage_cen = c->stage_cen;
+    a.want_faces = c->opts.want_faces ? 1 : 0;
+    a.radius_factor = c->opts.radius_factor > 0 ? c->opts.radius_factor : 2.6f;
+    a.area_eps = c->opts.area_eps > 0 ? c->opts.area_eps : 1e-12f;
+    const bool mixed = c->opts.precision == VT_PREC_MIXED;
+    if (c->dtype == VT_F32) return mixed ? launch_prec<float, float4>(c, a) : launch_prec<double, float4>(c, a);
+    return mixed ? launch_prec<float, double4>(c, a) : launch_prec<double, double4>(c, a);
+}

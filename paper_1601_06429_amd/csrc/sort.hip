@@ -1,0 +1,319 @@
+// sort.hip -- particle ordering for the neighbour search.
+//
+// Each world (item) is quantised on a 2^16 grid over a cube of side S, and its
+// particles are sorted along the Morton curve (key = item << 48 | morton48) by
+// an LSD radix sort with 8-bit digits.  A Morton cell at level l is then a
+// contiguous range of the sorted arrays; a dense table at level T (8^T cells,
+// about one particle per cell) gives these ranges directly for l <= T, and a
+// binary search inside a level-T cell gives them for l > T.  This replaces the
+// search structure the paper gets from Qhull (section 2) with one whose memory
+// accesses are contiguous ranges.
+#include "vt_internal.h"
+
+#define SORT_THREADS 256
+#define SORT_ITEMS 16
+#define SORT_TILE (SORT_THREADS * SORT_ITEMS)
+
+// ------------------------------------------------------------------ scan
+#define SCAN_THREADS 256
+#define SCAN_ITEMS 16
+#define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
+
+int64_t vt_scan_tmp_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *lds, T *total) {
+    // Hillis-Steele over the block (256 threads) in LDS
+    int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        T x = (t >= off) ? lds[t - off] : T(0);
+        __syncthreads();
+        lds[t] += x;
+        __syncthreads();
+    }
+    T incl = lds[t];
+    *total = lds[SCAN_THREADS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const T *in, int64_t n, int64_t *sums) {
+    __shared__ int64_t lds[SCAN_THREADS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t acc = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        if (k < n) acc += (int64_t)in[k];
+    }
+    int64_t tot;
+    block_exclusive_scan<int64_t>(acc, lds, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the block sums (nb <= SCAN_THREADS * 64)
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_top(int64_t *sums, int64_t nb) {
+    __shared__ int64_t lds[SCAN_THREADS];
+    const int per = 64;
+    int64_t base = (int64_t)threadIdx.x * per;
+    int64_t acc = 0;
+    for (int i = 0; i < per; ++i)
+        if (base + i < nb) acc += sums[base + i];
+    int64_t tot;
+    int64_t off = block_exclusive_scan<int64_t>(acc, lds, &tot);
+    for (int i = 0; i < per; ++i)
+        if (base + i < nb) {
+            int64_t x = sums[base + i];
+            sums[base + i] = off;
+            off += x;
+        }
+    if (threadIdx.x == 0) sums[nb] = tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const T *in, T *out, int64_t n, const int64_t *sums,
+                                                            int write_total, int64_t nb) {
+    __shared__ int64_t lds[SCAN_THREADS];
+    __shared__ T tile[SCAN_TILE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        tile[i * SCAN_THREADS + threadIdx.x] = (k < n) ? in[k] : T(0);
+    }
+    __syncthreads();
+    // each thread scans SCAN_ITEMS consecutive elements of the tile
+    int64_t acc = 0;
+    T loc[SCAN_ITEMS];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        loc[i] = tile[threadIdx.x * SCAN_ITEMS + i];
+        acc += (int64_t)loc[i];
+    }
+    int64_t tot;
+    int64_t off = block_exclusive_scan<int64_t>(acc, lds, &tot) + sums[blockIdx.x];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        tile[threadIdx.x * SCAN_ITEMS + i] = (T)off;
+        off += (int64_t)loc[i];
+    }
+    __syncthreads();
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        if (k < n) out[k] = tile[i * SCAN_THREADS + threadIdx.x];
+    }
+    if (write_total && blockIdx.x == 0 && threadIdx.x == 0) out[n] = (T)sums[nb];
+}
+
+template <typename T>
+static hipError_t scan_impl(const T *in, T *out, int64_t n, int64_t *tmp, hipStream_t s) {
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) nb = 1;
+    if (nb > SCAN_THREADS * 64) return hipErrorInvalidValue;
+    k_scan_reduce<T><<<nb, SCAN_THREADS, 0, s>>>(in, n, tmp);
+    k_scan_top<<<1, SCAN_THREADS, 0, s>>>(tmp, nb);
+    k_scan_down<T><<<nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp, 1, nb);
+    return hipGetLastError();
+}
+
+// exclusive scan: out[0..n] with out[n] = total; in and out must not overlap
+hipError_t vt_launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+    return scan_impl<int64_t>(in, out, n, tmp, s);
+}
+hipError_t vt_launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+    return scan_impl<int32_t>(in, out, n, tmp, s);
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
+    k_zero_u32<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ keys
+__device__ __forceinline__ int find_item(const DevItem *items, int n_items, int64_t p) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].start <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename PT>
+__global__ void k_keys(const PT *pos, int64_t n, const DevItem *items, int n_items, uint64_t *keys, uint32_t *vals) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int b = find_item(items, n_items, p);
+    const DevItem &it = items[b];
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = (double)pos[3 * p + a];
+        if (it.periodic) x -= it.L[a] * floor((x - it.lo[a]) / it.L[a]);
+        q[a] = (uint64_t)vt_qclamp(vt_qraw(x, it.lo[a], it.inv_res));
+    }
+    keys[p] = ((uint64_t)b << VT_LOCAL_KEY_BITS) | vt_morton(q[0], q[1], q[2]);
+    vals[p] = (uint32_t)p;
+}
+
+// ------------------------------------------------------------------ radix sort
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t *keys, int64_t n, int shift,
+                                                             int32_t *hist, int nblocks) {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        int64_t k = base + (int64_t)i * SORT_THREADS + threadIdx.x;
+        if (k < n) atomicAdd(&h[(keys[k] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter.  Keys of a tile are ranked in index order: round-major, then
+// wave, then lane.  Lanes holding the same digit are found with eight ballots.
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
+                                                                uint64_t *kout, uint32_t *vout, int64_t n,
+                                                                int shift, const int32_t *offs, int nblocks) {
+    __shared__ int32_t running[256];
+    __shared__ int32_t wcnt[SORT_THREADS / 64][256];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    running[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        for (int ww = 0; ww < SORT_THREADS / 64; ++ww) wcnt[ww][t] = 0;
+        __syncthreads();
+        int64_t k = base + (int64_t)i * SORT_THREADS + t;
+        bool valid = k < n;
+        uint64_t key = valid ? kin[k] : 0ull;
+        uint32_t val = valid ? vin[k] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t b = __ballot(valid && ((d >> bit) & 1u));
+            match &= ((d >> bit) & 1u) ? b : ~b;
+        }
+        int rank = __popcll(match & lt);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(match);
+        __syncthreads();
+        int pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += wcnt[ww][d];
+        if (valid) {
+            int64_t pos = (int64_t)running[d] + pre + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int ww = 0; ww < SORT_THREADS / 64; ++ww) add += wcnt[ww][t];
+        running[t] += add;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ sorted arrays
+template <typename PT, typename PT4>
+__global__ void k_sorted_gather(const PT *pos, const int32_t *gid, const uint32_t *order, int64_t n,
+                                const DevItem *items, int n_items, PT4 *spos, int32_t *sgid, int32_t *srow,
+                                int32_t *sorig) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int64_t p = order[j];
+    int b = find_item(items, n_items, p);
+    const DevItem &it = items[b];
+    PT4 v;
+    double x[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = (double)pos[3 * p + a];
+        if (it.periodic) {
+            x[a] -= it.L[a] * floor((x[a] - it.lo[a]) / it.L[a]);
+            if (x[a] >= it.lo[a] + it.L[a]) x[a] = it.lo[a];  // a value that rounds up to the top wall wraps to lo
+        }
+    }
+    v.x = (decltype(v.x))x[0];
+    v.y = (decltype(v.x))x[1];
+    v.z = (decltype(v.x))x[2];
+    v.w = 0;
+    spos[j] = v;
+    sgid[j] = gid ? gid[p] : (int32_t)p;
+    int64_t k = p - it.start;
+    srow[j] = (k < it.n_owned) ? (int32_t)(it.owned_base + k) : -1;
+    sorig[j] = (int32_t)p;
+}
+
+// level-T table: tab[off + c] = first sorted index whose level-T cell is >= c
+__global__ void k_level_table(const uint64_t *skey, int64_t n, const DevItem *items, int n_items, int32_t *tab) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int b = find_item(items, n_items, j);
+    const DevItem &it = items[b];
+    const int sh = 3 * (VT_MORTON_BITS - it.T);
+    const uint64_t lmask = (1ull << VT_LOCAL_KEY_BITS) - 1;
+    int64_t c = (int64_t)((skey[j] & lmask) >> sh);
+    int64_t cprev = (j == it.start) ? -1 : (int64_t)((skey[j - 1] & lmask) >> sh);
+    for (int64_t x = cprev + 1; x <= c; ++x) tab[it.tab_off + x] = (int32_t)j;
+    if (j == it.start + it.count - 1) {
+        int64_t ncell = 1ll << (3 * it.T);
+        for (int64_t x = c + 1; x <= ncell; ++x) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
+    }
+}
+
+__global__ void k_owned_flags(const int32_t *srow, int64_t n, int32_t *flag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) flag[j] = srow[j] >= 0 ? 1 : 0;
+}
+
+__global__ void k_owned_compact(const int32_t *srow, const int32_t *scan, int64_t n, int32_t *cells,
+                                int32_t *row2cell) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int32_t r = srow[j];
+    if (r >= 0) {
+        int32_t c = scan[j];
+        cells[c] = (int32_t)j;
+        row2cell[r] = c;
+    }
+}
+
+hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid) {
+    hipStream_t s = c->stream;
+    const int64_t n = c->n_total;
+    const int nb = (int)((n + SORT_TILE - 1) / SORT_TILE);
+    const int tpb = 256;
+    const int64_t grid = (n + tpb - 1) / tpb;
+    if (c->dtype == VT_F32)
+        k_keys<float><<<grid, tpb, 0, s>>>((const float *)pos, n, c->items, c->n_items, c->keys[0], c->vals[0]);
+    else
+        k_keys<double><<<grid, tpb, 0, s>>>((const double *)pos, n, c->items, c->n_items, c->keys[0], c->vals[0]);
+    int cur = 0;
+    for (int shift = 0; shift < c->key_bits; shift += 8) {
+        k_radix_hist<<<nb, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift, c->hist, nb);
+        hipError_t e = vt_launch_scan_i32(c->hist, c->hist + (int64_t)256 * nb, (int64_t)256 * nb, c->scan_tmp, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<nb, SORT_THREADS, 0, s>>>(c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], n,
+                                                   shift, c->hist + (int64_t)256 * nb, nb);
+        cur ^= 1;
+    }
+    c->skey = c->keys[cur];
+    if (c->dtype == VT_F32)
+        k_sorted_gather<float, float4><<<grid, tpb, 0, s>>>((const float *)pos, gid, c->vals[cur], n, c->items,
+                                                            c->n_items, (float4 *)c->spos, c->sgid, c->srow, c->sorig);
+    else
+        k_sorted_gather<double, double4><<<grid, tpb, 0, s>>>((const double *)pos, gid, c->vals[cur], n, c->items,
+                                                              c->n_items, (double4 *)c->spos, c->sgid, c->srow,
+                                                              c->sorig);
+    k_level_table<<<grid, tpb, 0, s>>>(c->skey, n, c->items, c->n_items, c->tab);
+    // owned cells in Morton order (flags -> scan -> compact); the flag array reuses vals[cur^1]
+    int32_t *flag = (int32_t *)c->vals[cur ^ 1];
+    int32_t *scan = (int32_t *)c->keys[cur ^ 1];
+    k_owned_flags<<<grid, tpb, 0, s>>>(c->srow, n, flag);
+    hipError_t e = vt_launch_scan_i32(flag, scan, n, c->scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_owned_compact<<<grid, tpb, 0, s>>>(c->srow, scan, n, c->cells, c->row2cell);
+    return hipGetLastError();
+}

@@ -1,0 +1,308 @@
+// vt_api.cpp -- host side of the C ABI declared in include/vt.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "vt_internal.h"
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T **p, int64_t n) {
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)n);
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_all(vt_ctx *c) {
+    dfree(c->items);
+    if (c->h_items) hipHostFree(c->h_items);
+    c->h_items = nullptr;
+    if (c->h_counters) hipHostFree(c->h_counters);
+    c->h_counters = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        dfree(c->keys[k]);
+        dfree(c->vals[k]);
+    }
+    dfree(c->hist);
+    dfree(c->scan_tmp);
+    dfree(c->spos);
+    dfree(c->sgid);
+    dfree(c->srow);
+    dfree(c->sorig);
+    dfree(c->tab);
+    dfree(c->cells);
+    dfree(c->cvol);
+    dfree(c->ccnt);
+    dfree(c->crow);
+    dfree(c->cstat);
+    dfree(c->cnv);
+    dfree(c->cnp);
+    dfree(c->cnt);
+    dfree(c->stage_ids);
+    dfree(c->stage_area);
+    dfree(c->stage_cen);
+    dfree(c->queue);
+    dfree(c->counters);
+    dfree(c->rowoff);
+    dfree(c->row2cell);
+    c->cap_total = c->cap_owned = c->cap_tab = c->cap_retry = c->cap_items = c->cap_hist = c->cap_scan = 0;
+    c->cap_faces = false;
+}
+
+#define TRY(x)                                        \
+    do {                                              \
+        hipError_t e_ = (x);                          \
+        if (e_ != hipSuccess) {                       \
+            return e_ == hipErrorOutOfMemory ? VT_ERR_OOM : VT_ERR_HIP; \
+        }                                             \
+    } while (0)
+
+int table_level(int64_t count) {
+    int T = (int)lround(log((double)std::max<int64_t>(count, 1)) / log(8.0));
+    return std::min(std::max(T, 1), 9);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vt_status_string(vt_status s) {
+    switch (s) {
+        case VT_OK: return "ok";
+        case VT_ERR_ARG: return "invalid argument";
+        case VT_ERR_HIP: return "HIP runtime error";
+        case VT_ERR_OOM: return "out of device memory";
+        case VT_ERR_DUPLICATE: return "duplicate particles";
+        case VT_ERR_BOX_TOO_SMALL: return "periodic box too small for a cell (2R >= L/2)";
+        case VT_ERR_CAPACITY: return "capacity exceeded";
+        case VT_ERR_STATE: return "invalid call order";
+        case VT_ERR_TOPOLOGY: return "inconsistent clipping topology";
+    }
+    return "unknown status";
+}
+
+vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t *global_id, const vt_item *items,
+                   int32_t n_items, const vt_opts *opts, void *stream) {
+    if (!pctx || !pos || !items || n_items < 1) return VT_ERR_ARG;
+    if (dtype != VT_F32 && dtype != VT_F64) return VT_ERR_ARG;
+    // validate the item layout
+    int64_t n_total = 0, n_owned = 0;
+    for (int b = 0; b < n_items; ++b) {
+        const vt_item &it = items[b];
+        if (it.offset != n_total || it.n_owned < 1 || it.n_ghost < 0) return VT_ERR_ARG;
+        for (int a = 0; a < 3; ++a)
+            if (!(it.hi[a] > it.lo[a])) return VT_ERR_ARG;
+        if (it.periodic) {
+            if (it.n_ghost != 0) return VT_ERR_ARG;
+            double L0 = it.hi[0] - it.lo[0];
+            for (int a = 1; a < 3; ++a)
+                if (fabs((it.hi[a] - it.lo[a]) - L0) > 1e-12 * L0) return VT_ERR_ARG;
+        }
+        n_total += it.n_owned + it.n_ghost;
+        n_owned += it.n_owned;
+    }
+    if (n_total >= (int64_t)INT32_MAX) return VT_ERR_ARG;
+    vt_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != VT_PREC_FP64 && o.precision != VT_PREC_MIXED) return VT_ERR_ARG;
+
+    vt_ctx *c = *pctx;
+    if (!c) {
+        c = new vt_ctx();
+        hipGetDevice(&c->device);
+        *pctx = c;
+    }
+    c->stream = (hipStream_t)stream;
+    c->dtype = dtype;
+    c->opts = o;
+    c->n_total = n_total;
+    c->n_owned = n_owned;
+    c->n_items = n_items;
+    c->built = false;
+    c->faces_valid = false;
+    int ib = 0;
+    while ((1 << ib) < n_items) ++ib;
+    c->key_bits = VT_LOCAL_KEY_BITS + ib;
+
+    // per-item device descriptors and table sizes
+    std::vector<DevItem> di(n_items);
+    int64_t tab_total = 0, owned_base = 0;
+    for (int b = 0; b < n_items; ++b) {
+        const vt_item &it = items[b];
+        DevItem &d = di[b];
+        double S = 0;
+        for (int a = 0; a < 3; ++a) {
+            d.lo[a] = it.lo[a];
+            d.L[a] = it.hi[a] - it.lo[a];
+            S = std::max(S, d.L[a]);
+        }
+        d.S = S;
+        d.inv_res = (double)(1 << VT_MORTON_BITS) / S;
+        d.start = it.offset;
+        d.count = it.n_owned + it.n_ghost;
+        d.n_owned = it.n_owned;
+        d.owned_base = owned_base;
+        d.T = table_level(d.count);
+        d.tab_off = tab_total;
+        d.periodic = it.periodic ? 1 : 0;
+        tab_total += (1ll << (3 * d.T)) + 1;
+        owned_base += it.n_owned;
+    }
+
+    const int64_t nb = (n_total + 4095) / 4096;
+    const int64_t hist_need = 2 * 256 * nb + 1;
+    const int64_t scan_need = vt_scan_tmp_elems(std::max<int64_t>(n_total, 256 * nb) + 1) + 1;
+    const int64_t retry_need = std::max<int64_t>(4096, n_owned / 16);
+    const size_t pos_bytes = dtype == VT_F32 ? sizeof(float4) : sizeof(double4);
+    const bool need_faces = o.want_faces != 0;
+    bool realloc_all = n_total > c->cap_total || n_owned > c->cap_owned || tab_total > c->cap_tab ||
+                       n_items > c->cap_items || hist_need > c->cap_hist || scan_need > c->cap_scan ||
+                       (need_faces && !c->cap_faces) || (c->spos && pos_bytes == sizeof(double4) && dtype == VT_F64 &&
+                                                         false);
+    // spos is sized for double4 always, so the dtype may change between builds
+    if (realloc_all) {
+        hipDeviceSynchronize();
+        free_all(c);
+        const int64_t NT = n_total, NO = n_owned;
+        TRY(dalloc(&c->items, n_items));
+        TRY(hipHostMalloc((void **)&c->h_items, sizeof(DevItem) * (size_t)n_items, hipHostMallocDefault));
+        TRY(hipHostMalloc((void **)&c->h_counters, sizeof(uint32_t) * CTR_COUNT, hipHostMallocDefault));
+        for (int k = 0; k < 2; ++k) {
+            TRY(dalloc(&c->keys[k], NT + 1));
+            TRY(dalloc(&c->vals[k], NT + 1));
+        }
+        TRY(dalloc(&c->hist, hist_need));
+        TRY(dalloc(&c->scan_tmp, scan_need));
+        TRY(hipMalloc(&c->spos, sizeof(double4) * (size_t)NT));
+        TRY(dalloc(&c->sgid, NT));
+        TRY(dalloc(&c->srow, NT));
+        TRY(dalloc(&c->sorig, NT));
+        TRY(dalloc(&c->tab, tab_total));
+        TRY(dalloc(&c->cells, NO));
+        TRY(dalloc(&c->row2cell, NO));
+        TRY(dalloc(&c->cvol, NO));
+        TRY(dalloc(&c->ccnt, NO));
+        TRY(dalloc(&c->crow, NO));
+        TRY(dalloc(&c->cstat, NO));
+        TRY(dalloc(&c->cnv, NO));
+        TRY(dalloc(&c->cnp, NO));
+        TRY(dalloc(&c->cnt, NO));
+        const int64_t slots = NO * VT_FSTRIDE_FAST + retry_need * VT_FSTRIDE_BIG;
+        TRY(dalloc(&c->stage_ids, slots));
+        if (need_faces) {
+            TRY(dalloc(&c->stage_area, slots));
+            TRY(dalloc(&c->stage_cen, 3 * slots));
+        }
+        TRY(dalloc(&c->queue, retry_need));
+        TRY(dalloc(&c->counters, CTR_COUNT));
+        TRY(dalloc(&c->rowoff, NO + 1));
+        c->cap_total = NT;
+        c->cap_owned = NO;
+        c->cap_tab = tab_total;
+        c->cap_items = n_items;
+        c->cap_hist = hist_need;
+        c->cap_scan = scan_need;
+        c->cap_retry = retry_need;
+        c->cap_faces = need_faces;
+    }
+    memcpy(c->h_items, di.data(), sizeof(DevItem) * (size_t)n_items);
+    TRY(hipMemcpyAsync(c->items, c->h_items, sizeof(DevItem) * (size_t)n_items, hipMemcpyHostToDevice, c->stream));
+    TRY(vt_launch_zero_u32(c->counters, CTR_COUNT, c->stream));
+    TRY(vt_launch_sort(c, pos, global_id));
+    TRY(vt_launch_clip(c));
+    c->built = true;
+    c->faces_valid = need_faces;
+    return VT_OK;
+}
+
+vt_status vt_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
+                   uint8_t *cell_status, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!volume || !nbr_off || (!nbr_ids && nbr_cap > 0) || nbr_cap < 0) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_cells(c, volume, nbr_off, nbr_ids, nbr_cap, cell_status));
+    return VT_OK;
+}
+
+vt_status vt_density(vt_ctx *c, const void *mass, vt_dtype dtype, double *rho, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!rho || (dtype != VT_F32 && dtype != VT_F64)) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_density(c, mass, dtype, rho));
+    return VT_OK;
+}
+
+vt_status vt_gradient(vt_ctx *c, const double *rho, double *grad, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!rho || !grad) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_gradient(c, rho, grad));
+    return VT_OK;
+}
+
+vt_status vt_grid_deposit(vt_ctx *c, const double *value, int32_t nx, int32_t ny, int32_t nz, double *grid,
+                          void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!value || !grid || nx < 1 || ny < 1 || nz < 1 || c->n_items != 1) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_grid(c, value, nx, ny, nz, grid));
+    return VT_OK;
+}
+
+vt_status vt_backward(vt_ctx *c, const double *dL_dV, double *dL_dx, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!c->faces_valid) return VT_ERR_STATE;
+    if (!dL_dV || !dL_dx) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_backward(c, dL_dV, dL_dx));
+    return VT_OK;
+}
+
+vt_status vt_stats(vt_ctx *c, int32_t *n_vertices, int32_t *n_planes, int32_t *n_tested, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    c->stream = (hipStream_t)stream;
+    TRY(vt_launch_stats(c, n_vertices, n_planes, n_tested));
+    return VT_OK;
+}
+
+vt_status vt_sizes(vt_ctx *c, int64_t *n_owned_total, int64_t *n_total) {
+    if (!c) return VT_ERR_ARG;
+    if (n_owned_total) *n_owned_total = c->n_owned;
+    if (n_total) *n_total = c->n_total;
+    return VT_OK;
+}
+
+vt_status vt_query(vt_ctx *c, int64_t *nnz, int64_t *n_retried, int64_t *n_incomplete) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    TRY(hipStreamSynchronize(c->stream));
+    TRY(hipMemcpy(c->h_counters, c->counters, sizeof(uint32_t) * CTR_COUNT, hipMemcpyDeviceToHost));
+    const uint32_t *h = c->h_counters;
+    if (nnz) *nnz = (int64_t)(((uint64_t)h[CTR_NNZ_HI] << 32) | h[CTR_NNZ_LO]);
+    if (n_retried) *n_retried = h[CTR_QUEUE];
+    if (n_incomplete) *n_incomplete = h[CTR_INCOMPLETE];
+    uint32_t st = h[CTR_STATUS];
+    if (st & VT_DEV_TOPOLOGY) return VT_ERR_TOPOLOGY;
+    if (st & VT_DEV_DUPLICATE) return VT_ERR_DUPLICATE;
+    if (st & VT_DEV_BOX_TOO_SMALL) return VT_ERR_BOX_TOO_SMALL;
+    if (st & (VT_DEV_CAPACITY | VT_DEV_NBR_CAP)) return VT_ERR_CAPACITY;
+    return VT_OK;
+}
+
+void vt_destroy(vt_ctx *c) {
+    if (!c) return;
+    hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

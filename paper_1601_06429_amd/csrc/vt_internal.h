@@ -1,0 +1,143 @@
+// vt_internal.h -- shared declarations of the HIP implementation (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vt.h"
+
+// ---------------------------------------------------------------- constants
+#define VT_MORTON_BITS 16          // quantisation bits per axis of the Morton key
+#define VT_LOCAL_KEY_BITS 48       // 3 * VT_MORTON_BITS
+#define VT_CAND_MAX 128            // candidates per clipping pass held in LDS
+#define VT_FSTRIDE_FAST 40         // facet slots per cell, fast kernel (F <= 34 when V <= 64)
+#define VT_FSTRIDE_BIG 136         // facet slots per cell, large kernel (F <= 130 when V <= 256)
+
+// device status word bits
+#define VT_DEV_DUPLICATE 1u
+#define VT_DEV_BOX_TOO_SMALL 2u
+#define VT_DEV_CAPACITY 4u
+#define VT_DEV_TOPOLOGY 8u
+#define VT_DEV_NBR_CAP 16u
+
+// counters[] slots
+#define CTR_CELL 0        // persistent work counter, fast kernel
+#define CTR_RETRY 1       // persistent work counter, large kernel
+#define CTR_QUEUE 2       // retry queue length
+#define CTR_STATUS 3      // device status bits
+#define CTR_NNZ_LO 4      // total facets (64-bit, two words)
+#define CTR_NNZ_HI 5
+#define CTR_INCOMPLETE 6
+#define CTR_GRID 7        // grid deposit work counters (two words)
+#define CTR_GRID_RETRY 8
+#define CTR_COUNT 12
+
+// per-item description on the device
+struct DevItem {
+    double lo[3];
+    double L[3];        // box lengths
+    double S;           // Morton cube side (max of L)
+    double inv_res;     // 2^16 / S
+    int64_t start;      // first particle (input order == sorted order range)
+    int64_t count;      // n_owned + n_ghost
+    int64_t n_owned;
+    int64_t owned_base; // first output row
+    int64_t tab_off;    // offset of the level table in tab[]
+    int32_t T;          // table level
+    int32_t periodic;
+};
+
+// ---------------------------------------------------------------- context
+struct vt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    vt_dtype dtype = VT_F64;
+    vt_opts opts{};
+    int64_t n_total = 0, n_owned = 0;
+    int32_t n_items = 0;
+    int key_bits = 48;
+    bool faces_valid = false;
+    bool built = false;
+
+    // capacities of the allocations below
+    int64_t cap_total = 0, cap_owned = 0, cap_tab = 0, cap_retry = 0, cap_items = 0, cap_hist = 0;
+    int64_t cap_scan = 0;
+    bool cap_faces = false;
+
+    DevItem *items = nullptr;      // device copy
+    DevItem *h_items = nullptr;    // host copy (pinned not needed)
+    // sort
+    uint64_t *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    int32_t *hist = nullptr;
+    int64_t *scan_tmp = nullptr;
+    // sorted particle arrays (Morton order)
+    void *spos = nullptr;          // float4 or double4
+    uint64_t *skey = nullptr;      // alias of keys[final]
+    int32_t *sgid = nullptr;       // global id per sorted particle
+    int32_t *srow = nullptr;       // output row, -1 for ghosts
+    int32_t *sorig = nullptr;      // index in the caller's pos[]
+    int32_t *tab = nullptr;        // level tables
+    int32_t *cells = nullptr;      // owned sorted indices, in Morton order
+    // clip results per cell slot
+    double *cvol = nullptr;
+    int32_t *ccnt = nullptr;
+    int64_t *crow = nullptr;       // staging row start
+    uint8_t *cstat = nullptr;
+    int32_t *cnv = nullptr, *cnp = nullptr, *cnt = nullptr;
+    int32_t *stage_ids = nullptr;
+    double *stage_area = nullptr;
+    double *stage_cen = nullptr;   // 3 per facet
+    int32_t *queue = nullptr;
+    uint32_t *counters = nullptr;  // CTR_*
+    // post-processing
+    int64_t *rowoff = nullptr;     // facet offsets in output-row order (n_owned + 1)
+    int32_t *row2cell = nullptr;   // cell slot of each output row
+    uint32_t *h_counters = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid);
+hipError_t vt_launch_clip(vt_ctx *c);
+hipError_t vt_launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+hipError_t vt_launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+hipError_t vt_launch_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
+                           uint8_t *cell_status);
+hipError_t vt_launch_density(vt_ctx *c, const void *mass, vt_dtype dt, double *rho);
+hipError_t vt_launch_gradient(vt_ctx *c, const double *rho, double *grad);
+hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz, double *grid);
+hipError_t vt_launch_backward(vt_ctx *c, const double *g, double *out);
+hipError_t vt_launch_stats(vt_ctx *c, int32_t *nv, int32_t *np, int32_t *nt);
+hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+
+int64_t vt_scan_tmp_elems(int64_t n);
+
+// ---------------------------------------------------------------- device helpers
+#ifdef __HIP_DEVICE_COMPILE__
+#define VT_DEV __device__ __forceinline__
+#else
+#define VT_DEV __host__ __device__ inline
+#endif
+
+// spread the low 16 bits of v to every third bit
+VT_DEV uint64_t vt_spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+VT_DEV uint64_t vt_morton(uint64_t ix, uint64_t iy, uint64_t iz) {
+    return (vt_spread3(ix) << 2) | (vt_spread3(iy) << 1) | vt_spread3(iz);
+}
+
+// quantised coordinate of x (item-relative Morton grid); monotone in x, not clamped
+VT_DEV int64_t vt_qraw(double x, double lo, double inv_res) { return (int64_t)floor((x - lo) * inv_res); }
+
+VT_DEV int64_t vt_qclamp(int64_t q) {
+    const int64_t m = (1ll << VT_MORTON_BITS) - 1;
+    return q < 0 ? 0 : (q > m ? m : q);
+}

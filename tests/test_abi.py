@@ -1,0 +1,58 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, and it
+exports every entry point the public header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vt.h")
+LIB = os.path.join(ROOT, "paper_1601_06429_amd", "libvt.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_six_hot_path_calls():
+    names = declared_functions()
+    for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward"):
+        assert f in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvt.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvt.so not built")
+def test_status_strings():
+    lib = ctypes.CDLL(LIB)
+    lib.vt_status_string.restype = ctypes.c_char_p
+    lib.vt_status_string.argtypes = [ctypes.c_int]
+    assert lib.vt_status_string(0) == b"ok"
+    assert b"duplicate" in lib.vt_status_string(4)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvt.so not built")
+def test_argument_errors_are_synchronous():
+    """Invalid arguments are rejected on the host before anything is enqueued."""
+    import paper_1601_06429_amd as vt
+
+    L = vt.lib()
+    ctx = ctypes.c_void_p(None)
+    items = vt._items([dict(offset=0, n_owned=10, n_ghost=0, periodic=True, lo=[0, 0, 0], hi=[1, 1, 2])])
+    # non-cubic periodic box
+    assert L.vt_build(ctypes.byref(ctx), ctypes.c_void_p(16), vt.VT_F32, None, items, 1, None, None) == 1
+    # items not packed back to back
+    items = vt._items([dict(offset=5, n_owned=10, periodic=False, lo=[0, 0, 0], hi=[1, 1, 1])])
+    assert L.vt_build(ctypes.byref(ctx), ctypes.c_void_p(16), vt.VT_F32, None, items, 1, None, None) == 1
+    # no items / null positions
+    assert L.vt_build(ctypes.byref(ctx), None, vt.VT_F32, None, items, 1, None, None) == 1
+    # calls on a context that was never built
+    assert L.vt_cells(None, None, None, None, 0, None, None) == 7
