@@ -51,12 +51,22 @@ class vt_opts(ctypes.Structure):
 
 
 def lib():
-    """Load libvt.so (raises if it has not been built)."""
+    """Load libvt.so (raises if it has not been built).
+
+    PyTorch-ROCm ships its own HIP runtime.  libvt must share the runtime that
+    owns the tensors, so torch (and, on a GPU machine, its HIP runtime) is
+    loaded before libvt: libvt's HIP symbols then bind to that runtime instead
+    of a second copy that would not see the device.
+    """
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libvt.so not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+            import torch
+
+            if torch.cuda.is_available():
+                torch.cuda.init()
             L = ctypes.CDLL(LIB_PATH)
             P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
             L.vt_build.argtypes = [ctypes.POINTER(P), P, I32, P, ctypes.POINTER(vt_item), I32,

@@ -272,8 +272,9 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     }
                     d2 = dx * dx + dy * dy + dz * dz;
                     if (j != j0) {
+                        // a coincident particle has no bisector: report it, do not clip with it
                         if (d2 == 0.0) dup = 1;
-                        keep = (d2 >= rl2) && (d2 < rh2);
+                        keep = (d2 > 0.0) && (d2 >= rl2) && (d2 < rh2);
                     }
                 }
                 uint64_t km = __ballot(keep);

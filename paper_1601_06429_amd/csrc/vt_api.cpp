@@ -1,6 +1,7 @@
 // vt_api.cpp -- host side of the C ABI declared in include/vt.h.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -59,13 +60,20 @@ void free_all(vt_ctx *c) {
     c->cap_faces = false;
 }
 
-#define TRY(x)                                        \
-    do {                                              \
-        hipError_t e_ = (x);                          \
-        if (e_ != hipSuccess) {                       \
-            return e_ == hipErrorOutOfMemory ? VT_ERR_OOM : VT_ERR_HIP; \
-        }                                             \
+vt_status hip_fail(hipError_t e, const char *what, int line) {
+    if (getenv("VT_DEBUG")) fprintf(stderr, "libvt: %s failed at vt_api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? VT_ERR_OOM : VT_ERR_HIP;
+}
+
+#define TRY(x)                                          \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__); \
     } while (0)
+
+// Launch errors are read with hipGetLastError(); clear whatever an earlier,
+// unrelated runtime call may have left there before enqueueing anything.
+void clear_stale_error() { (void)hipGetLastError(); }
 
 int table_level(int64_t count) {
     int T = (int)lround(log((double)std::max<int64_t>(count, 1)) / log(8.0));
@@ -163,13 +171,11 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
     const int64_t hist_need = 2 * 256 * nb + 1;
     const int64_t scan_need = vt_scan_tmp_elems(std::max<int64_t>(n_total, 256 * nb) + 1) + 1;
     const int64_t retry_need = std::max<int64_t>(4096, n_owned / 16);
-    const size_t pos_bytes = dtype == VT_F32 ? sizeof(float4) : sizeof(double4);
     const bool need_faces = o.want_faces != 0;
+    // spos is sized for double4, so the position dtype may change between builds
     bool realloc_all = n_total > c->cap_total || n_owned > c->cap_owned || tab_total > c->cap_tab ||
                        n_items > c->cap_items || hist_need > c->cap_hist || scan_need > c->cap_scan ||
-                       (need_faces && !c->cap_faces) || (c->spos && pos_bytes == sizeof(double4) && dtype == VT_F64 &&
-                                                         false);
-    // spos is sized for double4 always, so the dtype may change between builds
+                       (need_faces && !c->cap_faces);
     if (realloc_all) {
         hipDeviceSynchronize();
         free_all(c);
@@ -216,6 +222,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
         c->cap_faces = need_faces;
     }
     memcpy(c->h_items, di.data(), sizeof(DevItem) * (size_t)n_items);
+    clear_stale_error();
     TRY(hipMemcpyAsync(c->items, c->h_items, sizeof(DevItem) * (size_t)n_items, hipMemcpyHostToDevice, c->stream));
     TRY(vt_launch_zero_u32(c->counters, CTR_COUNT, c->stream));
     TRY(vt_launch_sort(c, pos, global_id));
@@ -230,6 +237,7 @@ vt_status vt_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids
     if (!c || !c->built) return VT_ERR_STATE;
     if (!volume || !nbr_off || (!nbr_ids && nbr_cap > 0) || nbr_cap < 0) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_cells(c, volume, nbr_off, nbr_ids, nbr_cap, cell_status));
     return VT_OK;
 }
@@ -238,6 +246,7 @@ vt_status vt_density(vt_ctx *c, const void *mass, vt_dtype dtype, double *rho, v
     if (!c || !c->built) return VT_ERR_STATE;
     if (!rho || (dtype != VT_F32 && dtype != VT_F64)) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_density(c, mass, dtype, rho));
     return VT_OK;
 }
@@ -246,6 +255,7 @@ vt_status vt_gradient(vt_ctx *c, const double *rho, double *grad, void *stream) 
     if (!c || !c->built) return VT_ERR_STATE;
     if (!rho || !grad) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_gradient(c, rho, grad));
     return VT_OK;
 }
@@ -255,6 +265,7 @@ vt_status vt_grid_deposit(vt_ctx *c, const double *value, int32_t nx, int32_t ny
     if (!c || !c->built) return VT_ERR_STATE;
     if (!value || !grid || nx < 1 || ny < 1 || nz < 1 || c->n_items != 1) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_grid(c, value, nx, ny, nz, grid));
     return VT_OK;
 }
@@ -264,6 +275,7 @@ vt_status vt_backward(vt_ctx *c, const double *dL_dV, double *dL_dx, void *strea
     if (!c->faces_valid) return VT_ERR_STATE;
     if (!dL_dV || !dL_dx) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_backward(c, dL_dV, dL_dx));
     return VT_OK;
 }
@@ -271,6 +283,7 @@ vt_status vt_backward(vt_ctx *c, const double *dL_dV, double *dL_dx, void *strea
 vt_status vt_stats(vt_ctx *c, int32_t *n_vertices, int32_t *n_planes, int32_t *n_tested, void *stream) {
     if (!c || !c->built) return VT_ERR_STATE;
     c->stream = (hipStream_t)stream;
+    clear_stale_error();
     TRY(vt_launch_stats(c, n_vertices, n_planes, n_tested));
     return VT_OK;
 }
@@ -291,8 +304,8 @@ vt_status vt_query(vt_ctx *c, int64_t *nnz, int64_t *n_retried, int64_t *n_incom
     if (n_retried) *n_retried = h[CTR_QUEUE];
     if (n_incomplete) *n_incomplete = h[CTR_INCOMPLETE];
     uint32_t st = h[CTR_STATUS];
+    if (st & VT_DEV_DUPLICATE) return VT_ERR_DUPLICATE;  // the root cause of any later failure
     if (st & VT_DEV_TOPOLOGY) return VT_ERR_TOPOLOGY;
-    if (st & VT_DEV_DUPLICATE) return VT_ERR_DUPLICATE;
     if (st & VT_DEV_BOX_TOO_SMALL) return VT_ERR_BOX_TOO_SMALL;
     if (st & (VT_DEV_CAPACITY | VT_DEV_NBR_CAP)) return VT_ERR_CAPACITY;
     return VT_OK;
