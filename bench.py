@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the Voronoi hot path on one MI355X.
+
+One step = the whole per-particle path over the clustered 2,097,152-particle
+periodic box (side 100, FP32 positions, half uniform background and half in 200
+NFW-like halos): Morton sort + clipping (vt_build with facets kept), neighbour
+CSR and volumes (vt_cells), densities (vt_density), density gradients
+(vt_gradient), the exact 256^3 grid deposit (vt_grid_deposit) and the volume
+adjoint (vt_backward).  Inputs are resident in HBM before the timed region.
+
+Printed (one JSON line): whole-step cells/s, the forward-only and backward
+rates, per-stage times from HIP events, the roofline of the dominant kernel
+(the clipping kernel; VALU-bound, algorithmic flops from the cost model
+6 P V + 60 V per cell, P = particles inside the security radius, V = final
+vertices) and the brute-force FP64 oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Voronoi cells/sec (neighbours+volume+density) at 2M clustered pts; bwd cells/s"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}  # vector FMA rate: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered2m", choices=["clustered2m", "uniform4096", "lattice16m",
+                                                                  "diff262k"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-variants", action="store_true", help="skip the mixed/fp64 forward comparison")
+    ap.add_argument("--fwd-only", action="store_true", help="time only vt_build + vt_cells + vt_density")
+    return ap.parse_args()
+
+
+def load_workload(name):
+    from paper_1601_06429_amd import workloads as wl
+
+    if name == "clustered2m":
+        return wl.workload2()
+    if name == "uniform4096":
+        return wl.workload1()
+    if name == "lattice16m":
+        return wl.workload3()
+    return wl.workload5()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
+              "described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1601_06429_amd as vt
+
+    vt.lib()
+    dev = torch.device("cuda:0")
+    w = load_workload(args.workload)
+    grid_dims = w.grid or (128, 128, 128)
+    prec = vt.PREC_MIXED if args.precision == "mixed" else vt.PREC_FP64
+    pos = torch.from_numpy(w.pos).to(dev)
+    mass = torch.from_numpy(w.mass).to(dev)
+    items = vt.whole_box(w.n, w.box_lo, w.box_hi, True)
+    N = w.n
+
+    ctx = vt.Context()
+    ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=True)
+    code, nnz, retried, incomplete = ctx.vt_query()
+    if code != 0:
+        raise SystemExit("build failed: %s" % vt.STATUS_NAMES.get(code))
+    vol = torch.empty(N, dtype=torch.float64, device=dev)
+    off = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device=dev)
+    st = torch.empty(N, dtype=torch.uint8, device=dev)
+    rho = torch.empty(N, dtype=torch.float64, device=dev)
+    grad = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    grid = torch.empty(grid_dims, dtype=torch.float64, device=dev)
+    dx = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    # adjoint input: dL/dV of a density-matching loss against the mean density (fixed, outside the timed region)
+    ctx.vt_cells_into(vol, off, ids, st)
+    ctx.vt_density(mass, out=rho)
+    torch.cuda.synchronize()
+    rho_mean = float(mass.sum()) / float(np.prod(w.box_len))
+    dLdV = (-2.0 * (torch.log(rho) - np.log(rho_mean)) / vol).contiguous()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    stage_ms = np.zeros(6)
+    build_ms = np.zeros(3)
+
+    def step(record):
+        if record:
+            ev[0].record()
+        ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=record)
+        if record:
+            ev[1].record()
+        ctx.vt_cells_into(vol, off, ids, st)
+        if record:
+            ev[2].record()
+        ctx.vt_density(mass, out=rho)
+        if record:
+            ev[3].record()
+        if not args.fwd_only:
+            ctx.vt_gradient(rho, out=grad)
+            if record:
+                ev[4].record()
+            ctx.vt_grid_deposit(rho, grid_dims, out=grid)
+            if record:
+                ev[5].record()
+            ctx.vt_backward(dLdV, out=dx)
+            if record:
+                ev[6].record()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # stage breakdown (separate, event-recorded steps)
+    nrec = 3
+    for _ in range(nrec):
+        step(True)
+        torch.cuda.synchronize()
+        n_ev = 4 if args.fwd_only else 7
+        for k in range(n_ev - 1):
+            stage_ms[k] += ev[k].elapsed_time(ev[k + 1]) / nrec
+        bm = ctx.vt_timings()
+        build_ms += np.asarray(bm) / nrec
+    code, nnz, retried, incomplete = ctx.vt_query()
+    if code != 0:
+        raise SystemExit("timed run reported: %s" % vt.STATUS_NAMES.get(code))
+
+    # cost model of the clipping kernel over the actual cells
+    nv, npl, ntest = ctx.vt_stats()
+    nv = nv.to(torch.float64)
+    npl = npl.to(torch.float64)
+    alg_flops = float((6.0 * npl * nv + 60.0 * nv).sum())
+    clip_ms = build_ms[1] + build_ms[2]
+    achieved = alg_flops / (clip_ms * 1e-3) / 1e12
+    dtype = "f64" if prec == vt.PREC_FP64 else "f32"
+
+    fwd_ms = stage_ms[0] + stage_ms[1] + stage_ms[2]
+    out = {
+        "metric": METRIC,
+        "value": N / (ms_per_step * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_cells": N, "box": float(w.box_len[0]), "positions": str(w.pos.dtype),
+                   "grid": list(grid_dims) if not args.fwd_only else None, "precision": args.precision,
+                   "step": "build+cells+density" + ("" if args.fwd_only else "+gradient+grid+backward")},
+        "fwd_cells_per_s": N / (fwd_ms * 1e-3),
+        "bwd_cells_per_s": (N / (stage_ms[5] * 1e-3)) if not args.fwd_only else None,
+        "stage_ms": {"build": stage_ms[0], "cells": stage_ms[1], "density": stage_ms[2],
+                     "gradient": stage_ms[3], "grid": stage_ms[4], "backward": stage_ms[5],
+                     "sort": build_ms[0], "clip": build_ms[1], "clip_large": build_ms[2]},
+        "nnz": nnz,
+        "retried_cells": retried,
+        "roofline": {"kernel": "k_clip (fast + large)", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype],
+                     "traffic": None, "alg_flops_per_launch": alg_flops, "launch_ms": clip_ms,
+                     "mean_planes": float(npl.mean()), "mean_vertices": float(nv.mean()),
+                     "mean_tested": float(ntest.to(torch.float64).mean())},
+    }
+
+    if not args.no_variants:
+        # forward-only comparison of the two precisions at the same accuracy bar
+        var = {}
+        for name, p in (("fp64", vt.PREC_FP64), ("mixed", vt.PREC_MIXED)):
+            c2 = vt.Context()
+            for _ in range(2):
+                c2.vt_build(pos, items, precision=p, want_faces=False)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                c2.vt_build(pos, items, precision=p, want_faces=False)
+                c2.vt_cells_into(vol, off, ids, st)
+                c2.vt_density(mass, out=rho)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            code2 = c2.vt_query()[0]
+            var[name] = {"fwd_cells_per_s": N * reps / (tb - ta), "status": vt.STATUS_NAMES.get(code2)}
+            del c2
+        out["precision_variants"] = var
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        nthr = min(os.cpu_count() or 1, 16)
+        rng = np.random.default_rng(12345)
+        sample = np.sort(rng.choice(N, min(args.cpu_sample, N), replace=False))
+        p64 = w.pos.astype(np.float64)
+        oracle.cells(p64, w.box_lo, w.box_hi, query=sample[:16], nthreads=nthr)  # warm (page-in)
+        ta = time.perf_counter()
+        ref = oracle.cells(p64, w.box_lo, w.box_hi, query=sample, nthreads=nthr)
+        dens = oracle.density(w.mass[sample], ref.volume)
+        tb = time.perf_counter()
+        out["cpu_baseline"] = {"value": len(sample) / (tb - ta), "unit": "cells/s", "cores": nthr, "kind": "oracle",
+                               "sample": "%d seeded cells of the same workload (neighbours+volume+density, "
+                                         "brute force over all %d particles per cell), %.1f s wall" %
+                                         (len(sample), N, tb - ta)}
+        # parity of the benchmarked configuration on the same sample
+        vol_h = vol.cpu().numpy()
+        off_h = off.cpu().numpy()
+        ids_h = ids.cpu().numpy()
+        same = all(np.array_equal(ids_h[off_h[i]:off_h[i + 1]], ref.neighbours(q)) for q, i in enumerate(sample))
+        rel = np.abs(vol_h[sample] - ref.volume) / ref.volume
+        out["parity_on_sample"] = {"neighbours_bit_exact": bool(same), "max_rel_volume_err": float(rel.max()),
+                                   "max_rel_density_err": float(np.max(np.abs(
+                                       rho.cpu().numpy()[sample] - dens) / dens))}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -96,7 +96,8 @@ typedef struct {
     float radius_factor;   /* first search radius in local mean spacings (default 2.6) */
     float area_eps;        /* facets with area <= area_eps * V^(2/3) are not facets (default 1e-12) */
     int32_t waves_per_cu;  /* persistent clip kernel occupancy (default 16) */
-    int32_t reserved[3];
+    int32_t timing;        /* record HIP events around the sort and clip kernels (see vt_timings) */
+    int32_t reserved[2];
 } vt_opts;
 
 /*
@@ -192,6 +193,14 @@ vt_status vt_query(vt_ctx *ctx, int64_t *nnz, int64_t *n_retried, int64_t *n_inc
  * candidates actually tested.  Used by the benchmark's cost model.
  */
 vt_status vt_stats(vt_ctx *ctx, int32_t *n_vertices, int32_t *n_planes, int32_t *n_tested, void *stream);
+
+/*
+ * vt_timings -- durations (ms) of the last build's stages, measured with HIP
+ * events recorded on the build's stream when opts.timing was set:
+ * ms[0] = Morton sort and tables, ms[1] = fast clip kernel, ms[2] = large
+ * clip kernel.  Synchronises on the events; VT_ERR_STATE if timing was off.
+ */
+vt_status vt_timings(vt_ctx *ctx, float ms[3]);
 
 /* n_owned_total and n_total of the last build (host, no sync). */
 vt_status vt_sizes(vt_ctx *ctx, int64_t *n_owned_total, int64_t *n_total);

@@ -47,7 +47,8 @@ class vt_item(ctypes.Structure):
 
 class vt_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_faces", ctypes.c_int32), ("radius_factor", ctypes.c_float),
-                ("area_eps", ctypes.c_float), ("waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("area_eps", ctypes.c_float), ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def lib():
@@ -79,12 +80,13 @@ def lib():
             L.vt_query.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]
             L.vt_stats.argtypes = [P, P, P, P, P]
             L.vt_sizes.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+            L.vt_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
             L.vt_destroy.argtypes = [P]
             L.vt_destroy.restype = None
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
-                      "vt_query", "vt_stats", "vt_sizes"):
+                      "vt_query", "vt_stats", "vt_sizes", "vt_timings"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -158,7 +160,7 @@ class Context:
             pass
 
     def vt_build(self, pos, items, global_id=None, precision=PREC_FP64, want_faces=False, radius_factor=0.0,
-                 area_eps=0.0, waves_per_cu=0, stream=None):
+                 area_eps=0.0, waves_per_cu=0, timing=False, stream=None):
         import torch
 
         _require_cuda(pos, "pos")
@@ -180,6 +182,7 @@ class Context:
         o.radius_factor = float(radius_factor)
         o.area_eps = float(area_eps)
         o.waves_per_cu = int(waves_per_cu)
+        o.timing = 1 if timing else 0
         arr = _items(items)
         self._keep = [pos, global_id]
         _check(lib().vt_build(ctypes.byref(self._ctx), _ptr(pos), dt, _ptr(global_id), arr, len(items),
@@ -189,6 +192,11 @@ class Context:
         self.n_owned, self.n_total = no.value, nt.value
         self.device = pos.device
         return self
+
+    def vt_timings(self):
+        ms = (ctypes.c_float * 3)()
+        _check(lib().vt_timings(self._ctx, ms), "vt_timings")
+        return [float(x) for x in ms]
 
     def vt_query(self):
         nnz, rt, inc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

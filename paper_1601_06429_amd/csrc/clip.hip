@@ -36,6 +36,7 @@ struct ClipMem {
     } u;
     int32_t rb[64];                      // gather: cell range starts
     int32_t rp[64];                      // gather: prefix of range lengths
+    int32_t hist[64];                    // gather: d^2 histogram of the shell
     PolyMem<T, VPL> P;
 };
 
@@ -188,7 +189,14 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
         bool overflow = false, corrupt = false;
         int ntested = 0, nplanes = 1;
 
-        // ---------------- search and clip, in shells of increasing radius
+        // ---------------- search and clip
+        // The first shell [0, r0) is fitted to LDS (a d^2 histogram picks a radius
+        // holding at most VT_CAND_MAX particles) and applied nearest first.  Each
+        // later shell reaches for the security radius 2R but grows the searched
+        // radius by at most 2x; a shell that fits in LDS is applied nearest first,
+        // a larger one is swept once with lanes = particles: a plane that cuts no
+        // vertex of the current cell is dropped (the cell only shrinks, so it never
+        // would cut it), the survivors are applied nearest first.
         double r_done = 0.0;
         double r_next = (double)A.radius_factor * local_spacing(A, it, bi, j0);
         const double Lmin = fmin(it.L[0], fmin(it.L[1], it.L[2]));
@@ -196,23 +204,21 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                                          : sqrt(it.L[0] * it.L[0] + it.L[1] * it.L[1] + it.L[2] * it.L[2]) * 1.0001;
         if (r_next > r_cap) r_next = r_cap;
         bool complete = false;
-        for (int pass = 0; pass < 64; ++pass) {
-            // ---- candidate cells: Morton level whose cell side is >= r_next
-            const double rh2 = r_next * r_next, rl2 = r_done * r_done;
+
+        // Morton cells covering the ball of radius r: ranges to S.rb / S.rp (lane = cell)
+        auto cover = [&](double r, int &ncq) -> int {
             int lvl = 0;
-            {
-                double c = it.S;
-                while (lvl < VT_MORTON_BITS && 0.5 * c >= r_next) {
-                    c *= 0.5;
-                    ++lvl;
-                }
+            double c = it.S;
+            while (lvl < VT_MORTON_BITS && 0.5 * c >= r) {
+                c *= 0.5;
+                ++lvl;
             }
             const int sh = VT_MORTON_BITS - lvl;
             const int64_t ncl = 1ll << lvl;
             int64_t a0[3], na[3];
             for (int a = 0; a < 3; ++a) {
-                int64_t q0 = vt_qraw(xs[a] - r_next, it.lo[a], it.inv_res) - 1;
-                int64_t q1 = vt_qraw(xs[a] + r_next, it.lo[a], it.inv_res) + 1;
+                int64_t q0 = vt_qraw(xs[a] - r, it.lo[a], it.inv_res) - 1;
+                int64_t q1 = vt_qraw(xs[a] + r, it.lo[a], it.inv_res) + 1;
                 int64_t i0 = q0 >> sh, i1 = q1 >> sh;
                 if (it.periodic) {
                     if (i1 - i0 + 1 >= ncl) {
@@ -226,7 +232,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 a0[a] = i0;
                 na[a] = i1 >= i0 ? i1 - i0 + 1 : 0;
             }
-            const int ncq = (int)(na[0] * na[1] * na[2]);  // at most 4 per axis
+            ncq = (int)(na[0] * na[1] * na[2]);  // at most 4 per axis
             int32_t rbeg = 0, rlen = 0;
             if (lane < ncq) {
                 int ix = lane % (int)na[0], iy = (lane / (int)na[0]) % (int)na[1], iz = lane / (int)(na[0] * na[1]);
@@ -246,40 +252,137 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
             S.rb[lane] = rbeg;
             S.rp[lane] = pre;
             wave_sync();
-            // ---- gather particles with r_done <= d < r_next
-            int n = 0;
-            for (int base = 0; base < total; base += WAVE) {
-                int f = base + lane;
+            return total;
+        };
+        // particle f of the flattened cover -> sorted index, separation, d^2
+        auto fetch = [&](int f, int ncq, int32_t &j, double &dx, double &dy, double &dz) -> double {
+            int lo = 0, hi = ncq - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            j = S.rb[lo] + (f - S.rp[lo]);
+            double px, py, pz;
+            load_pos<PT4>(A.spos, j, px, py, pz);
+            dx = px - sx;
+            dy = py - sy;
+            dz = pz - sz;
+            if (it.periodic) {
+                dx -= it.L[0] * rint(dx / it.L[0]);
+                dy -= it.L[1] * rint(dy / it.L[1]);
+                dz -= it.L[2] * rint(dz / it.L[2]);
+            }
+            return dx * dx + dy * dy + dz * dz;
+        };
+
+        // ---- one sweep over the shell [r_lo, r_hi): lanes = particles, planes that cut
+        // no vertex of the current cell are dropped, survivors are applied nearest first
+        auto sweep = [&](double r_lo, double r_hi) {
+            const double rl2 = r_lo * r_lo, rh2 = r_hi * r_hi;
+            int ncq;
+            const int total = cover(r_hi, ncq);
+            bool dirty = true;
+            for (int base = 0; base < total && !overflow && !corrupt; base += WAVE) {
+                const int f = base + lane;
                 bool keep = false;
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
                 int32_t j = -1;
                 if (f < total) {
-                    int lo = 0, hi = ncq - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
+                    d2 = fetch(f, ncq, j, dx, dy, dz);
+                    if (j != j0) {
+                        if (d2 == 0.0) dup = 1;
+                        keep = (d2 > 0.0) && (d2 >= rl2) && (d2 < rh2) && (d2 < 4.0 * P.R2);
                     }
-                    j = S.rb[lo] + (f - S.rp[lo]);
-                    double px, py, pz;
-                    load_pos<PT4>(A.spos, j, px, py, pz);
-                    dx = px - sx;
-                    dy = py - sy;
-                    dz = pz - sz;
-                    if (it.periodic) {
-                        dx -= it.L[0] * rint(dx / it.L[0]);
-                        dy -= it.L[1] * rint(dy / it.L[1]);
-                        dz -= it.L[2] * rint(dz / it.L[2]);
+                }
+                const uint64_t km = __ballot(keep);
+                if (km == 0) continue;
+                nplanes += __popcll(km);
+                ntested += __popcll(km);
+                if (dirty) {
+                    // vertex positions (and, mixed, their error bounds) for the lane-parallel test
+#pragma unroll
+                    for (int s = 0; s < VPL; ++s)
+                        if (P.alive[s] & mybit) {
+                            S.u.f.vp[s * 64 + lane][0] = (double)P.vx[s];
+                            S.u.f.vp[s * 64 + lane][1] = (double)P.vy[s];
+                            S.u.f.vp[s * 64 + lane][2] = (double)P.vz[s];
+                            S.u.f.fa[s * 64 + lane] = (double)P.ve[s];
+                        }
+                    wave_sync();
+                    dirty = false;
+                }
+                const double pd = 0.5 * d2;
+                const double nn = sqrt(d2);
+                bool act = false;
+#pragma unroll
+                for (int s = 0; s < VPL; ++s) {
+                    uint64_t m = P.alive[s];
+                    while (m) {
+                        const int k = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const double *v = S.u.f.vp[s * 64 + k];
+                        const double sv = dx * v[0] + dy * v[1] + dz * v[2] - pd;
+                        // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
+                        double marg = 0.0;
+                        if (std::is_same<T, float>::value)
+                            marg = nn * (S.u.f.fa[s * 64 + k] +
+                                         1e-6 * (sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + 0.5 * nn));
+                        act |= sv > -marg;
                     }
-                    d2 = dx * dx + dy * dy + dz * dz;
+                }
+                uint64_t am = __ballot(keep && act);
+                while (am) {
+                    const double key = (am & mybit) ? d2 : 1e300;
+                    const double mn = wave_min(key);
+                    const uint64_t who = __ballot((am & mybit) && d2 == mn);
+                    const int k = __builtin_ctzll(who);
+                    am &= ~(1ull << k);
+                    P4<double> p64;
+                    p64.x = __shfl(dx, k);
+                    p64.y = __shfl(dy, k);
+                    p64.z = __shfl(dz, k);
+                    p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
+                    const int32_t tag = __shfl(j, k);
+                    const int rc = P.clip(S.P, p64, tag);
+                    if (rc == CLIP_CUT) {
+                        dirty = true;
+                    } else if (rc == CLIP_OVERFLOW) {
+                        overflow = true;
+                        break;
+                    } else if (rc < 0) {
+                        corrupt = true;
+                        break;
+                    }
+                }
+            }
+            wave_sync();
+        };
+
+        int refine = 0;
+        for (int pass = 0; pass < 160; ++pass) {
+            const double rh2 = r_next * r_next, rl2 = r_done * r_done;
+            int ncq;
+            const int total = cover(r_next, ncq);
+            S.hist[lane] = 0;
+            wave_sync();
+            // ---- gather particles with r_done <= d < r_next (and a d^2 histogram)
+            int n = 0;
+            for (int base = 0; base < total; base += WAVE) {
+                const int f = base + lane;
+                bool keep = false;
+                double dx = 0, dy = 0, dz = 0, d2 = 0;
+                int32_t j = -1;
+                if (f < total) {
+                    d2 = fetch(f, ncq, j, dx, dy, dz);
                     if (j != j0) {
                         // a coincident particle has no bisector: report it, do not clip with it
                         if (d2 == 0.0) dup = 1;
                         keep = (d2 > 0.0) && (d2 >= rl2) && (d2 < rh2);
                     }
                 }
-                uint64_t km = __ballot(keep);
+                const uint64_t km = __ballot(keep);
                 if (keep) {
-                    int slot = n + __popcll(km & lt);
+                    const int slot = n + __popcll(km & lt);
                     if (slot < VT_CAND_MAX) {
                         S.u.c.cd[slot][0] = dx;
                         S.u.c.cd[slot][1] = dy;
@@ -289,63 +392,71 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                         uint32_t q = qf >= 16777215.0 ? 16777215u : (uint32_t)qf;
                         S.u.c.ckey[slot] = (q << 8) | (uint32_t)slot;
                     }
+                    int bin = (int)((d2 - rl2) / (rh2 - rl2) * 64.0);
+                    atomicAdd(&S.hist[bin < 0 ? 0 : (bin > 63 ? 63 : bin)], 1);
                 }
                 n += __popcll(km);
             }
             wave_sync();
-            if (n > VT_CAND_MAX) {
-                // too many particles in this shell: shrink its outer radius by the volume ratio
-                double fct = cbrt((double)VT_CAND_MAX / (double)n) * 0.9;
-                double rn = r_done + (r_next - r_done) * fct;
-                if (!(rn > r_done) || rn >= r_next) rn = r_done + 0.5 * (r_next - r_done);
-                r_next = rn;
+            if (n > VT_CAND_MAX && r_done == 0.0 && refine < 16) {
+                // first shell too full: the largest b with at most VT_CAND_MAX particles in bins [0, b)
+                const int h = S.hist[lane];
+                int tot;
+                const int pre = wave_excl_scan(h, &tot);
+                const uint64_t fit = __ballot(pre + h <= VT_CAND_MAX);
+                int b = (fit == ~0ull) ? 64 : __builtin_ctzll(~fit);
+                if (b < 1) b = 1;
+                r_next = sqrt(rl2 + (rh2 - rl2) * (double)b / 64.0);
+                ++refine;
                 continue;
             }
-            // ---- sort by distance
-            uint32_t k0 = (lane < n) ? S.u.c.ckey[lane] : 0xFFFFFFFFu;
-            uint32_t k1 = (lane + 64 < n) ? S.u.c.ckey[lane + 64] : 0xFFFFFFFFu;
-            if (n > 64)
-                bitonic128(k0, k1);
-            else if (n > 1)
-                k0 = bitonic64(k0);
-            // ---- clip in increasing distance; stop at the first particle beyond 2R
-            auto q4r = [&](double r2) -> uint32_t {
-                double x = 4.0 * r2 / rh2 * 16777216.0;
-                return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
-            };
-            uint32_t Q4R = q4r(P.R2);
-            for (int i = 0; i < n; ++i) {
-                uint32_t key = (i < 64) ? readlane_u32(k0, i) : readlane_u32(k1, i - 64);
-                if ((key >> 8) > Q4R) break;
-                const int slot = (int)(key & 0xFFu);
-                ++ntested;
-                P4<double> p64;
-                p64.x = S.u.c.cd[slot][0];
-                p64.y = S.u.c.cd[slot][1];
-                p64.z = S.u.c.cd[slot][2];
-                p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
-                int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
-                if (rc == CLIP_CUT) {
-                    Q4R = q4r(P.R2);
-                } else if (rc == CLIP_OVERFLOW) {
-                    overflow = true;
-                    break;
-                } else if (rc < 0) {
-                    corrupt = true;
-                    break;
+            if (n > VT_CAND_MAX) {
+                sweep(r_done, r_next);
+            } else {
+                // ---- sort by distance
+                uint32_t k0 = (lane < n) ? S.u.c.ckey[lane] : 0xFFFFFFFFu;
+                uint32_t k1 = (lane + 64 < n) ? S.u.c.ckey[lane + 64] : 0xFFFFFFFFu;
+                if (n > 64)
+                    bitonic128(k0, k1);
+                else if (n > 1)
+                    k0 = bitonic64(k0);
+                // ---- clip in increasing distance; stop at the first particle beyond 2R
+                auto q4r = [&](double r2) -> uint32_t {
+                    double x = 4.0 * r2 / rh2 * 16777216.0;
+                    return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
+                };
+                uint32_t Q4R = q4r(P.R2);
+                for (int i = 0; i < n; ++i) {
+                    const uint32_t key = (i < 64) ? readlane_u32(k0, i) : readlane_u32(k1, i - 64);
+                    if ((key >> 8) > Q4R) break;
+                    const int slot = (int)(key & 0xFFu);
+                    ++ntested;
+                    P4<double> p64;
+                    p64.x = S.u.c.cd[slot][0];
+                    p64.y = S.u.c.cd[slot][1];
+                    p64.z = S.u.c.cd[slot][2];
+                    p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
+                    const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
+                    if (rc == CLIP_CUT) {
+                        Q4R = q4r(P.R2);
+                    } else if (rc == CLIP_OVERFLOW) {
+                        overflow = true;
+                        break;
+                    } else if (rc < 0) {
+                        corrupt = true;
+                        break;
+                    }
                 }
-            }
-            if (overflow || corrupt) break;
-            // particles the security criterion had to examine in this shell
-            {
+                // particles the security criterion had to examine in this shell
                 int cntp = 0;
                 for (int b2 = lane; b2 < n; b2 += 64) {
                     double x = S.u.c.cd[b2][0], y = S.u.c.cd[b2][1], z = S.u.c.cd[b2][2];
                     if (x * x + y * y + z * z < 4.0 * P.R2) ++cntp;
                 }
                 nplanes += wave_sum_i(cntp);
+                wave_sync();
             }
-            wave_sync();
+            if (overflow || corrupt) break;
             r_done = r_next;
             const double need = 2.0 * sqrt(P.R2);
             if (need <= r_done) {
@@ -353,9 +464,11 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 break;
             }
             if (r_done >= r_cap) break;
-            r_next = fmax(need * (1.0 + 1e-9), r_done * 1.05);
+            // next shell: up to the security radius, growing the searched radius by 1.25x to 2x
+            r_next = fmin(fmax(need * (1.0 + 1e-9), 1.25 * r_done), 2.0 * r_done);
             if (r_next > r_cap) r_next = r_cap;
         }
+        const bool exhausted = !complete && r_done < r_cap;
         dup = __ballot(dup != 0) ? 1u : 0u;
 
         if (overflow && !RETRY) {
@@ -501,7 +614,10 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
         if (lane == 0) {
             uint8_t st = RETRY ? VT_CELL_RETRIED : 0;
             bool incomplete = false;
-            if (it.periodic) {
+            if (exhausted) {
+                atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                st |= VT_CELL_FAILED;
+            } else if (it.periodic) {
                 if (!complete || any_wall || 4.0 * Rfin >= Lmin) {
                     atomicOr(&A.counters[CTR_STATUS], VT_DEV_BOX_TOO_SMALL);
                     st |= VT_CELL_FAILED;
@@ -553,6 +669,10 @@ static hipError_t launch_prec(vt_ctx *c, ClipArgs &a) {
     a.queue = nullptr;
     hipError_t e = launch_one<T, PT4, 1, false>(c, a, 4);
     if (e != hipSuccess) return e;
+    if (c->timed) {
+        e = hipEventRecord(c->ev[2], c->stream);
+        if (e != hipSuccess) return e;
+    }
     a.row_base = (int64_t)c->cap_owned * VT_FSTRIDE_FAST;
     a.fstride = VT_FSTRIDE_BIG;
     a.queue = c->queue;

@@ -224,9 +224,15 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
     memcpy(c->h_items, di.data(), sizeof(DevItem) * (size_t)n_items);
     clear_stale_error();
     TRY(hipMemcpyAsync(c->items, c->h_items, sizeof(DevItem) * (size_t)n_items, hipMemcpyHostToDevice, c->stream));
+    c->timed = o.timing != 0;
+    if (c->timed && !c->ev[0])
+        for (int k = 0; k < 4; ++k) TRY(hipEventCreate(&c->ev[k]));
+    if (c->timed) TRY(hipEventRecord(c->ev[0], c->stream));
     TRY(vt_launch_zero_u32(c->counters, CTR_COUNT, c->stream));
     TRY(vt_launch_sort(c, pos, global_id));
+    if (c->timed) TRY(hipEventRecord(c->ev[1], c->stream));
     TRY(vt_launch_clip(c));
+    if (c->timed) TRY(hipEventRecord(c->ev[3], c->stream));
     c->built = true;
     c->faces_valid = need_faces;
     return VT_OK;
@@ -288,6 +294,13 @@ vt_status vt_stats(vt_ctx *c, int32_t *n_vertices, int32_t *n_planes, int32_t *n
     return VT_OK;
 }
 
+vt_status vt_timings(vt_ctx *c, float ms[3]) {
+    if (!c || !c->built || !c->timed || !ms) return VT_ERR_STATE;
+    TRY(hipEventSynchronize(c->ev[3]));
+    for (int k = 0; k < 3; ++k) TRY(hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    return VT_OK;
+}
+
 vt_status vt_sizes(vt_ctx *c, int64_t *n_owned_total, int64_t *n_total) {
     if (!c) return VT_ERR_ARG;
     if (n_owned_total) *n_owned_total = c->n_owned;
@@ -315,6 +328,8 @@ void vt_destroy(vt_ctx *c) {
     if (!c) return;
     hipDeviceSynchronize();
     free_all(c);
+    for (int k = 0; k < 4; ++k)
+        if (c->ev[k]) hipEventDestroy(c->ev[k]);
     delete c;
 }
 

@@ -94,11 +94,14 @@ struct vt_ctx {
     int64_t *rowoff = nullptr;     // facet offsets in output-row order (n_owned + 1)
     int32_t *row2cell = nullptr;   // cell slot of each output row
     uint32_t *h_counters = nullptr;
+    // optional stage timing
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
 };
 
 // ---------------------------------------------------------------- launchers
 hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid);
-hipError_t vt_launch_clip(vt_ctx *c);
+hipError_t vt_launch_clip(vt_ctx *c);  // records ev[2] between the two kernels when timing
 hipError_t vt_launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 hipError_t vt_launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 hipError_t vt_launch_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
