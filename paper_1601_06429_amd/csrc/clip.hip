@@ -34,8 +34,8 @@ struct ClipMem {
             double fc[64 * VPL][3];      // facet centroid (seed-relative)
         } f;
     } u;
-    int32_t rb[64];                      // gather: cell range starts
-    int32_t rp[64];                      // gather: prefix of range lengths
+    int32_t rb[216];                     // gather: cell range starts
+    int32_t rp[216];                     // gather: prefix of range lengths
     int32_t hist[64];                    // gather: d^2 histogram of the shell
     PolyMem<T, VPL> P;
 };
@@ -161,14 +161,17 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
     for (;;) {
         int64_t w = 0;
         if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_RETRY : CTR_CELL], 1u);
-        w = (int64_t)__shfl((long long)w, 0);
+        w = (int64_t)uni_i((int)__shfl((long long)w, 0));
         if (w >= ntodo) break;
-        const int32_t cslot = RETRY ? A.queue[w] : (int32_t)w;
-        const int32_t j0 = A.cells[cslot];
-        const int bi = find_item_d(A.items, A.n_items, j0);
+        const int32_t cslot = uni_i(RETRY ? A.queue[w] : (int32_t)w);
+        const int32_t j0 = uni_i(A.cells[cslot]);
+        const int bi = uni_i(find_item_d(A.items, A.n_items, j0));
         const DevItem &it = A.items[bi];
         double sx, sy, sz;
         load_pos<PT4>(A.spos, j0, sx, sy, sz);
+        sx = uni_d(sx);
+        sy = uni_d(sy);
+        sz = uni_d(sz);
         const double xs[3] = {sx, sy, sz};
 
         // ---------------- initial polytope: the box around the seed
@@ -198,24 +201,30 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
         // vertex of the current cell is dropped (the cell only shrinks, so it never
         // would cut it), the survivors are applied nearest first.
         double r_done = 0.0;
-        double r_next = (double)A.radius_factor * local_spacing(A, it, bi, j0);
+        double r_next = uni_d((double)A.radius_factor * local_spacing(A, it, bi, j0));
         const double Lmin = fmin(it.L[0], fmin(it.L[1], it.L[2]));
         const double r_cap = it.periodic ? 0.5 * Lmin
                                          : sqrt(it.L[0] * it.L[0] + it.L[1] * it.L[1] + it.L[2] * it.L[2]) * 1.0001;
         if (r_next > r_cap) r_next = r_cap;
         bool complete = false;
 
-        // Morton cells covering the ball of radius r: ranges to S.rb / S.rp (lane = cell)
-        auto cover = [&](double r, int &ncq) -> int {
+        // Morton cells that may hold particles with rmin <= d < r: cells of side in
+        // [r/2, r), pruned by their distance to the seed (boxes widened by one
+        // quantum, the rounding of the keys), empty ranges dropped; ranges go to
+        // S.rb / S.rp compacted.  Returns the number of ranges; *total the particles.
+        const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
+        auto cover = [&](double r, double rmin, int &total) -> int {
             int lvl = 0;
             double c = it.S;
-            while (lvl < VT_MORTON_BITS && 0.5 * c >= r) {
+            while (lvl < VT_MORTON_BITS && c >= r) {
                 c *= 0.5;
                 ++lvl;
             }
             const int sh = VT_MORTON_BITS - lvl;
             const int64_t ncl = 1ll << lvl;
-            int64_t a0[3], na[3];
+            const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
+            int64_t a0[3];
+            int na[3];
             for (int a = 0; a < 3; ++a) {
                 int64_t q0 = vt_qraw(xs[a] - r, it.lo[a], it.inv_res) - 1;
                 int64_t q1 = vt_qraw(xs[a] + r, it.lo[a], it.inv_res) + 1;
@@ -230,29 +239,66 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     if (i1 > ncl - 1) i1 = ncl - 1;
                 }
                 a0[a] = i0;
-                na[a] = i1 >= i0 ? i1 - i0 + 1 : 0;
+                na[a] = i1 >= i0 ? (int)(i1 - i0 + 1) : 0;  // at most 6
             }
-            ncq = (int)(na[0] * na[1] * na[2]);  // at most 4 per axis
-            int32_t rbeg = 0, rlen = 0;
-            if (lane < ncq) {
-                int ix = lane % (int)na[0], iy = (lane / (int)na[0]) % (int)na[1], iz = lane / (int)(na[0] * na[1]);
-                int64_t cx = a0[0] + ix, cy = a0[1] + iy, cz = a0[2] + iz;
-                if (it.periodic) {
-                    cx &= ncl - 1;
-                    cy &= ncl - 1;
-                    cz &= ncl - 1;
+            const int ncells = na[0] * na[1] * na[2];
+            const double r2 = r * r, rmin2 = rmin * rmin;
+            int count = 0;
+            for (int base = 0; base < ncells; base += WAVE) {
+                const int k = base + lane;
+                bool keep = false;
+                int32_t b = 0, e = 0;
+                if (k < ncells) {
+                    const int ix = k % na[0], iy = (k / na[0]) % na[1], iz = k / (na[0] * na[1]);
+                    const int64_t u[3] = {a0[0] + ix, a0[1] + iy, a0[2] + iz};
+                    // per axis: nearest and farthest distance from the seed to the cell,
+                    // minimised over the periodic images (a lower / upper bound for the
+                    // minimum-image distance of every particle in the cell)
+                    double dmin2 = 0.0, dmax2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double dn = 1e300, df = 1e300;
+                        for (int sh_ = -1; sh_ <= 1; ++sh_) {
+                            if (sh_ != 0 && !it.periodic) continue;
+                            const double off_ = sh_ * it.L[a];
+                            const double blo_ = it.lo[a] + (double)u[a] * c - quantum + off_;
+                            const double bhi_ = it.lo[a] + (double)(u[a] + 1) * c + quantum + off_;
+                            const double dl = blo_ - xs[a], dh = xs[a] - bhi_;
+                            dn = fmin(dn, fmax(0.0, fmax(dl, dh)));
+                            df = fmin(df, fmax(fabs(dl), fabs(dh)));
+                        }
+                        dmin2 += dn * dn;
+                        dmax2 += df * df;
+                    }
+                    keep = dmin2 < r2 && dmax2 >= rmin2;
+                    if (keep) {
+                        uint64_t cc[3];
+                        for (int a = 0; a < 3; ++a) cc[a] = (uint64_t)(it.periodic ? (u[a] & (ncl - 1)) : u[a]);
+                        cell_range(A, it, bi, lvl, cc[0], cc[1], cc[2], b, e);
+                        keep = e > b;
+                    }
                 }
-                int32_t b, e;
-                cell_range(A, it, bi, lvl, (uint64_t)cx, (uint64_t)cy, (uint64_t)cz, b, e);
-                rbeg = b;
-                rlen = e - b;
+                const uint64_t km = __ballot(keep);
+                if (keep) {
+                    const int slot = count + __popcll(km & lt);
+                    S.rb[slot] = b;
+                    S.rp[slot] = e - b;  // length for now
+                }
+                count += __popcll(km);
             }
-            int total;
-            int pre = wave_excl_scan(rlen, &total);
-            S.rb[lane] = rbeg;
-            S.rp[lane] = pre;
             wave_sync();
-            return total;
+            // lengths -> exclusive prefix
+            int carry = 0;
+            for (int base = 0; base < count; base += WAVE) {
+                const int k = base + lane;
+                const int len = k < count ? S.rp[k] : 0;
+                int tot;
+                const int pre = wave_excl_scan(len, &tot);
+                if (k < count) S.rp[k] = carry + pre;
+                carry += tot;
+            }
+            wave_sync();
+            total = uni_i(carry);
+            return uni_i(count);
         };
         // particle f of the flattened cover -> sorted index, separation, d^2
         auto fetch = [&](int f, int ncq, int32_t &j, double &dx, double &dy, double &dz) -> double {
@@ -268,9 +314,9 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
             dy = py - sy;
             dz = pz - sz;
             if (it.periodic) {
-                dx -= it.L[0] * rint(dx / it.L[0]);
-                dy -= it.L[1] * rint(dy / it.L[1]);
-                dz -= it.L[2] * rint(dz / it.L[2]);
+                dx -= it.L[0] * rint(dx * invL[0]);
+                dy -= it.L[1] * rint(dy * invL[1]);
+                dz -= it.L[2] * rint(dz * invL[2]);
             }
             return dx * dx + dy * dy + dz * dz;
         };
@@ -279,8 +325,8 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
         // no vertex of the current cell are dropped, survivors are applied nearest first
         auto sweep = [&](double r_lo, double r_hi) {
             const double rl2 = r_lo * r_lo, rh2 = r_hi * r_hi;
-            int ncq;
-            const int total = cover(r_hi, ncq);
+            int total;
+            const int ncq = cover(r_hi, r_lo, total);
             bool dirty = true;
             for (int base = 0; base < total && !overflow && !corrupt; base += WAVE) {
                 const int f = base + lane;
@@ -299,6 +345,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 nplanes += __popcll(km);
                 ntested += __popcll(km);
                 if (dirty) {
+                    P.update_r2();
                     // vertex positions (and, mixed, their error bounds) for the lane-parallel test
 #pragma unroll
                     for (int s = 0; s < VPL; ++s)
@@ -355,14 +402,16 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     }
                 }
             }
+            P.update_r2();
             wave_sync();
         };
 
         int refine = 0;
         for (int pass = 0; pass < 160; ++pass) {
             const double rh2 = r_next * r_next, rl2 = r_done * r_done;
-            int ncq;
-            const int total = cover(r_next, ncq);
+            const double inv_rh2 = 1.0 / rh2, inv_bin = 64.0 / (rh2 - rl2);
+            int total;
+            const int ncq = cover(r_next, r_done, total);
             S.hist[lane] = 0;
             wave_sync();
             // ---- gather particles with r_done <= d < r_next (and a d^2 histogram)
@@ -388,11 +437,11 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                         S.u.c.cd[slot][1] = dy;
                         S.u.c.cd[slot][2] = dz;
                         S.u.c.cid[slot] = j;
-                        double qf = d2 / rh2 * 16777216.0;
+                        double qf = d2 * inv_rh2 * 16777216.0;
                         uint32_t q = qf >= 16777215.0 ? 16777215u : (uint32_t)qf;
                         S.u.c.ckey[slot] = (q << 8) | (uint32_t)slot;
                     }
-                    int bin = (int)((d2 - rl2) / (rh2 - rl2) * 64.0);
+                    int bin = (int)((d2 - rl2) * inv_bin);
                     atomicAdd(&S.hist[bin < 0 ? 0 : (bin > 63 ? 63 : bin)], 1);
                 }
                 n += __popcll(km);
@@ -426,9 +475,16 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
                 };
                 uint32_t Q4R = q4r(P.R2);
+                bool stale = false;  // P.R2 is an upper bound until refreshed
                 for (int i = 0; i < n; ++i) {
                     const uint32_t key = (i < 64) ? readlane_u32(k0, i) : readlane_u32(k1, i - 64);
-                    if ((key >> 8) > Q4R) break;
+                    if ((key >> 8) > Q4R) {
+                        if (!stale) break;
+                        P.update_r2();
+                        Q4R = q4r(P.R2);
+                        stale = false;
+                        if ((key >> 8) > Q4R) break;
+                    }
                     const int slot = (int)(key & 0xFFu);
                     ++ntested;
                     P4<double> p64;
@@ -438,7 +494,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
                     const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
                     if (rc == CLIP_CUT) {
-                        Q4R = q4r(P.R2);
+                        stale = true;
                     } else if (rc == CLIP_OVERFLOW) {
                         overflow = true;
                         break;
@@ -447,6 +503,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                         break;
                     }
                 }
+                if (stale) P.update_r2();
                 // particles the security criterion had to examine in this shell
                 int cntp = 0;
                 for (int b2 = lane; b2 < n; b2 += 64) {
@@ -544,7 +601,12 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 return nx;
             };
             const double *v0 = S.u.f.vp[i0];
-            double Sx = 0, Sy = 0, Sz = 0, Cx = 0, Cy = 0, Cz = 0, at = 0, vf = 0;
+            // fan triangles are counter-clockwise seen from outside: their areas are
+            // half the component of the cross product along the face's unit normal
+            const P4<double> &pf = S.P.pl64[f];
+            const double inn = 1.0 / sqrt(pf.x * pf.x + pf.y * pf.y + pf.z * pf.z);
+            const double ux = pf.x * inn, uy = pf.y * inn, uz = pf.z * inn;
+            double Cx = 0, Cy = 0, Cz = 0, at = 0, vf = 0;
             int prev = next_of(i0);
             int guard = 0;
             while (prev >= 0 && guard < VMAX) {
@@ -554,10 +616,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 double ax = v1[0] - v0[0], ay = v1[1] - v0[1], az = v1[2] - v0[2];
                 double bx = v2[0] - v0[0], by = v2[1] - v0[1], bz = v2[2] - v0[2];
                 double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
-                Sx += cx;
-                Sy += cy;
-                Sz += cz;
-                double ta = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+                double ta = 0.5 * (cx * ux + cy * uy + cz * uz);
                 Cx += ta * (v0[0] + v1[0] + v2[0]) / 3.0;
                 Cy += ta * (v0[1] + v1[1] + v2[1]) / 3.0;
                 Cz += ta * (v0[2] + v1[2] + v2[2]) / 3.0;
@@ -567,7 +626,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 prev = cur;
                 ++guard;
             }
-            double A_ = 0.5 * sqrt(Sx * Sx + Sy * Sy + Sz * Sz);
+            double A_ = at;
             area_l[r] = A_;
             vol_l += vf;
             S.u.f.fa[f] = A_;
@@ -577,7 +636,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
         }
         const double V = wave_sum_d(vol_l);
         const double Rfin = sqrt(wave_max(r2max));
-        const double amin = (double)A.area_eps * pow(fabs(V), 2.0 / 3.0);
+        const double amin = (double)(A.area_eps * exp2f(log2f((float)fabs(V)) * (2.0f / 3.0f)));
         // facets of positive area generated by particles -> neighbour rows, ascending global id
         uint64_t keys[VPL];
         bool wall = false;

@@ -1,19 +1,44 @@
 // grid.hip -- average Voronoi density on a regular grid (paper section 2,
-// optional grid output; also its discussion section).  The paper does not give
-// the averaging rule; this is the exact volume average of the
-// piecewise-constant field over each voxel:
+// optional grid output).  The paper does not state the averaging rule; this is
+// the exact volume average of the piecewise-constant Voronoi field:
 //   grid[v] = sum_i value_i * vol(cell_i ∩ voxel_v) / vol(voxel_v).
-// One wavefront per cell: the cell is rebuilt from its facets (the bisectors
-// of its neighbours, from the staging rows of the clip kernel), then clipped
-// by the six walls of every voxel its bounding box touches; each overlap volume
-// is added to the voxel with an FP64 atomic.  Cells inside one voxel add their
-// whole volume directly.
+//
+// Overlap volumes without 3D clipping.  For a voxel B = [X_i, X_i+1) x R_jk
+// (R_jk a rectangle of the (y, z) grid) the field F = (psi(x), 0, 0) with
+// psi(x) = clamp(x - X_i, 0, h_x) inside the column over R_jk has divergence 1_B,
+// so by the divergence theorem
+//   vol(P ∩ B) = sum over faces f of P of  n_x(f)/|n(f)| * ∫_{f over R_jk} psi dA.
+// Projected on the (y, z) plane a face f becomes a convex polygon Omega_f on
+// which x is affine, and n_x dA/|n| = sign(n_x) dy dz.  Writing
+// G(X) = ∫∫_{Omega ∩ R ∩ {x > X}} (x - X) dy dz, the face contributes
+// sign(n_x) (G(X_i) - G(X_i+1)) to voxel i of the column.  Each G is an area
+// integral over a convex polygon, evaluated with Green's theorem from three
+// families of boundary segments -- edges of Omega, edges of R, and the chord
+// x = X -- each clipped against the other two regions (Cyrus-Beck), so every
+// lane keeps O(1) state.  Work items (face, rectangle, plane) are spread over
+// the lanes of the wavefront that rebuilt the cell from its facets.
+//
+// The grid lines are evaluated at X_i + 1e-12 h (likewise in y and z): a
+// vertex or face exactly on a grid line (lattice inputs) then has no tie; the
+// overlap volumes move by at most 1e-12 of a voxel.
 #include "poly.h"
+
+#define GRID_ACC 1024  // voxels accumulated in LDS per cell
 
 template <int VPL>
 struct GridMem {
-    double vp[64 * VPL][3];
-    uint64_t fm_save[64 * VPL][VPL];
+    static constexpr int FMAX = 64 * VPL;      // face slots
+    static constexpr int LOOP = 3 * 64 * VPL;  // vertex-face incidences (3 per vertex)
+    double vp[64 * VPL][3];  // vertex positions, grid frame (box origin at 0)
+    uint32_t vt[64 * VPL];   // vertex triples
+    int16_t loop[LOOP];      // face vertex loops, counter-clockwise in (y, z)
+    int32_t loff[FMAX + 1];
+    double fn[FMAX][4];      // face plane in the grid frame: n.g = d
+    int32_t frect[FMAX][4];  // y range (j0, nj), z range (k0, nk)
+    int32_t fpl[FMAX][2];    // planes strictly inside the face's x range: m0, count
+    int32_t ipre[FMAX + 1];  // prefix of work items per face
+    int32_t fid[FMAX];       // compacted face slots
+    double acc[GRID_ACC];
     PolyMem<double, VPL> P;
 };
 
@@ -49,26 +74,127 @@ __device__ __forceinline__ int64_t wrapi(int64_t i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Green's theorem terms of a directed segment: area and first moments in (y, z)
+struct Mom {
+    double A, My, Mz;
+};
+
+__device__ __forceinline__ void seg_add(Mom &m, double y0, double z0, double y1, double z1) {
+    const double cr = y0 * z1 - y1 * z0;
+    m.A += 0.5 * cr;
+    m.My += cr * (y0 + y1) * (1.0 / 6.0);
+    m.Mz += cr * (z0 + z1) * (1.0 / 6.0);
+}
+
+// restrict the parameter interval [t0, t1] of a segment to g >= 0, g affine along it
+__device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, double &t1) {
+    if (g0 >= 0.0 && g1 >= 0.0) return;
+    if (g0 < 0.0 && g1 < 0.0) {
+        t0 = 1.0;
+        t1 = 0.0;
+        return;
+    }
+    const double t = g0 / (g0 - g1);
+    if (g0 < 0.0) t0 = fmax(t0, t);
+    else t1 = fmin(t1, t);
+}
+
+// Integrals of D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0):
+// Omega the counter-clockwise loop loop[o .. o+m) of seed-relative vertices vp,
+// R = [Y0, Y0 + hy] x [Z0, Z0 + hz], H = {hs (e - ny y - nz z) > 0} if useH, with
+// e given for the shifted coordinates.  Returns area and first moments (shifted).
+template <int VPL>
+__device__ Mom region_moments(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
+                              bool useH, double hs, double e, double ny, double nz) {
+    Mom M = {0.0, 0.0, 0.0};
+    auto gH = [&](double y, double z) { return hs * (e - ny * y - nz * z); };
+    auto vy = [&](int k) { return S.vp[S.loop[o + k]][1] - Y0; };
+    auto vz = [&](int k) { return S.vp[S.loop[o + k]][2] - Z0; };
+    // (a) edges of Omega inside R ∩ H
+    for (int k = 0; k < m; ++k) {
+        const int k1 = (k + 1 == m) ? 0 : k + 1;
+        const double y0 = vy(k), z0 = vz(k), y1 = vy(k1), z1 = vz(k1);
+        double t0 = 0.0, t1 = 1.0;
+        cyrus_beck(y0, y1, t0, t1);
+        cyrus_beck(hy - y0, hy - y1, t0, t1);
+        cyrus_beck(z0, z1, t0, t1);
+        cyrus_beck(hz - z0, hz - z1, t0, t1);
+        if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
+        if (t0 < t1) {
+            const double dy = y1 - y0, dz = z1 - z0;
+            seg_add(M, y0 + t0 * dy, z0 + t0 * dz, y0 + t1 * dy, z0 + t1 * dz);
+        }
+    }
+    // (b) edges of R inside Omega ∩ H
+    const double ry[5] = {0.0, hy, hy, 0.0, 0.0}, rz[5] = {0.0, 0.0, hz, hz, 0.0};
+    for (int r = 0; r < 4; ++r) {
+        const double qy0 = ry[r], qz0 = rz[r], qy1 = ry[r + 1], qz1 = rz[r + 1];
+        double t0 = 0.0, t1 = 1.0;
+        for (int k = 0; k < m && t0 < t1; ++k) {
+            const int k1 = (k + 1 == m) ? 0 : k + 1;
+            const double py = vy(k), pz = vz(k);
+            const double du = vy(k1) - py, dv = vz(k1) - pz;
+            cyrus_beck(du * (qz0 - pz) - dv * (qy0 - py), du * (qz1 - pz) - dv * (qy1 - py), t0, t1);
+        }
+        if (useH) cyrus_beck(gH(qy0, qz0), gH(qy1, qz1), t0, t1);
+        if (t0 < t1) {
+            const double dy = qy1 - qy0, dz = qz1 - qz0;
+            seg_add(M, qy0 + t0 * dy, qz0 + t0 * dz, qy0 + t1 * dy, qz0 + t1 * dz);
+        }
+    }
+    // (c) the chord of H's boundary inside Omega ∩ R, directed with H on its left
+    if (useH) {
+        const double nn = ny * ny + nz * nz;
+        const double cy = 0.5 * hy, cz = 0.5 * hz;
+        const double sft = (ny * cy + nz * cz - e) / nn;
+        const double py = cy - sft * ny, pz = cz - sft * nz;  // point of the line nearest R's centre
+        const double L = 4.0 * (hy + hz) / sqrt(nn);
+        const double dy = -hs * nz * L, dz = hs * ny * L;      // direction with H on the left
+        const double qy0 = py - dy, qz0 = pz - dz, qy1 = py + dy, qz1 = pz + dz;
+        double t0 = 0.0, t1 = 1.0;
+        cyrus_beck(qy0, qy1, t0, t1);
+        cyrus_beck(hy - qy0, hy - qy1, t0, t1);
+        cyrus_beck(qz0, qz1, t0, t1);
+        cyrus_beck(hz - qz0, hz - qz1, t0, t1);
+        for (int k = 0; k < m && t0 < t1; ++k) {
+            const int k1 = (k + 1 == m) ? 0 : k + 1;
+            const double vy0 = vy(k), vz0 = vz(k);
+            const double du = vy(k1) - vy0, dv = vz(k1) - vz0;
+            cyrus_beck(du * (qz0 - vz0) - dv * (qy0 - vy0), du * (qz1 - vz0) - dv * (qy1 - vy0), t0, t1);
+        }
+        if (t0 < t1) {
+            const double ey = qy1 - qy0, ez = qz1 - qz0;
+            seg_add(M, qy0 + t0 * ey, qz0 + t0 * ez, qy0 + t1 * ey, qz0 + t1 * ez);
+        }
+    }
+    return M;
+}
+
 template <typename PT4, int VPL, bool RETRY>
-__global__ void __launch_bounds__(256) k_grid(GridArgs A) {
+__global__ void __launch_bounds__(128) k_grid(GridArgs A) {
     using M = GridMem<VPL>;
     extern __shared__ char smem[];
     const int wid = threadIdx.x >> 6;
     M &S = *reinterpret_cast<M *>(smem + (size_t)wid * sizeof(M));
     const int lane = lane_id();
     const uint64_t mybit = 1ull << lane;
+    const uint64_t lt = lanemask_lt();
     const DevItem &it = A.items[0];
     const double h[3] = {it.L[0] / A.nx, it.L[1] / A.ny, it.L[2] / A.nz};
+    const double ih[3] = {1.0 / h[0], 1.0 / h[1], 1.0 / h[2]};
+    const double del[3] = {1e-12 * h[0], 1e-12 * h[1], 1e-12 * h[2]};  // grid-line offset
     const double hv = h[0] * h[1] * h[2];
     const int dims[3] = {A.nx, A.ny, A.nz};
     const int64_t ntodo = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : A.ncells;
+    for (int k = lane; k < GRID_ACC; k += 64) S.acc[k] = 0.0;
+    wave_sync();
 
     for (;;) {
         int64_t w = 0;
         if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_GRID_RETRY : CTR_GRID], 1u);
-        w = (int64_t)__shfl((long long)w, 0);
+        w = (int64_t)uni_i((int)__shfl((long long)w, 0));
         if (w >= ntodo) break;
-        const int32_t c = RETRY ? A.queue[w] : (int32_t)w;
+        const int32_t c = uni_i(RETRY ? A.queue[w] : (int32_t)w);
         const uint8_t st = A.cstat[c];
         if (!RETRY && (st & VT_CELL_RETRIED)) continue;
         if (st & VT_CELL_FAILED) continue;
@@ -88,6 +214,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 bhi[a] = it.lo[a] + it.L[a] - xs[a];
             }
         }
+        // ---- rebuild the cell from its facets
         Poly<double, VPL> P;
         P.init_box(S.P, blo, bhi);
         bool bad = false;
@@ -107,8 +234,9 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 p.z -= it.L[2] * rint(p.z / it.L[2]);
             }
             p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
-            int rc = P.clip(S.P, p, j);
+            const int rc = P.clip(S.P, p, j);
             if (rc < 0) {
+                if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
                 bad = true;
                 break;
             }
@@ -117,28 +245,28 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
             continue;
         }
-        // bounding box of the cell -> voxel index ranges
+        // ---- vertices in the grid frame, bounding box, voxel ranges
         double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             if (P.alive[s] & mybit) {
                 const double v[3] = {P.vx[s], P.vy[s], P.vz[s]};
                 for (int a = 0; a < 3; ++a) {
+                    S.vp[s * 64 + lane][a] = v[a];
                     mn[a] = fmin(mn[a], v[a]);
                     mx[a] = fmax(mx[a], v[a]);
                 }
+                S.vt[s * 64 + lane] = P.vt[s];
             }
         }
+        // seed position in the grid frame; grid line m of axis a lies at m h + del - g0 from the seed
+        const double g0[3] = {xs[0] - it.lo[0], xs[1] - it.lo[1], xs[2] - it.lo[2]};
         int64_t i0[3], i1[3];
         for (int a = 0; a < 3; ++a) {
-            mn[a] = wave_min(mn[a]);
-            mx[a] = wave_max(mx[a]);
-            i0[a] = (int64_t)floor((xs[a] + mn[a] - it.lo[a]) / h[a]);
-            i1[a] = (int64_t)floor((xs[a] + mx[a] - it.lo[a]) / h[a]);
-            if (!it.periodic) {
-                if (i0[a] < 0) i0[a] = 0;
-                if (i1[a] > dims[a] - 1) i1[a] = dims[a] - 1;
-            }
+            mn[a] = uni_d(wave_min(mn[a]));
+            mx[a] = uni_d(wave_max(mx[a]));
+            i0[a] = (int64_t)floor((g0[a] + mn[a] - del[a]) * ih[a]);
+            i1[a] = (int64_t)floor((g0[a] + mx[a] - del[a]) * ih[a]);
         }
         if (i0[0] == i1[0] && i0[1] == i1[1] && i0[2] == i1[2]) {
             if (lane == 0) {
@@ -147,51 +275,198 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             }
             continue;
         }
-        // save the cell; every voxel starts from it
-        const Poly<double, VPL> P0 = P;
+        const int ni = (int)(i1[0] - i0[0] + 1), nj = (int)(i1[1] - i0[1] + 1), nk = (int)(i1[2] - i0[2] + 1);
+        const bool in_lds = (int64_t)ni * nj * nk <= GRID_ACC;
+        // ---- faces: compact the alive ones
+        int nf = 0;
 #pragma unroll
-        for (int r = 0; r < VPL; ++r)
-#pragma unroll
-            for (int ww = 0; ww < VPL; ++ww) S.fm_save[r * 64 + lane][ww] = S.P.fm[r * 64 + lane][ww];
+        for (int r = 0; r < VPL; ++r) {
+            const uint64_t m = P.fa[r];
+            if (m & mybit) S.fid[nf + __popcll(m & lt)] = r * 64 + lane;
+            nf += __popcll(m);
+        }
         wave_sync();
-        for (int64_t ix = i0[0]; ix <= i1[0]; ++ix)
-            for (int64_t iy = i0[1]; iy <= i1[1]; ++iy)
-                for (int64_t iz = i0[2]; iz <= i1[2]; ++iz) {
-                    P = P0;
+        // the vertex after u on face f, counter-clockwise seen from outside
+        auto next_on = [&](int f, const uint64_t *mf, int u) -> int {
+            const uint32_t t = S.vt[u];
+            const int t0 = t & 0xFF, t1 = (t >> 8) & 0xFF, t2 = (t >> 16) & 0xFF;
+            const int cf = (t0 == f) ? t2 : (t1 == f) ? t0 : t1;
+            int nx_ = -1;
 #pragma unroll
-                    for (int r = 0; r < VPL; ++r)
+            for (int ww = 0; ww < VPL; ++ww) {
+                uint64_t x = mf[ww] & S.P.fm[cf][ww];
+                if (ww == (u >> 6)) x &= ~(1ull << (u & 63));
+                if (nx_ < 0 && x) nx_ = ww * 64 + __builtin_ctzll(x);
+            }
+            return nx_;
+        };
+        // loop lengths and planes in the grid frame
+        int carry = 0;
+        for (int base = 0; base < nf; base += 64) {
+            const int q = base + lane;
+            int len = 0;
+            if (q < nf) {
+                const int f = S.fid[q];
+                uint64_t mf[VPL];
+                int u0 = -1;
 #pragma unroll
-                        for (int ww = 0; ww < VPL; ++ww) S.P.fm[r * 64 + lane][ww] = S.fm_save[r * 64 + lane][ww];
-                    wave_sync();
-                    const int64_t idx[3] = {ix, iy, iz};
-                    bool empty = false;
-                    for (int a = 0; a < 3 && !empty; ++a) {
-                        const double vlo = it.lo[a] + idx[a] * h[a] - xs[a];
-                        const double vhi = vlo + h[a];
-                        for (int sg = 0; sg < 2 && !empty; ++sg) {
-                            P4<double> p;
-                            p.x = p.y = p.z = 0.0;
-                            double nrm = sg ? 1.0 : -1.0;
-                            if (a == 0) p.x = nrm;
-                            if (a == 1) p.y = nrm;
-                            if (a == 2) p.z = nrm;
-                            p.d = sg ? vhi : -vlo;
-                            int rc = P.clip(S.P, p, -100);
-                            if (rc == CLIP_EMPTY) empty = true;
-                            else if (rc < 0) {
-                                empty = true;
-                                if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
-                            }
-                        }
-                    }
-                    if (empty) continue;
-                    const double vol = P.volume(S.P, S.vp);
-                    if (lane == 0 && vol > 0.0) {
-                        int64_t g = (wrapi(ix, dims[0]) * dims[1] + wrapi(iy, dims[1])) * dims[2] + wrapi(iz, dims[2]);
-                        unsafeAtomicAdd(&A.grid[g], val * vol / hv);
-                    }
-                    wave_sync();
+                for (int ww = 0; ww < VPL; ++ww) {
+                    mf[ww] = S.P.fm[f][ww];
+                    if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
                 }
+                int u = u0;
+                do {
+                    ++len;
+                    u = next_on(f, mf, u);
+                } while (u >= 0 && u != u0 && len < 64 * VPL);
+                const P4<double> &pf = S.P.pl64[f];
+                S.fn[q][0] = pf.x;
+                S.fn[q][1] = pf.y;
+                S.fn[q][2] = pf.z;
+                S.fn[q][3] = pf.d;  // seed-relative plane n.v = d
+            }
+            int tot;
+            const int pre = wave_excl_scan(len, &tot);
+            if (q < nf) S.loff[q] = carry + pre;
+            carry += tot;
+        }
+        if (lane == 0) S.loff[nf] = carry;
+        wave_sync();
+        if (carry > M::LOOP) {
+            if (lane == 0) {
+                atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                atomicOr(&A.counters[CTR_DEBUG], 1u << 16);
+            }
+            continue;
+        }
+        // loops, counter-clockwise in the (y, z) projection (faces seen from -x are reversed);
+        // extents and work items: rectangles x (1 + planes strictly inside the face's x range)
+        int nitem = 0;
+        for (int base = 0; base < nf; base += 64) {
+            const int q = base + lane;
+            int items = 0;
+            if (q < nf) {
+                const int f = S.fid[q];
+                uint64_t mf[VPL];
+                int u0 = -1;
+#pragma unroll
+                for (int ww = 0; ww < VPL; ++ww) {
+                    mf[ww] = S.P.fm[f][ww];
+                    if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
+                }
+                const int o = S.loff[q], m = S.loff[q + 1] - o;
+                const bool rev = S.fn[q][0] < 0.0;
+                double b[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
+                int u = u0;
+                for (int k = 0; k < m && u >= 0; ++k) {
+                    S.loop[o + (rev ? m - 1 - k : k)] = (int16_t)u;
+                    const double *p = S.vp[u];
+                    for (int a = 0; a < 3; ++a) {
+                        b[2 * a] = fmin(b[2 * a], p[a]);
+                        b[2 * a + 1] = fmax(b[2 * a + 1], p[a]);
+                    }
+                    u = next_on(f, mf, u);
+                }
+                const double nlen = sqrt(S.fn[q][0] * S.fn[q][0] + S.fn[q][1] * S.fn[q][1] + S.fn[q][2] * S.fn[q][2]);
+                // faces parallel to x add nothing (n_x = 0); nearly parallel ones are bounded by 1e-12 of a voxel
+                if (fabs(S.fn[q][0]) > 1e-12 * nlen) {
+                    const int64_t ja = (int64_t)floor((g0[1] + b[2] - del[1]) * ih[1]);
+                    const int64_t jb = (int64_t)floor((g0[1] + b[3] - del[1]) * ih[1]);
+                    const int64_t ka = (int64_t)floor((g0[2] + b[4] - del[2]) * ih[2]);
+                    const int64_t kb = (int64_t)floor((g0[2] + b[5] - del[2]) * ih[2]);
+                    // planes X_m = m h + del with xmin < X_m < xmax (grid frame)
+                    const int64_t m0 = (int64_t)floor((g0[0] + b[0] - del[0]) * ih[0]) + 1;
+                    const int64_t m1 = (int64_t)ceil((g0[0] + b[1] - del[0]) * ih[0]);
+                    S.frect[q][0] = (int)ja;
+                    S.frect[q][1] = (int)(jb - ja + 1);
+                    S.frect[q][2] = (int)ka;
+                    S.frect[q][3] = (int)(kb - ka + 1);
+                    S.fpl[q][0] = (int)m0;
+                    S.fpl[q][1] = (int)(m1 > m0 ? m1 - m0 : 0);
+                    items = S.frect[q][1] * S.frect[q][3] * (1 + S.fpl[q][1]);
+                }
+            }
+            int tot;
+            const int pre = wave_excl_scan(items, &tot);
+            if (q < nf) S.ipre[q] = nitem + pre;
+            nitem += tot;
+        }
+        if (lane == 0) S.ipre[nf] = nitem;
+        wave_sync();
+        nitem = uni_i(nitem);
+        // ---- work items
+        auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
+            if (v == 0.0) return;
+            if (in_lds) {
+                atomicAdd(&S.acc[(i - i0[0]) + ni * ((j - i0[1]) + (int64_t)nj * (k - i0[2]))], v);
+            } else {
+                int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(k, dims[2]);
+                unsafeAtomicAdd(&A.grid[g], val * v / hv);
+            }
+        };
+        for (int base = 0; base < nitem; base += 64) {
+            const int item = base + lane;
+            if (item < nitem) {
+                int lo = 0, hi = nf - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
+                }
+                const int q = lo;
+                int r = item - S.ipre[q];
+                const int nplane = 1 + S.fpl[q][1];
+                const int pi = r % nplane;
+                r /= nplane;
+                const int64_t jj = S.frect[q][0] + (r % S.frect[q][1]);
+                const int64_t kk = S.frect[q][2] + (r / S.frect[q][1]);
+                // rectangle corner (seed-relative); integrals are taken relative to it
+                const double Y0 = jj * h[1] + del[1] - g0[1];
+                const double Z0 = kk * h[2] + del[2] - g0[2];
+                const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2], dg = S.fn[q][3];
+                const double hs = nx_ > 0.0 ? 1.0 : -1.0, inx = 1.0 / fabs(nx_);
+                const int o = S.loff[q], m = S.loff[q + 1] - o;
+                const int64_t m0 = S.fpl[q][0];
+                // on the face x = (d - ny y - nz z) / nx; with y, z relative to the corner the
+                // constant becomes e = d - nx X - ny Y0 - nz Z0
+                if (pi == 0) {
+                    // the face over this rectangle: full voxels below it, and the voxel holding its x minimum
+                    const Mom M0 = region_moments<VPL>(S, o, m, Y0, Z0, h[1], h[2], false, hs, 0.0, ny_, nz_);
+                    if (M0.A != 0.0) {
+                        for (int64_t i = i0[0]; i <= m0 - 2; ++i) emit(i, jj, kk, hs * h[0] * M0.A);
+                        const double X = (m0 - 1) * h[0] + del[0] - g0[0];
+                        const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
+                        emit(m0 - 1, jj, kk, (e * M0.A - ny_ * M0.My - nz_ * M0.Mz) * inx);
+                    }
+                } else {
+                    // G at the plane X_m inside the face's x range: -G to voxel m-1, +G to voxel m
+                    const int64_t mm = m0 + pi - 1;
+                    const double X = mm * h[0] + del[0] - g0[0];
+                    const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
+                    const bool useH = !(ny_ == 0.0 && nz_ == 0.0);
+                    const Mom M1 = region_moments<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_);
+                    if (useH || hs * e > 0.0) {
+                        const double G = (e * M1.A - ny_ * M1.My - nz_ * M1.Mz) * inx;
+                        emit(mm - 1, jj, kk, -G);
+                        emit(mm, jj, kk, G);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        // ---- flush the cell's voxels
+        if (in_lds) {
+            const int nv = ni * nj * nk;
+            for (int k = lane; k < nv; k += 64) {
+                const double v = S.acc[k];
+                if (v != 0.0) {
+                    const int64_t i = i0[0] + k % ni, j = i0[1] + (k / ni) % nj, kz = i0[2] + k / (ni * nj);
+                    int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(kz, dims[2]);
+                    unsafeAtomicAdd(&A.grid[g], val * v / hv);
+                    S.acc[k] = 0.0;
+                }
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -217,7 +492,6 @@ static hipError_t launch_grid_one(vt_ctx *c, GridArgs &a, int wpb) {
 hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz, double *grid) {
     const int64_t ng = (int64_t)nx * ny * nz;
     k_zero_f64<<<(ng + 255) / 256, 256, 0, c->stream>>>(grid, ng);
-    // work counters of the two deposit kernels
     hipError_t ez = vt_launch_zero_u32(c->counters + CTR_GRID, 2, c->stream);
     if (ez != hipSuccess) return ez;
     GridArgs a;
@@ -241,10 +515,10 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.nz = nz;
     hipError_t e;
     if (c->dtype == VT_F32) {
-        e = launch_grid_one<float4, 2, false>(c, a, 4);
+        e = launch_grid_one<float4, 2, false>(c, a, 2);
         if (e == hipSuccess) e = launch_grid_one<float4, 4, true>(c, a, 1);
     } else {
-        e = launch_grid_one<double4, 2, false>(c, a, 4);
+        e = launch_grid_one<double4, 2, false>(c, a, 2);
         if (e == hipSuccess) e = launch_grid_one<double4, 4, true>(c, a, 1);
     }
     return e;

@@ -44,6 +44,15 @@ __device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
 }
 
+// values that are equal in every lane, moved to scalar registers
+__device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni_d(double x) {
+    long long b = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
     for (int o = 32; o > 0; o >>= 1) {
@@ -307,7 +316,7 @@ struct Poly {
                 r2l = fmax(r2l, d);
             }
         }
-        R2 = wave_max(r2l) * (1.0 + 1e-12);
+        R2 = uni_d(wave_max(r2l) * (1.0 + 1e-12));
     }
 
     // Clip by {y : p.y <= p.d} (p64 in FP64); `tag` identifies the plane.
@@ -416,35 +425,41 @@ struct Poly {
             }
             S.ptag[q] = tag;
         }
-        // 4. new vertex positions -> staging
+        // 4. cut edges -> staging triples (a, b, p) in rank order, then one new
+        //    vertex per lane: the intersection of its three planes
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             if (emask[s]) {
                 const uint32_t t = vt[s];
                 const int fx[3] = {(int)(t & 0xFF), (int)((t >> 8) & 0xFF), (int)((t >> 16) & 0xFF)};
                 int k = pre_s[s];
-                for (int e = 0; e < 3; ++e) {
-                    if (!(emask[s] & (1u << e))) continue;
-                    const int fa_ = fx[e], fb_ = fx[(e + 1) % 3];
-                    T wx, wy, wz;
-                    if constexpr (MIXED) {
-                        P4<float> pa = S.pl32[fa_], pb = S.pl32[fb_];
-                        float det = intersect3<float>(pa, pb, p, wx, wy, wz);
-                        float kap = S.pln[fa_] * S.pln[fb_] * pnorm / fabsf(det);
-                        float wn = sqrtf(wx * wx + wy * wy + wz * wz);
-                        float err = 16.f * U32 * (kap * (S.plh[fa_] + S.plh[fb_] + ph + wn) + wn);
-                        if (!(err < 1e30f)) err = 1e30f;
-                        S.ste[k] = err;
-                    } else {
-                        P4<double> pa = S.pl64[fa_], pb = S.pl64[fb_];
-                        intersect3<double>(pa, pb, p64, wx, wy, wz);
-                    }
-                    S.st[k][0] = wx;
-                    S.st[k][1] = wy;
-                    S.st[k][2] = wz;
-                    S.stt[k] = (uint32_t)fa_ | ((uint32_t)fb_ << 8) | ((uint32_t)q << 16);
-                    ++k;
+                for (int e = 0; e < 3; ++e)
+                    if (emask[s] & (1u << e))
+                        S.stt[k++] = (uint32_t)fx[e] | ((uint32_t)fx[(e + 1) % 3] << 8) | ((uint32_t)q << 16);
+            }
+        }
+        wave_sync();
+        for (int r0 = 0; r0 < NB; r0 += 64) {
+            const int k = r0 + lane;
+            if (k < NB) {
+                const uint32_t t = S.stt[k];
+                const int fa_ = t & 0xFF, fb_ = (t >> 8) & 0xFF;
+                T wx, wy, wz;
+                if constexpr (MIXED) {
+                    P4<float> pa = S.pl32[fa_], pb = S.pl32[fb_];
+                    float det = intersect3<float>(pa, pb, p, wx, wy, wz);
+                    float kap = S.pln[fa_] * S.pln[fb_] * pnorm / fabsf(det);
+                    float wn = sqrtf(wx * wx + wy * wy + wz * wz);
+                    float err = 16.f * U32 * (kap * (S.plh[fa_] + S.plh[fb_] + ph + wn) + wn);
+                    if (!(err < 1e30f)) err = 1e30f;
+                    S.ste[k] = err;
+                } else {
+                    P4<double> pa = S.pl64[fa_], pb = S.pl64[fb_];
+                    intersect3<double>(pa, pb, p64, wx, wy, wz);
                 }
+                S.st[k][0] = wx;
+                S.st[k][1] = wy;
+                S.st[k][2] = wz;
             }
         }
         wave_sync();
@@ -489,7 +504,8 @@ struct Poly {
             for (int ww = 0; ww < VPL; ++ww) al |= S.fm[f][ww] != 0ull;
             fa[r] = __ballot(al);
         }
-        update_r2();
+        // R2 is left as it was: an upper bound (the cell only shrinks); callers
+        // refresh it with update_r2() when they need the tighter value
         return CLIP_CUT;
     }
 

@@ -317,6 +317,8 @@ vt_status vt_query(vt_ctx *c, int64_t *nnz, int64_t *n_retried, int64_t *n_incom
     if (n_retried) *n_retried = h[CTR_QUEUE];
     if (n_incomplete) *n_incomplete = h[CTR_INCOMPLETE];
     uint32_t st = h[CTR_STATUS];
+    if (getenv("VT_DEBUG") && (st || h[CTR_DEBUG]))
+        fprintf(stderr, "libvt: device status 0x%x, debug 0x%x, queue %u\n", st, h[CTR_DEBUG], h[CTR_QUEUE]);
     if (st & VT_DEV_DUPLICATE) return VT_ERR_DUPLICATE;  // the root cause of any later failure
     if (st & VT_DEV_TOPOLOGY) return VT_ERR_TOPOLOGY;
     if (st & VT_DEV_BOX_TOO_SMALL) return VT_ERR_BOX_TOO_SMALL;

@@ -30,6 +30,7 @@
 #define CTR_INCOMPLETE 6
 #define CTR_GRID 7        // grid deposit work counters (two words)
 #define CTR_GRID_RETRY 8
+#define CTR_DEBUG 9        // bit k set: a clip in the grid kernel returned -k (diagnostics)
 #define CTR_COUNT 12
 
 // per-item description on the device

@@ -164,3 +164,119 @@ def test_large_cell_uses_big_kernel(vt, torch_cuda, oracle):
     ref = oracle.cells(p, 0.0, 1.0, query=rows, stride=256)
     compare_rows(cells, ref, rows, 1e-12, "bigcell")
     assert (cells.status.cpu().numpy()[0] & 2) != 0
+
+
+# ---------------------------------------------------------------- derived outputs
+def test_gradient_matches_oracle(vt, torch_cuda, oracle):
+    w = wl.workload1()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
+    cells = ctx.vt_cells()
+    rng = np.random.default_rng(4)
+    m = rng.uniform(0.5, 2.0, w.n)
+    rho = ctx.vt_density(torch_cuda.from_numpy(m).cuda())
+    grad = ctx.vt_gradient(rho).cpu().numpy()
+    ref = oracle.cells(w.pos, w.box_lo, w.box_hi)
+    off, ids = ref.csr()
+    rho_ref = oracle.density(m, ref.volume)
+    gref = oracle.gradient(w.pos, w.box_lo, w.box_hi, True, off, ids, rho_ref)
+    scale = np.maximum(np.linalg.norm(gref, axis=1), rho_ref / ref.volume ** (1.0 / 3.0))
+    err = np.linalg.norm(grad - gref, axis=1) / scale
+    assert err.max() < 1e-10, err.max()
+
+
+def test_gradient_linear_field_bounded(vt, torch_cuda):
+    rng = np.random.default_rng(9)
+    p = rng.random((5000, 3))
+    t = torch_cuda.from_numpy(p).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(len(p), 0.0, 1.0, periodic=False))
+    ctx.vt_cells()
+    g = np.array([0.7, -1.3, 2.1])
+    rho = torch_cuda.from_numpy(5.0 + p @ g).cuda()
+    grad = ctx.vt_gradient(rho).cpu().numpy()
+    np.testing.assert_allclose(grad, np.broadcast_to(g, grad.shape), atol=1e-9)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (32, 24, 20)])
+def test_grid_matches_oracle(vt, torch_cuda, oracle, dims):
+    w = wl.workload1()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
+    ctx.vt_cells()
+    rng = np.random.default_rng(6)
+    m = rng.uniform(0.5, 2.0, w.n)
+    rho = ctx.vt_density(torch_cuda.from_numpy(m).cuda())
+    g = ctx.vt_grid_deposit(rho, dims).cpu().numpy()
+    code = ctx.vt_query()[0]
+    assert code == 0
+    ref_cells = oracle.cells(w.pos, w.box_lo, w.box_hi)
+    gref = oracle.grid(w.pos, 0.0, 1.0, True, oracle.density(m, ref_cells.volume), dims)
+    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    assert abs(g.sum() / np.prod(dims) - m.sum()) <= 1e-12 * m.sum()
+
+
+def test_grid_unit_field_and_aligned_lattice(vt, torch_cuda):
+    w = wl.workload1()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
+    ctx.vt_cells()
+    g = ctx.vt_grid_deposit(torch_cuda.ones(w.n, dtype=torch_cuda.float64, device="cuda"), (20, 20, 20))
+    np.testing.assert_allclose(g.cpu().numpy(), 1.0, atol=1e-12)
+    nv = 8
+    h = 1.0 / nv
+    k = np.arange(nv // 2) * 2 * h
+    p = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    val = np.random.default_rng(4).uniform(1.0, 3.0, len(p))
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(p).cuda(), vt.whole_box(len(p), 0.0, 1.0))
+    ctx.vt_cells()
+    g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), (nv, nv, nv)).cpu().numpy()
+    for idx, v in enumerate(val):
+        a, b, c = np.rint(p[idx] / h).astype(int)
+        for da in (-1, 0):
+            for db in (-1, 0):
+                for dc in (-1, 0):
+                    assert abs(g[(a + da) % nv, (b + db) % nv, (c + dc) % nv] - v) < 1e-11 * v
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_backward_matches_oracle_adjoint(vt, torch_cuda, oracle, precision):
+    w = wl.workload1()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision, want_faces=True)
+    ctx.vt_cells()
+    g = np.random.default_rng(7).normal(size=w.n)
+    dx = ctx.vt_backward(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
+    ref = oracle.cells(w.pos, w.box_lo, w.box_hi)
+    dref = oracle.adjoint(ref, g)
+    scale = np.abs(dref).max()
+    assert np.abs(dx - dref).max() <= 1e-10 * scale
+
+
+def test_backward_requires_faces(vt, torch_cuda):
+    w = wl.workload1()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), want_faces=False)
+    with pytest.raises(vt.VTError) as e:
+        ctx.vt_backward(torch_cuda.zeros(w.n, dtype=torch_cuda.float64, device="cuda"))
+    assert e.value.code == 7
+
+
+def test_autograd_volume_fd(vt, torch_cuda, oracle):
+    """d(sum g V)/dx through torch.autograd vs central differences of the oracle's volumes."""
+    rng = np.random.default_rng(21)
+    n = 600
+    p = rng.random((n, 3))
+    x = torch_cuda.from_numpy(p).cuda().requires_grad_(True)
+    V = vt.voronoi_volume(x, 0.0, 1.0)
+    g = torch_cuda.from_numpy(rng.normal(size=n)).cuda()
+    (V * g).sum().backward()
+    grad = x.grad.cpu().numpy()
+    gn = g.cpu().numpy()
+    h = 1e-6
+    for k in rng.choice(n, 5, replace=False):
+        for ax in range(3):
+            pp, pm = p.copy(), p.copy()
+            pp[k, ax] += h
+            pm[k, ax] -= h
+            fd = (gn * (oracle.cells(pp, 0.0, 1.0).volume - oracle.cells(pm, 0.0, 1.0).volume)).sum() / (2 * h)
+            assert abs(fd - grad[k, ax]) <= 1e-6 * max(abs(fd), 1e-3)
