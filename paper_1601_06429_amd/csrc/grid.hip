@@ -11,9 +11,9 @@
 // Projected on the (y, z) plane a face f becomes a convex polygon Omega_f on
 // which x is affine, and n_x dA/|n| = sign(n_x) dy dz.  Writing
 // G(X) = ∫∫_{Omega ∩ R ∩ {x > X}} (x - X) dy dz, the face contributes
-// sign(n_x) (G(X_i) - G(X_i+1)) to voxel i of the column.  Each G is an area
-// integral over a convex polygon, evaluated with Green's theorem from three
-// families of boundary segments -- edges of Omega, edges of R, and the chord
+// sign(n_x) (G(X_i) - G(X_i+1)) to voxel i of the column.  Each G is an
+// integral of an affine function over a convex polygon, taken over its boundary
+// from three families of segments -- edges of Omega, edges of R, and the chord
 // x = X -- each clipped against the other two regions (Cyrus-Beck), so every
 // lane keeps O(1) state.  Work items (face, rectangle, plane) are spread over
 // the lanes of the wavefront that rebuilt the cell from its facets.
@@ -74,17 +74,20 @@ __device__ __forceinline__ int64_t wrapi(int64_t i, int n) {
     return r < 0 ? r + n : r;
 }
 
-// Green's theorem terms of a directed segment: area and first moments in (y, z)
-struct Mom {
-    double A, My, Mz;
+// Area A of a region D in the (y, z) plane and G = ∫∫_D (x - X) dy dz, x the
+// affine height of the face over D.  Both come from the boundary of D by
+// Green's theorem, as a fan of triangles (O, p, q) over its directed boundary
+// segments (p, q) with O the face's first vertex: each triangle adds its signed
+// area times the mean of x - X at its corners.  Heights are taken from the
+// face's own 3D vertices where a point lies on a face edge (interpolated), are 0
+// on the chord x = X, and come from the plane equation only at points of R's
+// edges inside the projection.  A face nearly parallel to x projects to a thin
+// sliver on which the plane equation has a large slope; every point used lies
+// in the sliver and every triangle has at most its area, so the rounding error
+// stays at eps * (cell size)^3 instead of growing like 1/n_x.
+struct Reg {
+    double A, G;
 };
-
-__device__ __forceinline__ void seg_add(Mom &m, double y0, double z0, double y1, double z1) {
-    const double cr = y0 * z1 - y1 * z0;
-    m.A += 0.5 * cr;
-    m.My += cr * (y0 + y1) * (1.0 / 6.0);
-    m.Mz += cr * (z0 + z1) * (1.0 / 6.0);
-}
 
 // restrict the parameter interval [t0, t1] of a segment to g >= 0, g affine along it
 __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, double &t1) {
@@ -99,17 +102,26 @@ __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, dou
     else t1 = fmin(t1, t);
 }
 
-// Integrals of D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0):
-// Omega the counter-clockwise loop loop[o .. o+m) of seed-relative vertices vp,
-// R = [Y0, Y0 + hy] x [Z0, Z0 + hz], H = {hs (e - ny y - nz z) > 0} if useH, with
-// e given for the shifted coordinates.  Returns area and first moments (shifted).
+// D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0): Omega the
+// counter-clockwise loop loop[o .. o+m) of seed-relative vertices vp,
+// R = [Y0, Y0 + hy] x [Z0, Z0 + hz], H = {hs (e - ny y - nz z) > 0} if useH (the
+// part of the face above x = X), with e given for the shifted coordinates and
+// rnx = 1 / n_x.
 template <int VPL>
-__device__ Mom region_moments(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
-                              bool useH, double hs, double e, double ny, double nz) {
-    Mom M = {0.0, 0.0, 0.0};
+__device__ Reg region_integrals(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
+                                bool useH, double hs, double e, double ny, double nz, double X, double rnx) {
+    Reg D = {0.0, 0.0};
     auto gH = [&](double y, double z) { return hs * (e - ny * y - nz * z); };
     auto vy = [&](int k) { return S.vp[S.loop[o + k]][1] - Y0; };
     auto vz = [&](int k) { return S.vp[S.loop[o + k]][2] - Z0; };
+    auto vx = [&](int k) { return S.vp[S.loop[o + k]][0] - X; };
+    const double Oy = vy(0), Oz = vz(0), gO = vx(0);
+    auto tri = [&](double y0, double z0, double g0, double y1, double z1, double g1) {
+        const double cr = (y0 - Oy) * (z1 - Oz) - (y1 - Oy) * (z0 - Oz);
+        D.A += 0.5 * cr;
+        D.G += cr * (gO + g0 + g1) * (1.0 / 6.0);
+    };
+    auto gplane = [&](double y, double z) { return gO - (ny * (y - Oy) + nz * (z - Oz)) * rnx; };
     // (a) edges of Omega inside R ∩ H
     for (int k = 0; k < m; ++k) {
         const int k1 = (k + 1 == m) ? 0 : k + 1;
@@ -121,8 +133,8 @@ __device__ Mom region_moments(const GridMem<VPL> &S, int o, int m, double Y0, do
         cyrus_beck(hz - z0, hz - z1, t0, t1);
         if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
         if (t0 < t1) {
-            const double dy = y1 - y0, dz = z1 - z0;
-            seg_add(M, y0 + t0 * dy, z0 + t0 * dz, y0 + t1 * dy, z0 + t1 * dz);
+            const double dy = y1 - y0, dz = z1 - z0, xa = vx(k), dx = vx(k1) - xa;
+            tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
         }
     }
     // (b) edges of R inside Omega ∩ H
@@ -139,10 +151,11 @@ __device__ Mom region_moments(const GridMem<VPL> &S, int o, int m, double Y0, do
         if (useH) cyrus_beck(gH(qy0, qz0), gH(qy1, qz1), t0, t1);
         if (t0 < t1) {
             const double dy = qy1 - qy0, dz = qz1 - qz0;
-            seg_add(M, qy0 + t0 * dy, qz0 + t0 * dz, qy0 + t1 * dy, qz0 + t1 * dz);
+            const double ya = qy0 + t0 * dy, za = qz0 + t0 * dz, yb = qy0 + t1 * dy, zb = qz0 + t1 * dz;
+            tri(ya, za, gplane(ya, za), yb, zb, gplane(yb, zb));
         }
     }
-    // (c) the chord of H's boundary inside Omega ∩ R, directed with H on its left
+    // (c) the chord x = X inside Omega ∩ R, directed with H on its left (x - X = 0 on it)
     if (useH) {
         const double nn = ny * ny + nz * nz;
         const double cy = 0.5 * hy, cz = 0.5 * hz;
@@ -164,10 +177,10 @@ __device__ Mom region_moments(const GridMem<VPL> &S, int o, int m, double Y0, do
         }
         if (t0 < t1) {
             const double ey = qy1 - qy0, ez = qz1 - qz0;
-            seg_add(M, qy0 + t0 * ey, qz0 + t0 * ez, qy0 + t1 * ey, qz0 + t1 * ez);
+            tri(qy0 + t0 * ey, qz0 + t0 * ez, 0.0, qy0 + t1 * ey, qz0 + t1 * ez, 0.0);
         }
     }
-    return M;
+    return D;
 }
 
 template <typename PT4, int VPL, bool RETRY>
@@ -423,19 +436,18 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
                 const double Y0 = jj * h[1] + del[1] - g0[1];
                 const double Z0 = kk * h[2] + del[2] - g0[2];
                 const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2], dg = S.fn[q][3];
-                const double hs = nx_ > 0.0 ? 1.0 : -1.0, inx = 1.0 / fabs(nx_);
+                const double hs = nx_ > 0.0 ? 1.0 : -1.0, rnx = 1.0 / nx_;
                 const int o = S.loff[q], m = S.loff[q + 1] - o;
                 const int64_t m0 = S.fpl[q][0];
-                // on the face x = (d - ny y - nz z) / nx; with y, z relative to the corner the
-                // constant becomes e = d - nx X - ny Y0 - nz Z0
+                // on the face n.v = d; with y, z relative to the corner, the plane's value at
+                // (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0
                 if (pi == 0) {
                     // the face over this rectangle: full voxels below it, and the voxel holding its x minimum
-                    const Mom M0 = region_moments<VPL>(S, o, m, Y0, Z0, h[1], h[2], false, hs, 0.0, ny_, nz_);
-                    if (M0.A != 0.0) {
-                        for (int64_t i = i0[0]; i <= m0 - 2; ++i) emit(i, jj, kk, hs * h[0] * M0.A);
-                        const double X = (m0 - 1) * h[0] + del[0] - g0[0];
-                        const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
-                        emit(m0 - 1, jj, kk, (e * M0.A - ny_ * M0.My - nz_ * M0.Mz) * inx);
+                    const double X = (m0 - 1) * h[0] + del[0] - g0[0];
+                    const Reg R0 = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], false, hs, 0.0, ny_, nz_, X, rnx);
+                    if (R0.A != 0.0) {
+                        for (int64_t i = i0[0]; i <= m0 - 2; ++i) emit(i, jj, kk, hs * h[0] * R0.A);
+                        emit(m0 - 1, jj, kk, hs * R0.G);
                     }
                 } else {
                     // G at the plane X_m inside the face's x range: -G to voxel m-1, +G to voxel m
@@ -443,9 +455,9 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
                     const double X = mm * h[0] + del[0] - g0[0];
                     const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
                     const bool useH = !(ny_ == 0.0 && nz_ == 0.0);
-                    const Mom M1 = region_moments<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_);
                     if (useH || hs * e > 0.0) {
-                        const double G = (e * M1.A - ny_ * M1.My - nz_ * M1.Mz) * inx;
+                        const Reg R1 = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
+                        const double G = hs * R1.G;
                         emit(mm - 1, jj, kk, -G);
                         emit(mm, jj, kk, G);
                     }
