@@ -36,7 +36,10 @@
  *      pass is exhaustive).  The result therefore does not depend on any search
  *      structure.  Periodic results are only claimed when 2R < L/2, where the
  *      minimum image is the only image that can matter.
- *   4. Volume by fan tetrahedra from the seed; face area and centroid by fan
+ *   4. Each final vertex is recomputed from three of the planes that meet
+ *      there (a vertex is equidistant from the seed and those particles) in
+ *      extended precision, so rounding does not accumulate over the cuts.
+ *   5. Volume by fan tetrahedra from the seed; face area and centroid by fan
  *      triangles; faces of (near) zero area are not facets.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
@@ -420,6 +423,86 @@ static int cmp_cand(const void *a, const void *b) {
 }
 
 /*
+ * Vertex refinement.  Every vertex of the final cell is a point equidistant
+ * from the seed and the particles (or walls) of the faces that meet there.
+ * Edge interpolation during clipping lets rounding errors accumulate from one
+ * cut to the next, so each vertex is recomputed from three of its incident
+ * face planes (the best-conditioned triple) by Cramer's rule in extended
+ * precision.  Topology is untouched.
+ */
+#define REF_MAXF 8
+static void plane_of(const world *Wd, int64_t i, int64_t tag, const double blo[3], const double bhi[3],
+                     long double n[3], long double *d) {
+    if (tag >= 0) {
+        double D[3];
+        delta(Wd, i, tag, D);
+        for (int c = 0; c < 3; ++c) n[c] = D[c];
+        *d = 0.5L * (n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    } else {
+        int k = (int)(-1 - tag), a = k / 2;
+        for (int c = 0; c < 3; ++c) n[c] = 0.0L;
+        n[a] = (k & 1) ? 1.0L : -1.0L;
+        *d = (k & 1) ? (long double)bhi[a] : -(long double)blo[a];
+    }
+}
+
+static long double det3(const long double a[3], const long double b[3], const long double c[3]) {
+    return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+static int refine_vertices(const world *Wd, int64_t i, poly *P, const double blo[3], const double bhi[3]) {
+    int *inc = (int *)malloc(sizeof(int) * (size_t)P->nv * REF_MAXF);
+    int *cnt = (int *)calloc((size_t)P->nv, sizeof(int));
+    long double *pl = (long double *)malloc(sizeof(long double) * 4 * (size_t)(P->nf > 0 ? P->nf : 1));
+    if (!inc || !cnt || !pl) {
+        free(inc);
+        free(cnt);
+        free(pl);
+        return -1;
+    }
+    for (int f = 0; f < P->nf; ++f) {
+        plane_of(Wd, i, P->ftag[f], blo, bhi, pl + 4 * f, pl + 4 * f + 3);
+        for (int k = 0; k < P->flen[f]; ++k) {
+            int v = P->fv[P->fofs[f] + k];
+            if (cnt[v] < REF_MAXF) inc[v * REF_MAXF + cnt[v]++] = f;
+        }
+    }
+    for (int v = 0; v < P->nv; ++v) {
+        int m = cnt[v];
+        if (m < 3) continue;
+        long double best = 0.0L;
+        int fa = -1, fb = -1, fc = -1;
+        for (int a = 0; a < m; ++a)
+            for (int b = a + 1; b < m; ++b)
+                for (int c = b + 1; c < m; ++c) {
+                    const int *q = inc + v * REF_MAXF;
+                    long double dd = fabsl(det3(pl + 4 * q[a], pl + 4 * q[b], pl + 4 * q[c]));
+                    if (dd > best) {
+                        best = dd;
+                        fa = q[a];
+                        fb = q[b];
+                        fc = q[c];
+                    }
+                }
+        if (fa < 0) continue;
+        const long double *A = pl + 4 * fa, *B = pl + 4 * fb, *C = pl + 4 * fc;
+        long double det = det3(A, B, C);
+        long double r[3] = {A[3], B[3], C[3]};
+        for (int col = 0; col < 3; ++col) {
+            long double a2[3] = {A[0], A[1], A[2]}, b2[3] = {B[0], B[1], B[2]}, c2[3] = {C[0], C[1], C[2]};
+            a2[col] = r[0];
+            b2[col] = r[1];
+            c2[col] = r[2];
+            P->v[3 * v + col] = (double)(det3(a2, b2, c2) / det);
+        }
+    }
+    free(inc);
+    free(cnt);
+    free(pl);
+    return 0;
+}
+
+/*
  * Build the cell of particle i into *out (which points at W->a or W->b).
  * Returns 0 on success.  *rmax2 receives the squared largest vertex distance,
  * *nplanes the number of particles with |D| < 2R (plus one), for the cost
@@ -488,7 +571,8 @@ static int build_cell(const world *Wd, int64_t i, work *W, poly **out, double to
         if (D[0] * D[0] + D[1] * D[1] + D[2] * D[2] < 4.0 * r2) np++;
     }
     *nplanes = np;
-    *rmax2 = r2;
+    if (refine_vertices(Wd, i, P, blo, bhi)) return ORA_ERR_NOMEM;
+    *rmax2 = poly_rmax2(P);
     *out = P;
     return ORA_OK;
 }
@@ -497,33 +581,35 @@ typedef struct {
     double area, cen[3];
 } face_geom;
 
-/* volume (seed at origin), and per-face area / centroid by fan triangles */
+/* volume (seed at origin), and per-face area / centroid by fan triangles,
+   accumulated in extended precision */
 static double poly_measure(const poly *P, face_geom *fg) {
-    double vol = 0.0;
+    long double vol = 0.0L;
     for (int f = 0; f < P->nf; ++f) {
         int o = P->fofs[f], m = P->flen[f];
         const double *w0 = P->v + 3 * P->fv[o];
-        double S[3] = {0, 0, 0}, C[3] = {0, 0, 0}, at = 0.0;
+        long double S[3] = {0, 0, 0}, C[3] = {0, 0, 0}, at = 0.0L;
         for (int k = 1; k + 1 < m; ++k) {
             const double *w1 = P->v + 3 * P->fv[o + k];
             const double *w2 = P->v + 3 * P->fv[o + k + 1];
-            double a[3] = {w1[0] - w0[0], w1[1] - w0[1], w1[2] - w0[2]};
-            double b[3] = {w2[0] - w0[0], w2[1] - w0[1], w2[2] - w0[2]};
-            double x[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            long double a[3] = {(long double)w1[0] - w0[0], (long double)w1[1] - w0[1], (long double)w1[2] - w0[2]};
+            long double b[3] = {(long double)w2[0] - w0[0], (long double)w2[1] - w0[1], (long double)w2[2] - w0[2]};
+            long double x[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
             for (int c = 0; c < 3; ++c) S[c] += x[c];
-            double ta = 0.5 * sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-            for (int c = 0; c < 3; ++c) C[c] += ta * (w0[c] + w1[c] + w2[c]) / 3.0;
+            long double ta = 0.5L * sqrtl(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            for (int c = 0; c < 3; ++c) C[c] += ta * ((long double)w0[c] + w1[c] + w2[c]) / 3.0L;
             at += ta;
             /* tetrahedron (seed, w0, w1, w2) */
-            vol += (w0[0] * (w1[1] * w2[2] - w1[2] * w2[1]) - w0[1] * (w1[0] * w2[2] - w1[2] * w2[0]) +
-                    w0[2] * (w1[0] * w2[1] - w1[1] * w2[0])) / 6.0;
+            vol += ((long double)w0[0] * ((long double)w1[1] * w2[2] - (long double)w1[2] * w2[1]) -
+                    (long double)w0[1] * ((long double)w1[0] * w2[2] - (long double)w1[2] * w2[0]) +
+                    (long double)w0[2] * ((long double)w1[0] * w2[1] - (long double)w1[1] * w2[0])) / 6.0L;
         }
         if (fg) {
-            fg[f].area = 0.5 * sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
-            for (int c = 0; c < 3; ++c) fg[f].cen[c] = at > 0 ? C[c] / at : w0[c];
+            fg[f].area = (double)(0.5L * sqrtl(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]));
+            for (int c = 0; c < 3; ++c) fg[f].cen[c] = at > 0 ? (double)(C[c] / at) : w0[c];
         }
     }
-    return vol;
+    return (double)vol;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -8,6 +8,9 @@ re-types the oracle's own formulas.
 * an independent Qhull tessellation (scipy.spatial, the library the paper
   itself builds on) of a periodically tiled point set;
 * exhaustive half-space vertex enumeration for tiny bounded sets;
+* exact rational cell volumes (vertices solved from their bisector planes in
+  ``fractions.Fraction`` on the dyadic FP32 inputs) for the most crowded cells of
+  a clustered set;
 * exact-recovery and conservation properties of the gradient, grid and adjoint.
 """
 import itertools
@@ -219,6 +222,83 @@ def test_exhaustive_tiny_bounded_sets(oracle):
             assert set(c.neighbours(i).tolist()) == facets
         assert abs(c.volume.sum() - 1.0) < 1e-12
 
+
+
+def _exact_volume(p64, L, i, tree):
+    """Exact volume of periodic cell i: topology from Qhull on the local set,
+    every vertex solved from its three bisector planes in rational arithmetic
+    (FP32 inputs and their differences are exact dyadic rationals)."""
+    from fractions import Fraction as Fr
+
+    from scipy.spatial import Voronoi
+
+    k = 64
+    while True:
+        dist, nb = tree.query(p64[i], k=k)
+        D = p64[nb] - p64[i]
+        D -= L * np.rint(D / L)
+        vor = Voronoi(D)
+        reg = vor.regions[vor.point_region[0]]
+        if -1 not in reg and 2 * np.sqrt((vor.vertices[reg] ** 2).sum(1).max()) < dist[-1]:
+            break
+        k *= 2
+    faces = {}
+    for (a, b), rv in zip(vor.ridge_points, vor.ridge_vertices):
+        if 0 in (a, b):
+            faces[b if a == 0 else a] = rv
+    planes = {}
+    for j in faces:
+        d = [Fr(float(p64[nb[j], c])) - Fr(float(p64[i, c])) for c in range(3)]
+        planes[j] = [x - Fr(L) * round(float(x) / L) for x in d]
+    inc = {}
+    for j, rv in faces.items():
+        for v in rv:
+            inc.setdefault(v, []).append(j)
+
+    def det3(m):
+        return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+                + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+
+    vert = {}
+    for v, js in inc.items():
+        m = [planes[j] for j in js[:3]]
+        r = [sum(x * x for x in row) / 2 for row in m]
+        det = det3(m)
+        vert[v] = [det3([[r[q] if c == col else m[q][c] for c in range(3)] for q in range(3)]) / det
+                   for col in range(3)]
+    vol = Fr(0)
+    for j, rv in faces.items():
+        pts = np.array([[float(x) for x in vert[v]] for v in rv])
+        n = np.array([float(x) for x in planes[j]])
+        ctr = pts.mean(0)
+        u = pts[0] - ctr
+        u -= n * (u @ n) / (n @ n)
+        w = np.cross(n, u)
+        loop = [vert[rv[o]] for o in np.argsort(np.arctan2((pts - ctr) @ w, (pts - ctr) @ u))]
+        for t in range(1, len(loop) - 1):
+            a, b, c = loop[0], loop[t], loop[t + 1]
+            vol += (a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0])
+                    + a[2] * (b[0] * c[1] - b[1] * c[0])) / 6
+    return float(vol), set(int(nb[j]) for j in faces)
+
+
+def test_exact_rational_volumes_clustered(oracle):
+    """Crowded halo cells are the worst conditioned; the oracle must match exact volumes."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(2016)
+    L = 10.0
+    p, _ = wl.clustered_box(rng, 20000, L, 12, (0.3, 1.0))
+    p64 = p.astype(np.float64)
+    tree = cKDTree(p64, boxsize=L)
+    c_all = oracle.cells(p64, 0.0, L, query=rng.choice(len(p), 400, replace=False))
+    dense = np.argsort(c_all.volume)[:24]
+    query = np.concatenate([c_all.query[dense], rng.choice(len(p), 24, replace=False)])
+    c = oracle.cells(p64, 0.0, L, query=query)
+    for q, i in enumerate(query):
+        ve, nbrs = _exact_volume(p64, L, int(i), tree)
+        assert set(c.neighbours(q).tolist()) == nbrs, i
+        assert abs(c.volume[q] - ve) <= 1e-14 * ve, (i, c.volume[q], ve)
 
 def test_bounded_world_flags(oracle):
     rng = np.random.default_rng(3)
