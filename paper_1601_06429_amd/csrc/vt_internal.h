@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/vt.h"
+#include "vt.h"
 
 // ---------------------------------------------------------------- constants
 #define VT_MORTON_BITS 16          // quantisation bits per axis of the Morton key

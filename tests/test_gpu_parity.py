@@ -215,6 +215,44 @@ def test_grid_matches_oracle(vt, torch_cuda, oracle, dims):
     assert abs(g.sum() / np.prod(dims) - m.sum()) <= 1e-12 * m.sum()
 
 
+def test_grid_bounded_world_matches_oracle(vt, torch_cuda, oracle):
+    """Walls of a bounded world are faces of the boundary cells; the deposit must still be exact."""
+    rng = np.random.default_rng(8)
+    p = rng.random((1500, 3))
+    val = rng.uniform(0.5, 2.0, len(p))
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(p).cuda(), vt.whole_box(len(p), 0.0, 1.0, periodic=False))
+    ctx.vt_cells()
+    dims = (12, 10, 14)
+    g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
+    assert ctx.vt_query()[0] == 0
+    gref = oracle.grid(p, 0.0, 1.0, False, val, dims)
+    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+
+
+def test_grid_large_cell(vt, torch_cuda, oracle):
+    """Cells with more than 64 vertices go through the large-capacity kernels (clip and grid)."""
+    m = 90
+    k = np.arange(m) + 0.5
+    phi = np.arccos(1 - 2 * k / m)
+    th = math.pi * (1 + 5 ** 0.5) * k
+    sph = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1) * 0.05
+    rng = np.random.default_rng(2)
+    bg = rng.random((3000, 3))
+    bg = bg[np.linalg.norm(bg - 0.5, axis=1) > 0.12]
+    p = np.concatenate([[[0.5, 0.5, 0.5]], 0.5 + sph, bg])
+    val = np.zeros(len(p))
+    val[:m + 1] = rng.uniform(0.5, 2.0, m + 1)
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(p).cuda(), vt.whole_box(len(p), 0.0, 1.0))
+    ctx.vt_cells()
+    code, _, retried, _ = ctx.vt_query()
+    assert code == 0 and retried >= 1
+    dims = (64, 64, 64)
+    g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
+    assert ctx.vt_query()[0] == 0
+    gref = oracle.grid(p, 0.0, 1.0, True, val, dims, query=np.arange(m + 1))
+    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+
+
 def test_grid_unit_field_and_aligned_lattice(vt, torch_cuda):
     w = wl.workload1()
     t = torch_cuda.from_numpy(w.pos).cuda()
