@@ -122,6 +122,26 @@ def whole_box(n, box_lo, box_hi, periodic=True):
     return [dict(offset=0, n_owned=int(n), n_ghost=0, periodic=bool(periodic), lo=lo, hi=hi)]
 
 
+def pack_worlds(worlds):
+    """Pack bounded worlds into one batch for ``vt_build``.
+
+    ``worlds`` is a sequence of (owned, ghosts, lo, hi): owned and ghost
+    positions (n x 3 arrays of one dtype) and the world's box [lo, hi] (the
+    owned region plus its buffer).  Returns (positions, items, global_ids):
+    positions concatenated world by world, owned first, the item list, and
+    int32 global ids equal to the position row.
+    """
+    parts, items, off = [], [], 0
+    for owned, ghosts, lo, hi in worlds:
+        parts += [owned, ghosts]
+        items.append(dict(offset=off, n_owned=len(owned), n_ghost=len(ghosts), periodic=False,
+                          lo=np.broadcast_to(np.asarray(lo, np.float64), 3),
+                          hi=np.broadcast_to(np.asarray(hi, np.float64), 3)))
+        off += len(owned) + len(ghosts)
+    pos = np.ascontiguousarray(np.concatenate(parts))
+    return pos, items, np.arange(off, dtype=np.int32)
+
+
 def _items(items):
     arr = (vt_item * len(items))()
     for k, it in enumerate(items):

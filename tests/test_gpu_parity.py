@@ -166,6 +166,90 @@ def test_large_cell_uses_big_kernel(vt, torch_cuda, oracle):
     assert (cells.status.cpu().numpy()[0] & 2) != 0
 
 
+
+# ---------------------------------------------------------------- batched worlds
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_items_match_oracle(vt, torch_cuda, oracle, precision):
+    """Uneven clustered sub-volumes with ghost buffers in one build; every owned cell
+    against the oracle run on that item's own bounded world."""
+    items = wl.workload4(n_items=6, n_range=(1500, 6000), seed_offset=1)
+    worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
+    pos, desc, gid = vt.pack_worlds(worlds)
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(pos).cuda(), desc,
+                                global_id=torch_cuda.from_numpy(gid).cuda(), precision=precision)
+    code, nnz, retried, n_inc = ctx.vt_query()
+    assert code == 0
+    cells = ctx.vt_cells()
+    st = cells.status.cpu().numpy()
+    row = 0
+    inc_ref = 0
+    for d, it in zip(desc, items):
+        p64 = pos[d["offset"]:d["offset"] + d["n_owned"] + d["n_ghost"]].astype(np.float64)
+        ref = oracle.cells(p64, d["lo"], d["hi"], periodic=False, query=np.arange(d["n_owned"]),
+                           gid=gid[d["offset"]:d["offset"] + len(p64)].astype(np.int64))
+        rows = row + np.arange(d["n_owned"])
+        compare_rows(cells, ref, rows, TOL[precision], "item at row %d" % row)
+        flag_gpu = (st[rows] & 1) != 0
+        flag_ref = (ref.flags & (oracle.FLAG_WALL | oracle.FLAG_INCOMPLETE)) != 0
+        assert np.array_equal(flag_gpu, flag_ref)
+        inc_ref += int(flag_ref.sum())
+        row += d["n_owned"]
+    assert n_inc == inc_ref
+    assert row == ctx.n_owned
+
+
+def test_batched_graph_capture_replays(vt, torch_cuda):
+    """build + CSR + density captured once in a HIP graph and replayed on moved positions;
+    every replay must equal an eager build of the same positions."""
+    torch = torch_cuda
+    items = wl.workload4(n_items=5, n_range=(1500, 6000), seed_offset=2)
+    worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
+    pos, desc, gid = vt.pack_worlds(worlds)
+    t = torch.from_numpy(pos).cuda()
+    g_id = torch.from_numpy(gid).cuda()
+    ctx = vt.Context().vt_build(t, desc, global_id=g_id, precision=1)  # allocates
+    nnz = ctx.vt_query()[1]
+    n = ctx.n_owned
+    vol = torch.empty(n, dtype=torch.float64, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(int(nnz * 1.5) + 4096, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.vt_build(t, desc, global_id=g_id, precision=1)
+        ctx.vt_cells_into(vol, off, ids, st)
+        ctx.vt_density(None, out=rho)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.vt_build(t, desc, global_id=g_id, precision=1)
+        ctx.vt_cells_into(vol, off, ids, st)
+        ctx.vt_density(None, out=rho)
+    rng = np.random.default_rng(12)
+    lo = np.concatenate([np.repeat(d["lo"][None, :], d["n_owned"] + d["n_ghost"], 0) for d in desc])
+    hi = np.concatenate([np.repeat(d["hi"][None, :], d["n_owned"] + d["n_ghost"], 0) for d in desc])
+    for rep in range(3):
+        moved = pos + rng.uniform(-1e-3, 1e-3, pos.shape).astype(pos.dtype)
+        moved = np.clip(moved, lo.astype(pos.dtype), np.nextafter(hi.astype(pos.dtype), -np.inf))
+        t.copy_(torch.from_numpy(moved))
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy().copy() for x in (vol, off, st, rho)]
+        got_ids = ids[: int(got[1][-1])].cpu().numpy().copy()
+        ref = vt.Context().vt_build(torch.from_numpy(moved).cuda(), desc, global_id=g_id, precision=1)
+        assert ref.vt_query()[0] == 0
+        rc = ref.vt_cells()
+        rrho = ref.vt_density().cpu().numpy()
+        assert np.array_equal(got[0], rc.volume.cpu().numpy()), rep
+        assert np.array_equal(got[1], rc.nbr_off.cpu().numpy()), rep
+        assert np.array_equal(got_ids, rc.nbr_ids.cpu().numpy()), rep
+        assert np.array_equal(got[2], rc.status.cpu().numpy()), rep
+        assert np.array_equal(got[3], rrho), rep
+        assert ctx.vt_query()[0] == 0
+
 # ---------------------------------------------------------------- derived outputs
 def test_gradient_matches_oracle(vt, torch_cuda, oracle):
     w = wl.workload1()
