@@ -31,9 +31,9 @@
  *      image vector from the seed to particle j) of the 64 nearest particles,
  *      nearest first; each face is clipped Sutherland-Hodgman style and the cut
  *      polygon becomes the new face.
- *   3. Scan ALL particles once more and clip by every j with |D_j| < 2 R,
- *      where R is the current largest vertex distance (R only shrinks, so one
- *      pass is exhaustive).  The result therefore does not depend on any search
+ *   3. Scan ALL particles once more and clip by every j with |D_j| < 2 R not
+ *      already applied, where R is the current largest vertex distance (R only
+ *      shrinks, so one pass is exhaustive).  The result therefore does not depend on any search
  *      structure.  Periodic results are only claimed when 2R < L/2, where the
  *      minimum image is the only image that can matter.
  *   4. Each final vertex is recomputed from three of the planes that meet
@@ -415,6 +415,11 @@ static void heap_push(cand *h, int *sz, int cap, cand c) {
     }
 }
 
+static int cmp_i64(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
 static int cmp_cand(const void *a, const void *b) {
     const cand *x = (const cand *)a, *y = (const cand *)b;
     if (cand_less(x, y)) return -1;
@@ -534,8 +539,10 @@ static int build_cell(const world *Wd, int64_t i, work *W, poly **out, double to
     }
     qsort(heap, (size_t)hs, sizeof(cand), cmp_cand);
     double r2 = poly_rmax2(P);
+    int napplied = 0;
     for (int k = 0; k < hs; ++k) {
         if (heap[k].d2 >= 4.0 * r2 * (1.0 + 1e-9)) break;
+        napplied = k + 1;
         double D[3];
         delta(Wd, i, heap[k].j, D);
         double dd = 0.5 * heap[k].d2;
@@ -547,9 +554,15 @@ static int build_cell(const world *Wd, int64_t i, work *W, poly **out, double to
             r2 = poly_rmax2(P);
         }
     }
-    /* pass B: every particle, exhaustive */
+    /* pass B: every particle, exhaustive.  A bisector already applied in pass A is
+       skipped: the cell is an intersection of half-spaces, each taken once (a second
+       cut by the same plane could only shave rounding slivers off its own face). */
+    int64_t used[K_NEAREST];
+    for (int k = 0; k < napplied; ++k) used[k] = heap[k].j;
+    qsort(used, (size_t)napplied, sizeof(int64_t), cmp_i64);
     for (int64_t j = 0; j < Wd->n; ++j) {
         if (j == i) continue;
+        if (napplied && bsearch(&j, used, (size_t)napplied, sizeof(int64_t), cmp_i64)) continue;
         double D[3];
         delta(Wd, i, j, D);
         double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];

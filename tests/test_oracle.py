@@ -300,6 +300,40 @@ def test_exact_rational_volumes_clustered(oracle):
         assert set(c.neighbours(q).tolist()) == nbrs, i
         assert abs(c.volume[q] - ve) <= 1e-14 * ve, (i, c.volume[q], ve)
 
+def test_clustered_lists_unique_symmetric_and_conserving(oracle):
+    """Every cell of a crowded clustered set: no particle twice in a neighbour list (one
+    facet per neighbour), symmetric lists, and volumes summing to the box volume."""
+    rng = np.random.default_rng(77)
+    L = 10.0
+    p, _ = wl.clustered_box(rng, 20000, L, 12, (0.3, 1.0))
+    c = oracle.cells(p.astype(np.float64), 0.0, L)
+    sets = []
+    for q in range(len(p)):
+        nb = c.neighbours(q)
+        assert len(nb) == len(set(nb.tolist())), q
+        sets.append(set(nb.tolist()))
+    for q in range(0, len(p), 7):
+        for j in sets[q]:
+            assert q in sets[j]
+    assert abs(c.volume.sum() - L ** 3) <= 1e-12 * L ** 3
+
+
+def test_benchmark_workload_cells_exact(oracle):
+    """Two crowded cells of the 2M clustered workload where a bisector applied twice once
+    left a duplicate facet; their volumes must equal the exact rational volumes."""
+    from scipy.spatial import cKDTree
+
+    w = wl.workload2()
+    p64 = w.pos.astype(np.float64)
+    rows = np.array([2028842, 2055653])
+    c = oracle.cells(p64, w.box_lo, w.box_hi, query=rows)
+    tree = cKDTree(p64, boxsize=100.0)
+    for q, i in enumerate(rows):
+        ve, nbrs = _exact_volume(p64, 100.0, int(i), tree)
+        assert c.neighbours(q).tolist() == sorted(nbrs)
+        assert abs(c.volume[q] - ve) <= 1e-14 * ve
+
+
 def test_bounded_world_flags(oracle):
     rng = np.random.default_rng(3)
     p = rng.random((600, 3))
