@@ -27,7 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Voronoi cells/sec (neighbours+volume+density) at 2M clustered pts; bwd cells/s"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}  # vector FMA rate: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# vector peaks from unit counts: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s in FP64;
+# FP32 counts two packed operations per lane (157.3 TFLOP/s)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 
 def parse():
@@ -39,10 +41,119 @@ def parse():
                                                                   "diff262k"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-variants", action="store_true", help="skip the mixed/fp64 forward comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-item form")
     ap.add_argument("--fwd-only", action="store_true", help="time only vt_build + vt_cells + vt_density")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (traffic calibration for rocprofv3 counters)")
     return ap.parse_args()
+
+
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_clip_clustered2m_traffic.md")
+CLIP_SOURCES = ["paper_1601_06429_amd/csrc/clip.hip", "paper_1601_06429_amd/csrc/poly.h",
+                "paper_1601_06429_amd/csrc/vt_internal.h"]
+
+
+def copy_calibration():
+    """A plain device copy of COPY_BYTES, five times: rocprofv3 FETCH_SIZE / WRITE_SIZE read
+    on it give the factor between the counters and true HBM bytes."""
+    import torch
+
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}))
+
+
+def clip_sources_sha1():
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in CLIP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fast clip kernel, from the committed counter summary;
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.strip("- \n").split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha1") != clip_sources_sha1():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batched_forms(torch, vt, reps=5):
+    """64 uneven ghost-buffered sub-volumes in one build: eager vs HIP-graph replay, FP64 vs mixed."""
+    from paper_1601_06429_amd import workloads as wl
+
+    items = wl.workload4()
+    worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
+    pos, desc, gid = vt.pack_worlds(worlds)
+    t = torch.from_numpy(pos).cuda()
+    g_id = torch.from_numpy(gid).cuda()
+    n_owned = sum(d["n_owned"] for d in desc)
+    res = {"workload": "batched-64-items-fp32", "items": len(desc), "n_owned": n_owned,
+           "n_ghost": sum(d["n_ghost"] for d in desc), "step": "build+cells+density"}
+    keep = {}
+    for name, p in (("fp64", vt.PREC_FP64), ("mixed", vt.PREC_MIXED)):
+        ctx = vt.Context().vt_build(t, desc, global_id=g_id, precision=p)
+        code, nnz, retried, inc = ctx.vt_query()
+        vol = torch.empty(n_owned, dtype=torch.float64, device="cuda")
+        off = torch.empty(n_owned + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(int(nnz * 1.05) + 4096, dtype=torch.int32, device="cuda")
+        st = torch.empty(n_owned, dtype=torch.uint8, device="cuda")
+        rho = torch.empty(n_owned, dtype=torch.float64, device="cuda")
+
+        def step():
+            ctx.vt_build(t, desc, global_id=g_id, precision=p)
+            ctx.vt_cells_into(vol, off, ids, st)
+            ctx.vt_density(None, out=rho)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        code = ctx.vt_query()[0]
+        res[name] = {"eager_cells_per_s": n_owned * reps / (tb - ta), "graph_cells_per_s": n_owned * reps / (td - tc),
+                     "graph_ms": (td - tc) * 1e3 / reps, "status": vt.STATUS_NAMES.get(code),
+                     "retried": retried, "incomplete": inc}
+        keep[name] = (vol.cpu().numpy(), off.cpu().numpy(), ids[: int(off[-1])].cpu().numpy())
+        del graph, ctx
+    v64, o64, i64 = keep["fp64"]
+    vm, om, im = keep["mixed"]
+    res["mixed_vs_fp64"] = {"max_rel_volume_diff": float(np.max(np.abs(vm - v64) / v64)),
+                            "neighbours_identical": bool(np.array_equal(o64, om) and np.array_equal(i64, im))}
+    return res
 
 
 def load_workload(name):
@@ -59,6 +170,9 @@ def load_workload(name):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
               "described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
@@ -148,12 +262,14 @@ def main():
     if code != 0:
         raise SystemExit("timed run reported: %s" % vt.STATUS_NAMES.get(code))
 
-    # cost model of the clipping kernel over the actual cells
+    # cost model of the fast clipping kernel over the cells it computed (retried cells excluded)
     nv, npl, ntest = ctx.vt_stats()
+    ctx.vt_cells_into(vol, off, ids, st)
+    fast = (st & 2) == 0
     nv = nv.to(torch.float64)
     npl = npl.to(torch.float64)
-    alg_flops = float((6.0 * npl * nv + 60.0 * nv).sum())
-    clip_ms = build_ms[1] + build_ms[2]
+    alg_flops = float(((6.0 * npl * nv + 60.0 * nv) * fast).sum())
+    clip_ms = build_ms[1]
     achieved = alg_flops / (clip_ms * 1e-3) / 1e12
     dtype = "f64" if prec == vt.PREC_FP64 else "f32"
 
@@ -181,9 +297,10 @@ def main():
                      "sort": build_ms[0], "clip": build_ms[1], "clip_large": build_ms[2]},
         "nnz": nnz,
         "retried_cells": retried,
-        "roofline": {"kernel": "k_clip (fast + large)", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_clip fast (cells up to 64 vertices)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype],
-                     "traffic": None, "alg_flops_per_launch": alg_flops, "launch_ms": clip_ms,
+                     "traffic": measured_traffic() if prec == vt.PREC_FP64 else None,
+                     "alg_flops_per_launch": alg_flops, "launch_ms": clip_ms,
                      "mean_planes": float(npl.mean()), "mean_vertices": float(nv.mean()),
                      "mean_tested": float(ntest.to(torch.float64).mean())},
     }
@@ -208,6 +325,11 @@ def main():
             var[name] = {"fwd_cells_per_s": N * reps / (tb - ta), "status": vt.STATUS_NAMES.get(code2)}
             del c2
         out["precision_variants"] = var
+
+    if not args.no_batched and not args.fwd_only:
+        del ctx
+        torch.cuda.empty_cache()
+        out["batched"] = batched_forms(torch, vt)
 
     if not args.no_cpu_baseline:
         import oracle
