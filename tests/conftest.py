@@ -19,3 +19,20 @@ def oracle():
 
     ora.build()
     return ora
+
+
+@pytest.fixture(scope="session")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="session")
+def vt(torch_cuda):
+    import paper_1601_06429_amd as vt
+
+    vt.lib()
+    return vt

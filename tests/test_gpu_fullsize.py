@@ -1,0 +1,139 @@
+"""GPU checks at the full sizes of the benchmark's workloads.
+
+* lattice+halos 16M (FP32, mixed and FP64 paths): sampled cells against the oracle, plus
+  volume conservation over the whole box;
+* diff262k: the adjoint gradient of a density-matching loss at full size against central
+  finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
+  perturbed loss is evaluated exactly on a small bounded world around the moved particle
+  (its own cell and its neighbours' cells as owned cells, the surrounding particles as
+  buffer); all 3072 worlds go through one batched build, and every owned cell of every
+  world must be complete.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from paper_1601_06429_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lattice16m():
+    return wl.workload3()
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, precision):
+    w = lattice16m
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision)
+    code, nnz, retried, inc = ctx.vt_query()
+    assert code == 0
+    cells = ctx.vt_cells()
+    vol = cells.volume.cpu().numpy()
+    assert abs(vol.sum() - 1.0) <= 1e-12
+    off = cells.nbr_off.cpu().numpy()
+    ids = cells.nbr_ids.cpu().numpy()
+    rng = np.random.default_rng(3003)
+    sample = np.sort(rng.choice(w.n, 256, replace=False))
+    ref = oracle.cells(w.pos.astype(np.float64), w.box_lo, w.box_hi, query=sample)
+    tol = 1e-12 if precision == 0 else 2e-5
+    for q, i in enumerate(sample):
+        assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
+        assert abs(vol[i] - ref.volume[q]) <= tol * ref.volume[q], i
+    del ctx, cells, t
+    torch_cuda.cuda.empty_cache()
+
+
+def _target(torch, x, lam, phi, amp, mean):
+    s = torch.ones(x.shape[0], dtype=x.dtype, device=x.device)
+    for a in range(3):
+        s = s * torch.sin(2.0 * math.pi * x[:, a] / float(lam[a]) + float(phi[a]))
+    return mean * (1.0 + amp * s)
+
+
+def test_diff262k_adjoint_vs_finite_differences(vt, torch_cuda):
+    torch = torch_cuda
+    w = wl.workload5()
+    n = w.n
+    lam, phi, amp = w.extra["target_lambda"], w.extra["target_phase"], w.extra["target_amplitude"]
+    mean = float(w.mass.sum())
+    p64 = w.pos.astype(np.float64)
+    x = torch.from_numpy(p64).cuda().requires_grad_(True)
+    V = vt.voronoi_volume(x, 0.0, 1.0)
+    loss = ((torch.log(1.0 / V) - torch.log(_target(torch, x, lam, phi, amp, mean))) ** 2).sum()
+    loss.backward()
+    grad = x.grad.cpu().numpy()
+
+    # neighbour lists of the unperturbed set
+    ctx = vt.Context().vt_build(torch.from_numpy(p64).cuda(), vt.whole_box(n, 0.0, 1.0))
+    cells = ctx.vt_cells()
+    off = cells.nbr_off.cpu().numpy()
+    ids = cells.nbr_ids.cpu().numpy()
+    tree = cKDTree(p64, boxsize=1.0)
+    rows = w.extra["fd_rows"]
+    h = 1e-6
+
+    def mind(a, b):
+        d = a - b
+        return d - np.rint(d)
+
+    def worlds_for(ks, factor):
+        # radius: every affected cell's offset from x_k plus `factor` times its largest
+        # neighbour distance (a generous scale for twice its security radius)
+        worlds, meta = [], []
+        for k in ks:
+            aff = np.concatenate([[k], ids[off[k]:off[k + 1]]]).astype(np.int64)
+            r = 0.0
+            for i in aff:
+                nb = ids[off[i]:off[i + 1]]
+                far = np.sqrt((mind(p64[nb], p64[i]) ** 2).sum(1)).max()
+                r = max(r, np.sqrt((mind(p64[i], p64[k]) ** 2).sum()) + factor * far)
+            near = np.asarray(tree.query_ball_point(p64[k], min(r, 0.45)), dtype=np.int64)
+            loc = np.concatenate([aff, np.setdiff1d(near, aff)])
+            d = mind(p64[loc], p64[k])
+            rb = np.abs(d).max() * 1.0000001
+            base = p64[k] + d
+            for a in range(3):
+                for s in (1.0, -1.0):
+                    q = base.copy()
+                    q[0, a] += s * h
+                    worlds.append((q[:len(aff)], q[len(aff):], p64[k] - rb, p64[k] + rb))
+                    meta.append((k, a, s, len(aff)))
+        return worlds, meta
+
+    fd = {}
+    todo, factor = list(rows), 2.0
+    while todo:
+        assert factor <= 16.0, "local worlds keep missing particles"
+        worlds, meta = worlds_for(todo, factor)
+        pos, desc, gid = vt.pack_worlds(worlds)
+        bctx = vt.Context().vt_build(torch.from_numpy(pos).cuda(), desc, global_id=torch.from_numpy(gid).cuda())
+        assert bctx.vt_query()[0] == 0
+        bc = bctx.vt_cells()
+        bvol = bc.volume.cpu().numpy()
+        bst = bc.status.cpu().numpy()
+        row, redo, part = 0, set(), {}
+        for (k, a, s, na), (owned, _, _, _) in zip(meta, worlds):
+            v = bvol[row:row + na]
+            if (bst[row:row + na] & 1).any():
+                redo.add(k)
+            rt = wl.target_density(np.mod(owned, 1.0), lam, phi, amp, mean)
+            part.setdefault(k, np.zeros(3))[a] += s * float(np.sum((np.log(1.0 / v) - np.log(rt)) ** 2)) / (2 * h)
+            row += na
+        for k in part:
+            if k not in redo:
+                fd[k] = part[k]
+        print("local worlds: factor %.0f, %d particles, %d to redo" % (factor, len(pos), len(redo)))
+        todo, factor = sorted(redo), factor * 2.0
+        del bctx, bc
+    fd = np.array([fd[k] for k in rows])
+    g = grad[rows]
+    scale = np.abs(g).max(axis=1, keepdims=True)
+    err = np.abs(fd - g) / np.maximum(scale, 1e-3 * np.abs(g).max())
+    print("finite differences: max scaled error %.3e, median %.3e" % (err.max(), np.median(err)))
+    assert np.median(err) < 1e-6
+    assert np.quantile(err, 0.99) < 1e-4

@@ -17,23 +17,6 @@ pytestmark = pytest.mark.gpu
 TOL = {0: 1e-12, 1: 2e-5}
 
 
-@pytest.fixture(scope="module")
-def torch_cuda():
-    import torch
-
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    return torch
-
-
-@pytest.fixture(scope="module")
-def vt():
-    import paper_1601_06429_amd as vt
-
-    vt.lib()
-    return vt
-
-
 def run(vt, torch, pos, lo, hi, periodic=True, precision=0, want_faces=False, **kw):
     t = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(len(pos), lo, hi, periodic), precision=precision,
