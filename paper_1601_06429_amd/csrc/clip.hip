@@ -54,6 +54,7 @@ struct ClipArgs {
     int64_t queue_cap;
     uint32_t *counters;
     double *cvol;
+    double *crad;             // largest vertex distance of each cell
     int32_t *ccnt;
     int64_t *crow;
     uint8_t *cstat;
@@ -544,6 +545,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                 atomicOr(&A.counters[CTR_STATUS], corrupt ? VT_DEV_TOPOLOGY : VT_DEV_CAPACITY);
                 if (dup) atomicOr(&A.counters[CTR_STATUS], VT_DEV_DUPLICATE);
                 A.cvol[cslot] = 0.0;
+                A.crad[cslot] = 0.0;
                 A.ccnt[cslot] = 0;
                 A.crow[cslot] = row;
                 A.cstat[cslot] = VT_CELL_FAILED | (RETRY ? VT_CELL_RETRIED : 0);
@@ -694,6 +696,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
             const int32_t kept = cnt < A.fstride ? cnt : (int32_t)A.fstride;
             if (cnt > A.fstride) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
             A.cvol[cslot] = V;
+            A.crad[cslot] = Rfin;
             A.ccnt[cslot] = kept;
             A.crow[cslot] = row;
             A.cstat[cslot] = st;
@@ -753,6 +756,7 @@ hipError_t vt_launch_clip(vt_ctx *c) {
     a.queue_cap = c->cap_retry;
     a.counters = c->counters;
     a.cvol = c->cvol;
+    a.crad = c->crad;
     a.ccnt = c->ccnt;
     a.crow = c->crow;
     a.cstat = c->cstat;

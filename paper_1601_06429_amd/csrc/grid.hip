@@ -23,8 +23,6 @@
 // overlap volumes move by at most 1e-12 of a voxel.
 #include "poly.h"
 
-#define GRID_ACC 1024  // voxels accumulated in LDS per cell
-
 template <int VPL>
 struct GridMem {
     static constexpr int FMAX = 64 * VPL;      // face slots
@@ -38,7 +36,6 @@ struct GridMem {
     int32_t fpl[FMAX][2];    // planes strictly inside the face's x range: m0, count
     int32_t ipre[FMAX + 1];  // prefix of work items per face
     int32_t fid[FMAX];       // compacted face slots
-    double acc[GRID_ACC];
     PolyMem<double, VPL> P;
 };
 
@@ -53,6 +50,7 @@ struct GridArgs {
     const int32_t *ccnt;
     const uint8_t *cstat;
     const double *cvol;
+    const double *crad;
     const int32_t *stage_ids;
     const int32_t *srow;
     const double *value;
@@ -199,8 +197,6 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
     const double hv = h[0] * h[1] * h[2];
     const int dims[3] = {A.nx, A.ny, A.nz};
     const int64_t ntodo = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : A.ncells;
-    for (int k = lane; k < GRID_ACC; k += 64) S.acc[k] = 0.0;
-    wave_sync();
 
     for (;;) {
         int64_t w = 0;
@@ -217,6 +213,25 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
         double sx, sy, sz;
         gpos<PT4>(A.spos, j0, sx, sy, sz);
         const double xs[3] = {sx, sy, sz};
+        {
+            // a cell inside one voxel (its ball of radius R, the largest vertex distance, is)
+            // deposits its whole volume without being rebuilt
+            const double rc = A.crad[c];
+            int64_t va[3];
+            bool one = true;
+            for (int a = 0; a < 3; ++a) {
+                const double g = xs[a] - it.lo[a];
+                va[a] = (int64_t)floor((g - rc - del[a]) * ih[a]);
+                one = one && va[a] == (int64_t)floor((g + rc - del[a]) * ih[a]);
+            }
+            if (one) {
+                if (lane == 0) {
+                    int64_t g = (wrapi(va[0], dims[0]) * dims[1] + wrapi(va[1], dims[1])) * dims[2] + wrapi(va[2], dims[2]);
+                    unsafeAtomicAdd(&A.grid[g], val * A.cvol[c] / hv);
+                }
+                continue;
+            }
+        }
         double blo[3], bhi[3];
         for (int a = 0; a < 3; ++a) {
             if (it.periodic) {
@@ -288,8 +303,6 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
             }
             continue;
         }
-        const int ni = (int)(i1[0] - i0[0] + 1), nj = (int)(i1[1] - i0[1] + 1), nk = (int)(i1[2] - i0[2] + 1);
-        const bool in_lds = (int64_t)ni * nj * nk <= GRID_ACC;
         // ---- faces: compact the alive ones
         int nf = 0;
 #pragma unroll
@@ -410,12 +423,8 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
         // ---- work items
         auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
             if (v == 0.0) return;
-            if (in_lds) {
-                atomicAdd(&S.acc[(i - i0[0]) + ni * ((j - i0[1]) + (int64_t)nj * (k - i0[2]))], v);
-            } else {
-                int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(k, dims[2]);
-                unsafeAtomicAdd(&A.grid[g], val * v / hv);
-            }
+            int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(k, dims[2]);
+            unsafeAtomicAdd(&A.grid[g], val * v / hv);
         };
         for (int base = 0; base < nitem; base += 64) {
             const int item = base + lane;
@@ -465,20 +474,6 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
             }
         }
         wave_sync();
-        // ---- flush the cell's voxels
-        if (in_lds) {
-            const int nv = ni * nj * nk;
-            for (int k = lane; k < nv; k += 64) {
-                const double v = S.acc[k];
-                if (v != 0.0) {
-                    const int64_t i = i0[0] + k % ni, j = i0[1] + (k / ni) % nj, kz = i0[2] + k / (ni * nj);
-                    int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(kz, dims[2]);
-                    unsafeAtomicAdd(&A.grid[g], val * v / hv);
-                    S.acc[k] = 0.0;
-                }
-            }
-            wave_sync();
-        }
     }
 }
 
@@ -517,6 +512,7 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.ccnt = c->ccnt;
     a.cstat = c->cstat;
     a.cvol = c->cvol;
+    a.crad = c->crad;
     a.stage_ids = c->stage_ids;
     a.srow = c->srow;
     a.value = value;

@@ -43,6 +43,7 @@ void free_all(vt_ctx *c) {
     dfree(c->tab);
     dfree(c->cells);
     dfree(c->cvol);
+    dfree(c->crad);
     dfree(c->ccnt);
     dfree(c->crow);
     dfree(c->cstat);
@@ -197,6 +198,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
         TRY(dalloc(&c->cells, NO));
         TRY(dalloc(&c->row2cell, NO));
         TRY(dalloc(&c->cvol, NO));
+        TRY(dalloc(&c->crad, NO));
         TRY(dalloc(&c->ccnt, NO));
         TRY(dalloc(&c->crow, NO));
         TRY(dalloc(&c->cstat, NO));

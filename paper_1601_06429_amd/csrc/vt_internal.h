@@ -82,6 +82,7 @@ struct vt_ctx {
     int32_t *cells = nullptr;      // owned sorted indices, in Morton order
     // clip results per cell slot
     double *cvol = nullptr;
+    double *crad = nullptr;        // largest vertex distance per cell
     int32_t *ccnt = nullptr;
     int64_t *crow = nullptr;       // staging row start
     uint8_t *cstat = nullptr;
