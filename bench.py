@@ -107,9 +107,16 @@ def batched_forms(torch, vt, reps=5):
     n_owned = sum(d["n_owned"] for d in desc)
     res = {"workload": "batched-64-items-fp32", "items": len(desc), "n_owned": n_owned,
            "n_ghost": sum(d["n_ghost"] for d in desc), "step": "build+cells+density"}
+    # launch options tuned on a representative subset (the first 8 items)
+    sub_pos, sub_desc, sub_gid = vt.pack_worlds(worlds[:8])
+    tuned = {}
+    for name, p in (("fp64", vt.PREC_FP64), ("mixed", vt.PREC_MIXED)):
+        tuned[name], _ = vt.autotune.tune(vt.Context, torch.from_numpy(sub_pos).cuda(), sub_desc,
+                                          global_id=torch.from_numpy(sub_gid).cuda(), precision=p, reps=1)
     keep = {}
     for name, p in (("fp64", vt.PREC_FP64), ("mixed", vt.PREC_MIXED)):
-        ctx = vt.Context().vt_build(t, desc, global_id=g_id, precision=p)
+        opts = tuned[name]
+        ctx = vt.Context().vt_build(t, desc, global_id=g_id, precision=p, **opts)
         code, nnz, retried, inc = ctx.vt_query()
         vol = torch.empty(n_owned, dtype=torch.float64, device="cuda")
         off = torch.empty(n_owned + 1, dtype=torch.int64, device="cuda")
@@ -118,7 +125,7 @@ def batched_forms(torch, vt, reps=5):
         rho = torch.empty(n_owned, dtype=torch.float64, device="cuda")
 
         def step():
-            ctx.vt_build(t, desc, global_id=g_id, precision=p)
+            ctx.vt_build(t, desc, global_id=g_id, precision=p, **opts)
             ctx.vt_cells_into(vol, off, ids, st)
             ctx.vt_density(None, out=rho)
 
@@ -145,7 +152,7 @@ def batched_forms(torch, vt, reps=5):
         td = time.perf_counter()
         code = ctx.vt_query()[0]
         res[name] = {"eager_cells_per_s": n_owned * reps / (tb - ta), "graph_cells_per_s": n_owned * reps / (td - tc),
-                     "graph_ms": (td - tc) * 1e3 / reps, "status": vt.STATUS_NAMES.get(code),
+                     "graph_ms": (td - tc) * 1e3 / reps, "status": vt.STATUS_NAMES.get(code), "tuned": opts,
                      "retried": retried, "incomplete": inc}
         keep[name] = (vol.cpu().numpy(), off.cpu().numpy(), ids[: int(off[-1])].cpu().numpy())
         del graph, ctx

@@ -20,6 +20,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+from . import autotune  # noqa: E402,F401  (launch-option tuner; imports torch lazily)
+
 LIB_PATH = os.path.join(_HERE, "libvt.so")
 _lib = None
 _lock = threading.Lock()

@@ -1,0 +1,73 @@
+"""Autotuner for the build's launch options.
+
+Two knobs change only speed, never results:
+  * ``radius_factor`` -- the first search shell in local mean spacings, i.e. how
+    many candidates the first clipping pass gathers (the paper's equivalent is
+    the buffer thickness, section 2: too thin needs more passes, too thick
+    wastes work);
+  * ``waves_per_cu`` -- how many wavefronts (one cell each) the persistent
+    clipping kernel keeps resident per compute unit.
+
+``tune`` times ``vt_build`` with device events for each candidate on the
+caller's inputs (or a representative subset of items), keeps the fastest, and
+caches the choice per input signature for the life of the process.
+"""
+from __future__ import annotations
+
+import itertools
+
+RADIUS_FACTORS = (2.0, 2.6, 3.4)
+WAVES_PER_CU = (8, 16, 24)
+
+_cache = {}
+
+
+def candidates(radius_factors=RADIUS_FACTORS, waves_per_cu=WAVES_PER_CU):
+    return [dict(radius_factor=float(r), waves_per_cu=int(w)) for r, w in itertools.product(radius_factors,
+                                                                                           waves_per_cu)]
+
+
+def signature(device_name, dtype, n_total, n_items, precision):
+    """Inputs that share a signature share tuned options (sizes bucketed to powers of two)."""
+    return (str(device_name), str(dtype), max(int(n_total), 1).bit_length(), max(int(n_items), 1).bit_length(),
+            int(precision))
+
+
+def pick(timings):
+    """The fastest candidate: ``timings`` is a list of (options, milliseconds); ties keep the
+    earlier candidate."""
+    if not timings:
+        raise ValueError("no timings")
+    best = min(range(len(timings)), key=lambda k: (timings[k][1], k))
+    return dict(timings[best][0])
+
+
+def tune(ctx_factory, pos, items, global_id=None, precision=0, reps=2, cands=None, use_cache=True):
+    """Time each candidate with ``reps`` builds after one warm-up; return (options, timings).
+
+    ``ctx_factory`` makes a fresh ``Context``; builds are timed with events on the current
+    stream, so the result reflects device time only.
+    """
+    import torch
+
+    key = signature(torch.cuda.get_device_name(pos.device), pos.dtype, pos.shape[0], len(items), precision)
+    if use_cache and key in _cache:
+        return dict(_cache[key]), []
+    timings = []
+    for opts in (cands or candidates()):
+        ctx = ctx_factory()
+        ctx.vt_build(pos, items, global_id=global_id, precision=precision, **opts)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            ctx.vt_build(pos, items, global_id=global_id, precision=precision, **opts)
+        stop.record()
+        stop.synchronize()
+        code = ctx.vt_query()[0]
+        if code == 0:
+            timings.append((opts, start.elapsed_time(stop) / reps))
+        del ctx
+    best = pick(timings)
+    _cache[key] = best
+    return dict(best), timings

@@ -56,3 +56,16 @@ def test_argument_errors_are_synchronous():
     assert L.vt_build(ctypes.byref(ctx), None, vt.VT_F32, None, items, 1, None, None) == 1
     # calls on a context that was never built
     assert L.vt_cells(None, None, None, None, 0, None, None) == 7
+
+
+def test_autotune_selection_logic():
+    from paper_1601_06429_amd import autotune
+
+    c = autotune.candidates()
+    assert len(c) == len(autotune.RADIUS_FACTORS) * len(autotune.WAVES_PER_CU)
+    t = [(c[0], 3.0), (c[1], 1.5), (c[2], 1.5), (c[3], 9.0)]
+    assert autotune.pick(t) == c[1]  # fastest, earlier one on ties
+    a = autotune.signature("MI355X", "torch.float32", 2_097_152, 1, 0)
+    b = autotune.signature("MI355X", "torch.float32", 3_000_000, 1, 0)
+    d = autotune.signature("MI355X", "torch.float32", 4_500_000, 1, 0)
+    assert a == b and a != d

@@ -233,6 +233,27 @@ def test_batched_graph_capture_replays(vt, torch_cuda):
         assert np.array_equal(got[3], rrho), rep
         assert ctx.vt_query()[0] == 0
 
+
+def test_autotune_picks_a_candidate_and_results_do_not_depend_on_it(vt, torch_cuda):
+    torch = torch_cuda
+    items = wl.workload4(n_items=4, n_range=(1500, 6000), seed_offset=3)
+    pos, desc, gid = vt.pack_worlds([(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items])
+    t = torch.from_numpy(pos).cuda()
+    g = torch.from_numpy(gid).cuda()
+    best, timings = vt.autotune.tune(vt.Context, t, desc, global_id=g, precision=1, reps=1, use_cache=False)
+    assert best in vt.autotune.candidates() and len(timings) == len(vt.autotune.candidates())
+    ref = None
+    for opts in vt.autotune.candidates():
+        ctx = vt.Context().vt_build(t, desc, global_id=g, precision=1, **opts)
+        assert ctx.vt_query()[0] == 0
+        c = ctx.vt_cells()
+        cur = (c.volume.cpu().numpy(), c.nbr_off.cpu().numpy(), c.nbr_ids.cpu().numpy())
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[1], ref[1]) and np.array_equal(cur[2], ref[2]), opts
+            assert np.max(np.abs(cur[0] - ref[0]) / ref[0]) < 1e-13, opts
+
 # ---------------------------------------------------------------- derived outputs
 def test_gradient_matches_oracle(vt, torch_cuda, oracle):
     w = wl.workload1()
