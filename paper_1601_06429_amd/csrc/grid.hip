@@ -106,7 +106,7 @@ __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, dou
 // part of the face above x = X), with e given for the shifted coordinates and
 // rnx = 1 / n_x.
 template <int VPL>
-__device__ Reg region_integrals(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
+__device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
                                 bool useH, double hs, double e, double ny, double nz, double X, double rnx) {
     Reg D = {0.0, 0.0};
     auto gH = [&](double y, double z) { return hs * (e - ny * y - nz * z); };
@@ -450,23 +450,22 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
                 const int64_t m0 = S.fpl[q][0];
                 // on the face n.v = d; with y, z relative to the corner, the plane's value at
                 // (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0
-                if (pi == 0) {
-                    // the face over this rectangle: full voxels below it, and the voxel holding its x minimum
-                    const double X = (m0 - 1) * h[0] + del[0] - g0[0];
-                    const Reg R0 = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], false, hs, 0.0, ny_, nz_, X, rnx);
-                    if (R0.A != 0.0) {
-                        for (int64_t i = i0[0]; i <= m0 - 2; ++i) emit(i, jj, kk, hs * h[0] * R0.A);
-                        emit(m0 - 1, jj, kk, hs * R0.G);
-                    }
-                } else {
-                    // G at the plane X_m inside the face's x range: -G to voxel m-1, +G to voxel m
-                    const int64_t mm = m0 + pi - 1;
-                    const double X = mm * h[0] + del[0] - g0[0];
-                    const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
-                    const bool useH = !(ny_ == 0.0 && nz_ == 0.0);
-                    if (useH || hs * e > 0.0) {
-                        const Reg R1 = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
-                        const double G = hs * R1.G;
+                // pi == 0: the face over this rectangle against the plane below its x minimum
+                // (full voxels below it, and the voxel holding its x minimum); pi > 0: G at the
+                // plane X_m inside the face's x range, -G to voxel m-1 and +G to voxel m
+                const int64_t mm = m0 + pi - 1;
+                const double X = mm * h[0] + del[0] - g0[0];
+                const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
+                const bool useH = pi > 0 && !(ny_ == 0.0 && nz_ == 0.0);
+                if (pi == 0 || useH || hs * e > 0.0) {
+                    const Reg Rg = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
+                    const double G = hs * Rg.G;
+                    if (pi == 0) {
+                        if (Rg.A != 0.0) {
+                            for (int64_t i = i0[0]; i < mm; ++i) emit(i, jj, kk, hs * h[0] * Rg.A);
+                            emit(mm, jj, kk, G);
+                        }
+                    } else {
                         emit(mm - 1, jj, kk, -G);
                         emit(mm, jj, kk, G);
                     }
