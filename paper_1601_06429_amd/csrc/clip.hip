@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
                         const double *v = S.u.f.vp[s * 64 + k];
-                        const double sv = dx * v[0] + dy * v[1] + dz * v[2] - pd;
+                        const double sv = fma(v[0], dx, fma(v[1], dy, v[2] * dz)) - pd;  // the clip's rounding
                         // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
                         double marg = 0.0;
                         if (std::is_same<T, float>::value)
@@ -475,34 +475,97 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
                     double x = 4.0 * r2 / rh2 * 16777216.0;
                     return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
                 };
+                // Candidates go in chunks of 64 in increasing distance.  Each lane tests its
+                // plane against every vertex of the current cell (staged in LDS); a plane that
+                // cuts no vertex now never will (the cell only shrinks) and is dropped.  The
+                // rest are applied one by one, nearest first, until one lies beyond 2R.
                 uint32_t Q4R = q4r(P.R2);
                 bool stale = false;  // P.R2 is an upper bound until refreshed
-                for (int i = 0; i < n; ++i) {
-                    const uint32_t key = (i < 64) ? readlane_u32(k0, i) : readlane_u32(k1, i - 64);
-                    if ((key >> 8) > Q4R) {
-                        if (!stale) break;
+                bool done = false;
+                for (int c0 = 0; c0 < n && !done; c0 += 64) {
+                    if (stale) {
                         P.update_r2();
                         Q4R = q4r(P.R2);
                         stale = false;
-                        if ((key >> 8) > Q4R) break;
                     }
-                    const int slot = (int)(key & 0xFFu);
-                    ++ntested;
-                    P4<double> p64;
-                    p64.x = S.u.c.cd[slot][0];
-                    p64.y = S.u.c.cd[slot][1];
-                    p64.z = S.u.c.cd[slot][2];
-                    p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
-                    const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
-                    if (rc == CLIP_CUT) {
-                        stale = true;
-                    } else if (rc == CLIP_OVERFLOW) {
-                        overflow = true;
-                        break;
-                    } else if (rc < 0) {
-                        corrupt = true;
-                        break;
+                    const int i = c0 + lane;
+                    const uint32_t key = (i < n) ? (c0 == 0 ? k0 : k1) : 0xFFFFFFFFu;
+                    const bool near = i < n && (key >> 8) <= Q4R;
+                    if (__ballot(near) == 0) break;
+#pragma unroll
+                    for (int s = 0; s < VPL; ++s)
+                        if (P.alive[s] & mybit) {
+                            S.P.st[s * 64 + lane][0] = P.vx[s];
+                            S.P.st[s * 64 + lane][1] = P.vy[s];
+                            S.P.st[s * 64 + lane][2] = P.vz[s];
+                            if constexpr (std::is_same<T, float>::value) S.P.ste[s * 64 + lane] = P.ve[s];
+                        }
+                    wave_sync();
+                    bool act = false;
+                    if (near) {
+                        const int slot = (int)(key & 0xFFu);
+                        const double dx = S.u.c.cd[slot][0], dy = S.u.c.cd[slot][1], dz = S.u.c.cd[slot][2];
+                        const double d2 = dx * dx + dy * dy + dz * dz;
+                        const double pd = 0.5 * d2;
+                        const double nn = sqrt(d2);
+#pragma unroll
+                        for (int s = 0; s < VPL; ++s) {
+                            uint64_t m = P.alive[s];
+                            while (m && !act) {
+                                const int k = __builtin_ctzll(m);
+                                m &= m - 1;
+                                const double vx = (double)S.P.st[s * 64 + k][0], vy = (double)S.P.st[s * 64 + k][1],
+                                             vz = (double)S.P.st[s * 64 + k][2];
+                                // same rounding as the clip's own side test
+                                const double sv = fma(vx, dx, fma(vy, dy, vz * dz)) - pd;
+                                // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
+                                double marg = 0.0;
+                                if (std::is_same<T, float>::value)
+                                    marg = nn * ((double)S.P.ste[s * 64 + k] +
+                                                 1e-6 * (sqrt(vx * vx + vy * vy + vz * vz) + 0.5 * nn));
+                                act = sv > -marg;
+                            }
+                        }
                     }
+                    uint64_t am = __ballot(near && act);
+                    while (am) {
+                        const int k = __builtin_ctzll(am);
+                        am &= am - 1;
+                        const uint32_t kk = readlane_u32(key, k);
+                        if ((kk >> 8) > Q4R) {
+                            if (!stale) {
+                                done = true;
+                                break;
+                            }
+                            P.update_r2();
+                            Q4R = q4r(P.R2);
+                            stale = false;
+                            if ((kk >> 8) > Q4R) {
+                                done = true;
+                                break;
+                            }
+                        }
+                        const int slot = (int)(kk & 0xFFu);
+                        ++ntested;
+                        P4<double> p64;
+                        p64.x = S.u.c.cd[slot][0];
+                        p64.y = S.u.c.cd[slot][1];
+                        p64.z = S.u.c.cd[slot][2];
+                        p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
+                        const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
+                        if (rc == CLIP_CUT) {
+                            stale = true;
+                        } else if (rc == CLIP_OVERFLOW) {
+                            overflow = true;
+                            done = true;
+                            break;
+                        } else if (rc < 0) {
+                            corrupt = true;
+                            done = true;
+                            break;
+                        }
+                    }
+                    wave_sync();
                 }
                 if (stale) P.update_r2();
                 // particles the security criterion had to examine in this shell
