@@ -46,6 +46,8 @@ struct GridArgs {
     int64_t ncells;
     const int32_t *queue;
     int64_t queue_cap;
+    int32_t *gqueue;          // cells the normal kernel could not hold, for the large kernel
+    int64_t gqueue_cap;
     const int64_t *crow;
     const int32_t *ccnt;
     const uint8_t *cstat;
@@ -182,7 +184,7 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
 }
 
 template <typename PT4, int VPL, bool RETRY>
-__global__ void __launch_bounds__(128) k_grid(GridArgs A) {
+__global__ void __launch_bounds__(256) k_grid(GridArgs A) {
     using M = GridMem<VPL>;
     extern __shared__ char smem[];
     const int wid = threadIdx.x >> 6;
@@ -196,14 +198,16 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
     const double del[3] = {1e-12 * h[0], 1e-12 * h[1], 1e-12 * h[2]};  // grid-line offset
     const double hv = h[0] * h[1] * h[2];
     const int dims[3] = {A.nx, A.ny, A.nz};
-    const int64_t ntodo = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : A.ncells;
+    const int64_t nq = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : 0;
+    const int64_t ntodo =
+        RETRY ? nq + (int64_t)min((uint64_t)A.counters[CTR_GRID_Q], (uint64_t)A.gqueue_cap) : A.ncells;
 
     for (;;) {
         int64_t w = 0;
         if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_GRID_RETRY : CTR_GRID], 1u);
         w = (int64_t)uni_i((int)__shfl((long long)w, 0));
         if (w >= ntodo) break;
-        const int32_t c = uni_i(RETRY ? A.queue[w] : (int32_t)w);
+        const int32_t c = uni_i(RETRY ? (w < nq ? A.queue[w] : A.gqueue[w - nq]) : (int32_t)w);
         const uint8_t st = A.cstat[c];
         if (!RETRY && (st & VT_CELL_RETRIED)) continue;
         if (st & VT_CELL_FAILED) continue;
@@ -242,32 +246,67 @@ __global__ void __launch_bounds__(128) k_grid(GridArgs A) {
                 bhi[a] = it.lo[a] + it.L[a] - xs[a];
             }
         }
-        // ---- rebuild the cell from its facets
+        // ---- rebuild the cell from its facets.  The planes are loaded lane-parallel; the
+        // normal kernel applies them nearest first (the cell then stays close to its final
+        // size, 64 vertices suffice), the large kernel in stored order.  A cell that still
+        // outgrows the normal kernel goes to the large one.
         Poly<double, VPL> P;
         P.init_box(S.P, blo, bhi);
-        bool bad = false;
+        bool bad = false, over = false;
         const int64_t row = A.crow[c];
         const int32_t cnt = A.ccnt[c];
-        for (int32_t t = 0; t < cnt; ++t) {
-            const int32_t j = A.stage_ids[row + t];
-            double px, py, pz;
-            gpos<PT4>(A.spos, j, px, py, pz);
-            P4<double> p;
-            p.x = px - sx;
-            p.y = py - sy;
-            p.z = pz - sz;
-            if (it.periodic) {
-                p.x -= it.L[0] * rint(p.x / it.L[0]);
-                p.y -= it.L[1] * rint(p.y / it.L[1]);
-                p.z -= it.L[2] * rint(p.z / it.L[2]);
+        for (int32_t t0 = 0; t0 < cnt && !bad && !over; t0 += 64) {
+            const int32_t t = t0 + lane;
+            double qx = 0.0, qy = 0.0, qz = 0.0;
+            int32_t qj = -1;
+            uint64_t key = ~0ull;
+            if (t < cnt) {
+                qj = A.stage_ids[row + t];
+                gpos<PT4>(A.spos, qj, qx, qy, qz);
+                qx -= sx;
+                qy -= sy;
+                qz -= sz;
+                if (it.periodic) {
+                    qx -= it.L[0] * rint(qx / it.L[0]);
+                    qy -= it.L[1] * rint(qy / it.L[1]);
+                    qz -= it.L[2] * rint(qz / it.L[2]);
+                }
+                const float d2f = (float)(qx * qx + qy * qy + qz * qz);
+                key = RETRY ? (uint64_t)lane : (((uint64_t)__float_as_uint(d2f) << 32) | (uint64_t)lane);
             }
-            p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
-            const int rc = P.clip(S.P, p, j);
-            if (rc < 0) {
-                if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
-                bad = true;
-                break;
+            if (!RETRY) {
+                uint64_t kk[1] = {key};
+                bitonic_u64<1>(kk);
+                key = kk[0];
             }
+            const int nin = min(64, cnt - t0);
+            for (int i = 0; i < nin; ++i) {
+                const int src = (int)(readlane_u32((uint32_t)(key & 0xFFFFFFFFull), i) & 63u);
+                P4<double> p;
+                p.x = __shfl(qx, src);
+                p.y = __shfl(qy, src);
+                p.z = __shfl(qz, src);
+                p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
+                const int32_t j = __shfl(qj, src);
+                const int rc = P.clip(S.P, p, j);
+                if (rc == CLIP_OVERFLOW && !RETRY) {
+                    over = true;
+                    break;
+                }
+                if (rc < 0) {
+                    if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
+                    bad = true;
+                    break;
+                }
+            }
+        }
+        if (over) {
+            if (lane == 0) {
+                const uint32_t qi = atomicAdd(&A.counters[CTR_GRID_Q], 1u);
+                if ((int64_t)qi < A.gqueue_cap) A.gqueue[qi] = c;
+                else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+            }
+            continue;
         }
         if (bad) {
             if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
@@ -490,7 +529,7 @@ static hipError_t launch_grid_one(vt_ctx *c, GridArgs &a, int wpb) {
     int ncu = 0;
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
     if (ncu <= 0) ncu = 256;
-    int64_t blocks = RETRY ? (int64_t)ncu : (int64_t)ncu * 8 / wpb;
+    int64_t blocks = RETRY ? (int64_t)ncu : (int64_t)ncu * 16 / wpb;
     kern<<<dim3((unsigned)blocks), dim3(64 * wpb), lds, c->stream>>>(a);
     return hipGetLastError();
 }
@@ -498,7 +537,7 @@ static hipError_t launch_grid_one(vt_ctx *c, GridArgs &a, int wpb) {
 hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz, double *grid) {
     const int64_t ng = (int64_t)nx * ny * nz;
     k_zero_f64<<<(ng + 255) / 256, 256, 0, c->stream>>>(grid, ng);
-    hipError_t ez = vt_launch_zero_u32(c->counters + CTR_GRID, 2, c->stream);
+    hipError_t ez = vt_launch_zero_u32(c->counters + CTR_GRID, CTR_GRID_Q - CTR_GRID + 1, c->stream);
     if (ez != hipSuccess) return ez;
     GridArgs a;
     a.spos = c->spos;
@@ -507,6 +546,8 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.ncells = c->n_owned;
     a.queue = c->queue;
     a.queue_cap = c->cap_retry;
+    a.gqueue = c->gqueue;
+    a.gqueue_cap = c->cap_retry;
     a.crow = c->crow;
     a.ccnt = c->ccnt;
     a.cstat = c->cstat;
@@ -522,10 +563,10 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.nz = nz;
     hipError_t e;
     if (c->dtype == VT_F32) {
-        e = launch_grid_one<float4, 2, false>(c, a, 2);
+        e = launch_grid_one<float4, 1, false>(c, a, 4);
         if (e == hipSuccess) e = launch_grid_one<float4, 4, true>(c, a, 1);
     } else {
-        e = launch_grid_one<double4, 2, false>(c, a, 2);
+        e = launch_grid_one<double4, 1, false>(c, a, 4);
         if (e == hipSuccess) e = launch_grid_one<double4, 4, true>(c, a, 1);
     }
     return e;

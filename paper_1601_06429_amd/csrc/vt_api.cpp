@@ -54,6 +54,7 @@ void free_all(vt_ctx *c) {
     dfree(c->stage_area);
     dfree(c->stage_cen);
     dfree(c->queue);
+    dfree(c->gqueue);
     dfree(c->counters);
     dfree(c->rowoff);
     dfree(c->row2cell);
@@ -212,6 +213,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
             TRY(dalloc(&c->stage_cen, 3 * slots));
         }
         TRY(dalloc(&c->queue, retry_need));
+        TRY(dalloc(&c->gqueue, retry_need));
         TRY(dalloc(&c->counters, CTR_COUNT));
         TRY(dalloc(&c->rowoff, NO + 1));
         c->cap_total = NT;

@@ -31,6 +31,7 @@
 #define CTR_GRID 7        // grid deposit work counters (two words)
 #define CTR_GRID_RETRY 8
 #define CTR_DEBUG 9        // bit k set: a clip in the grid kernel returned -k (diagnostics)
+#define CTR_GRID_Q 10      // grid deposit: cells handed from the normal to the large kernel
 #define CTR_COUNT 12
 
 // per-item description on the device
@@ -91,6 +92,7 @@ struct vt_ctx {
     double *stage_area = nullptr;
     double *stage_cen = nullptr;   // 3 per facet
     int32_t *queue = nullptr;
+    int32_t *gqueue = nullptr;     // grid deposit overflow queue
     uint32_t *counters = nullptr;  // CTR_*
     // post-processing
     int64_t *rowoff = nullptr;     // facet offsets in output-row order (n_owned + 1)
