@@ -99,7 +99,7 @@ def batched_forms(torch, vt, reps=5):
     """64 uneven ghost-buffered sub-volumes in one build: eager vs HIP-graph replay, FP64 vs mixed."""
     from paper_1601_06429_amd import workloads as wl
 
-    items = wl.workload4()
+    items = wl.batched64()
     worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
     pos, desc, gid = vt.pack_worlds(worlds)
     t = torch.from_numpy(pos).cuda()
@@ -167,12 +167,12 @@ def load_workload(name):
     from paper_1601_06429_amd import workloads as wl
 
     if name == "clustered2m":
-        return wl.workload2()
+        return wl.clustered2m()
     if name == "uniform4096":
-        return wl.workload1()
+        return wl.uniform4096()
     if name == "lattice16m":
-        return wl.workload3()
-    return wl.workload5()
+        return wl.lattice_halos16m()
+    return wl.diff262k()
 
 
 def main():
@@ -181,8 +181,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
-              "described in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path; got --gpus %d" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -144,9 +144,9 @@ vt_status vt_cells(vt_ctx *ctx, double *volume, int64_t *nbr_off, int32_t *nbr_i
 vt_status vt_density(vt_ctx *ctx, const void *mass, vt_dtype dtype, double *rho, void *stream);
 
 /*
- * vt_gradient -- density gradient per owned particle "from density and
- * neighbouring information" (section 2).  The paper gives no formula; this is
- * the unweighted least-squares fit over the Voronoi neighbours:
+ * vt_gradient -- density gradient per owned particle, built from the densities
+ * and the neighbour lists (section 2).  The paper gives no formula; this is the
+ * unweighted least-squares fit over the Voronoi neighbours:
  *   grad_i = G^-1 b,  G = sum_j D_ij D_ij^T,  b = sum_j (rho_j - rho_i) D_ij,
  * D_ij the separation (minimum image in periodic boxes).
  *   rho   device, n_total doubles indexed like pos (ghost entries are used

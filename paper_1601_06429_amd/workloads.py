@@ -7,17 +7,17 @@ about 3.5M and 27.5M particles, a halo catalogue and an SDSS-like mock, paper
 sections 2-3) are not available; these generators stand in for them with the
 clustering the workloads prescribe: a uniform background plus NFW-like halos.
 
-Workloads (seed = 20160126 + workload number):
-  1  4096 points, i.i.d. uniform in the periodic unit cube, FP64, unit masses.
-  2  2,097,152 points in a periodic box of side 100, FP32: half uniform, half in
+Workloads (seeds in SEEDS):
+  uniform4096       4096 points, i.i.d. uniform in the periodic unit cube, FP64, unit masses.
+  clustered2m       2,097,152 points in a periodic box of side 100, FP32: half uniform, half in
      200 NFW-like halos (concentration 5-15, radius 0.5-3, masses log-uniform
      over two decades), unit masses; density deposited on a 256^3 grid.
-  3  16,777,216 points: 256^3 lattice in the periodic unit box with Gaussian
+  lattice_halos16m  16,777,216 points: 256^3 lattice in the periodic unit box with Gaussian
      displacements (sigma = 0.3 spacing), 20% of points replaced by 1000 NFW-like
      halos of mean overdensity 1e2-1e4, FP32, unit masses.
-  4  64 cuboid sub-volumes of 1e4-1e6 owned points (log-uniform), workload-2
+  batched64         64 cuboid sub-volumes of 1e4-1e6 owned points (log-uniform), clustered-2M
      density and mix, each with a ghost buffer of 3 mean spacings.
-  5  262,144 points, workload-2 mix scaled to the periodic unit cube, plus a
+  diff262k          262,144 points, the clustered mix scaled to the periodic unit cube, plus a
      smooth sinusoidal target density for a density-matching loss.
 """
 from __future__ import annotations
@@ -28,10 +28,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 SEED_BASE = 20160126
+# one seed per workload (kept stable so that stored results stay comparable)
+SEEDS = {"uniform4096": SEED_BASE + 1, "clustered2m": SEED_BASE + 2, "lattice_halos16m": SEED_BASE + 3,
+         "batched64": SEED_BASE + 4, "diff262k": SEED_BASE + 5}
 
 
-def rng_for(workload: int) -> np.random.Generator:
-    return np.random.default_rng(SEED_BASE + int(workload))
+def rng_for(name: str) -> np.random.Generator:
+    return np.random.default_rng(SEEDS[name])
 
 
 # --------------------------------------------------------------------------
@@ -164,8 +167,8 @@ def uniform_box(n, length=1.0, seed=0, dtype=np.float64, name="uniform"):
     return Workload(name, p, np.ones(n, dtype=np.float64), np.zeros(3), np.full(3, L))
 
 
-def workload1():
-    rng = rng_for(1)
+def uniform4096():
+    rng = rng_for("uniform4096")
     n = 4096
     p = rng.random((n, 3))
     p = redraw_duplicates(rng, p, 0.0, 1.0, np.float64)
@@ -193,15 +196,15 @@ def clustered_box(rng, n, length, n_halo, r_range, conc_range=(5.0, 15.0), dtype
     return p, info
 
 
-def workload2(n=2_097_152):
-    rng = rng_for(2)
+def clustered2m(n=2_097_152):
+    rng = rng_for("clustered2m")
     L = 100.0
     p, info = clustered_box(rng, n, L, 200, (0.5, 3.0))
     return Workload("clustered-2M-fp32", p, np.ones(n), np.zeros(3), np.full(3, L), True, (256, 256, 256), info)
 
 
-def workload3(side=256):
-    rng = rng_for(3)
+def lattice_halos16m(side=256):
+    rng = rng_for("lattice_halos16m")
     n = side ** 3
     g = (np.arange(side, dtype=np.float64) + 0.5) / side
     p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
@@ -249,9 +252,9 @@ def ghost_width(border_factor, spacing):
     return float(border_factor) * float(spacing)
 
 
-def workload4(n_items=64, n_range=(1e4, 1e6), border_factor=3.0, seed_offset=0):
-    rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
-    s = 100.0 / 2_097_152 ** (1.0 / 3.0)   # workload-2 mean spacing, 0.78125
+def batched64(n_items=64, n_range=(1e4, 1e6), border_factor=3.0, seed_offset=0):
+    rng = np.random.default_rng(SEEDS["batched64"] + seed_offset)
+    s = 100.0 / 2_097_152 ** (1.0 / 3.0)   # mean spacing of the clustered 2M box, 0.78125
     nbar = 1.0 / s ** 3
     w = ghost_width(border_factor, s)
     items = []
@@ -283,8 +286,8 @@ def workload4(n_items=64, n_range=(1e4, 1e6), border_factor=3.0, seed_offset=0):
     return items
 
 
-def workload5(n=262_144):
-    rng = rng_for(5)
+def diff262k(n=262_144):
+    rng = rng_for("diff262k")
     s2 = 100.0 / 2_097_152 ** (1.0 / 3.0)
     s5 = 1.0 / n ** (1.0 / 3.0)
     scale = s5 / s2

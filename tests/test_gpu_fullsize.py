@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def lattice16m():
-    return wl.workload3()
+    return wl.lattice_halos16m()
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -57,7 +57,7 @@ def _target(torch, x, lam, phi, amp, mean):
 
 def test_diff262k_adjoint_vs_finite_differences(vt, torch_cuda):
     torch = torch_cuda
-    w = wl.workload5()
+    w = wl.diff262k()
     n = w.n
     lam, phi, amp = w.extra["target_lambda"], w.extra["target_phase"], w.extra["target_amplitude"]
     mean = float(w.mass.sum())

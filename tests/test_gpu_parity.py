@@ -44,7 +44,7 @@ def compare_rows(cells, ref, rows, tol, label=""):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_uniform_4096_all_cells(vt, torch_cuda, oracle, precision):
-    w = wl.workload1()
+    w = wl.uniform4096()
     ctx, code, cells = run(vt, torch_cuda, w.pos, w.box_lo, w.box_hi, precision=precision)
     assert code == 0
     ref = oracle.cells(w.pos, w.box_lo, w.box_hi)
@@ -94,7 +94,7 @@ def test_neighbour_symmetry_and_box_sum(vt, torch_cuda):
 
 
 def test_determinism(vt, torch_cuda):
-    w = wl.workload1()
+    w = wl.uniform4096()
     _, _, a = run(vt, torch_cuda, w.pos, w.box_lo, w.box_hi)
     _, _, b = run(vt, torch_cuda, w.pos, w.box_lo, w.box_hi)
     assert torch_cuda.equal(a.volume, b.volume)
@@ -155,7 +155,7 @@ def test_large_cell_uses_big_kernel(vt, torch_cuda, oracle):
 def test_batched_items_match_oracle(vt, torch_cuda, oracle, precision):
     """Uneven clustered sub-volumes with ghost buffers in one build; every owned cell
     against the oracle run on that item's own bounded world."""
-    items = wl.workload4(n_items=6, n_range=(1500, 6000), seed_offset=1)
+    items = wl.batched64(n_items=6, n_range=(1500, 6000), seed_offset=1)
     worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
     pos, desc, gid = vt.pack_worlds(worlds)
     ctx = vt.Context().vt_build(torch_cuda.from_numpy(pos).cuda(), desc,
@@ -185,7 +185,7 @@ def test_batched_graph_capture_replays(vt, torch_cuda):
     """build + CSR + density captured once in a HIP graph and replayed on moved positions;
     every replay must equal an eager build of the same positions."""
     torch = torch_cuda
-    items = wl.workload4(n_items=5, n_range=(1500, 6000), seed_offset=2)
+    items = wl.batched64(n_items=5, n_range=(1500, 6000), seed_offset=2)
     worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
     pos, desc, gid = vt.pack_worlds(worlds)
     t = torch.from_numpy(pos).cuda()
@@ -236,7 +236,7 @@ def test_batched_graph_capture_replays(vt, torch_cuda):
 
 def test_autotune_picks_a_candidate_and_results_do_not_depend_on_it(vt, torch_cuda):
     torch = torch_cuda
-    items = wl.workload4(n_items=4, n_range=(1500, 6000), seed_offset=3)
+    items = wl.batched64(n_items=4, n_range=(1500, 6000), seed_offset=3)
     pos, desc, gid = vt.pack_worlds([(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items])
     t = torch.from_numpy(pos).cuda()
     g = torch.from_numpy(gid).cuda()
@@ -256,7 +256,7 @@ def test_autotune_picks_a_candidate_and_results_do_not_depend_on_it(vt, torch_cu
 
 # ---------------------------------------------------------------- derived outputs
 def test_gradient_matches_oracle(vt, torch_cuda, oracle):
-    w = wl.workload1()
+    w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
     cells = ctx.vt_cells()
@@ -287,7 +287,7 @@ def test_gradient_linear_field_bounded(vt, torch_cuda):
 
 @pytest.mark.parametrize("dims", [(16, 16, 16), (32, 24, 20)])
 def test_grid_matches_oracle(vt, torch_cuda, oracle, dims):
-    w = wl.workload1()
+    w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
     ctx.vt_cells()
@@ -342,7 +342,7 @@ def test_grid_large_cell(vt, torch_cuda, oracle):
 
 
 def test_grid_unit_field_and_aligned_lattice(vt, torch_cuda):
-    w = wl.workload1()
+    w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
     ctx.vt_cells()
@@ -366,7 +366,7 @@ def test_grid_unit_field_and_aligned_lattice(vt, torch_cuda):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_backward_matches_oracle_adjoint(vt, torch_cuda, oracle, precision):
-    w = wl.workload1()
+    w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision, want_faces=True)
     ctx.vt_cells()
@@ -379,7 +379,7 @@ def test_backward_matches_oracle_adjoint(vt, torch_cuda, oracle, precision):
 
 
 def test_backward_requires_faces(vt, torch_cuda):
-    w = wl.workload1()
+    w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), want_faces=False)
     with pytest.raises(vt.VTError) as e:

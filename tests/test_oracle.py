@@ -88,7 +88,7 @@ def test_fcc_rhombic_dodecahedra(oracle):
 # ---------------------------------------------------------------- random sets
 @pytest.fixture(scope="module")
 def uniform_cells(oracle):
-    w = wl.workload1()
+    w = wl.uniform4096()
     return w, oracle.cells(w.pos, w.box_lo, w.box_hi)
 
 
@@ -323,7 +323,7 @@ def test_benchmark_workload_cells_exact(oracle):
     left a duplicate facet; their volumes must equal the exact rational volumes."""
     from scipy.spatial import cKDTree
 
-    w = wl.workload2()
+    w = wl.clustered2m()
     p64 = w.pos.astype(np.float64)
     rows = np.array([2028842, 2055653])
     c = oracle.cells(p64, w.box_lo, w.box_hi, query=rows)
@@ -461,9 +461,9 @@ def test_buffer_width_worked_example():
 
 
 def test_workload_shapes():
-    w1 = wl.workload1()
+    w1 = wl.uniform4096()
     assert w1.pos.shape == (4096, 3) and w1.pos.dtype == np.float64
     assert wl.duplicate_rows(w1.pos).size == 0
-    w5 = wl.workload5(n=4096)
+    w5 = wl.diff262k(n=4096)
     assert w5.pos.dtype == np.float32 and np.all((w5.pos >= 0) & (w5.pos < 1))
     assert wl.duplicate_rows(w5.pos).size == 0
