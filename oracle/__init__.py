@@ -16,9 +16,9 @@ code", Astronomy & Computing):
 
 Readings where the paper is silent (documented with the design notes):
   * gradient: unweighted least squares over the Voronoi neighbours,
-    grad = G^-1 b, G = sum D D^T, b = sum (rho_j - rho_i) D (parity unpinned
-    against the paper's own code, which is not available; pinned against the
-    exact-recovery property for linear fields);
+    grad = G^-1 b, G = sum D D^T, b = sum (rho_j - rho_i) D (the paper's own
+    formula is not given; pinned by exact recovery of linear fields and a
+    zero gradient on lattices);
   * grid: exact volume average of the piecewise-constant Voronoi density over
     each voxel (pinned by mass conservation and exact lattice cases);
   * adjoint: dV_i/dx_j = A_ij (x_j - c_ij) / d_ij and
