@@ -147,7 +147,7 @@ __device__ __forceinline__ void load_pos(const void *spos, int32_t j, double &x,
 }
 
 template <typename T, typename PT4, int VPL, bool RETRY>
-__global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
+__device__ __forceinline__ void clip_cells(const ClipArgs &A) {
     using M = ClipMem<T, VPL>;
     constexpr int VMAX = 64 * VPL;
     extern __shared__ char smem[];
@@ -771,10 +771,23 @@ __global__ void __launch_bounds__(256) k_clip(ClipArgs A) {
     }
 }
 
+// The fast kernel is register-capped at three resident waves per SIMD: the extra
+// occupancy hides LDS latency better than the few spills cost.  The large kernel
+// (rare cells, four vertices per lane) keeps its registers.
+template <typename T, typename PT4>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_clip(ClipArgs A) {
+    clip_cells<T, PT4, 1, false>(A);
+}
+
+template <typename T, typename PT4>
+__global__ void __launch_bounds__(256) k_clip_large(ClipArgs A) {
+    clip_cells<T, PT4, 4, true>(A);
+}
+
 template <typename T, typename PT4, int VPL, bool RETRY>
 static hipError_t launch_one(vt_ctx *c, ClipArgs &a, int wpb) {
     const size_t lds = sizeof(ClipMem<T, VPL>) * (size_t)wpb;
-    auto kern = k_clip<T, PT4, VPL, RETRY>;
+    auto kern = RETRY ? k_clip_large<T, PT4> : k_clip<T, PT4>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int ncu = 0;
