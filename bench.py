@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-variants", action="store_true", help="skip the mixed/fp64 forward comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-item form")
+    ap.add_argument("--no-tune", action="store_true", help="library default launch options instead of the autotuner's")
     ap.add_argument("--fwd-only", action="store_true", help="time only vt_build + vt_cells + vt_density")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (traffic calibration for rocprofv3 counters)")
@@ -198,8 +199,10 @@ def main():
     items = vt.whole_box(w.n, w.box_lo, w.box_hi, True)
     N = w.n
 
+    # launch options from the library's autotuner (untimed; results do not depend on them)
+    tuned = {} if args.no_tune else vt.autotune.tune(vt.Context, pos, items, precision=prec, reps=1)[0]
     ctx = vt.Context()
-    ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=True)
+    ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=True, **tuned)
     code, nnz, retried, incomplete = ctx.vt_query()
     if code != 0:
         raise SystemExit("build failed: %s" % vt.STATUS_NAMES.get(code))
@@ -225,7 +228,7 @@ def main():
     def step(record):
         if record:
             ev[0].record()
-        ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=record)
+        ctx.vt_build(pos, items, precision=prec, want_faces=True, timing=record, **tuned)
         if record:
             ev[1].record()
         ctx.vt_cells_into(vol, off, ids, st)
@@ -296,7 +299,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_cells": N, "box": float(w.box_len[0]), "positions": str(w.pos.dtype),
                    "grid": list(grid_dims) if not args.fwd_only else None, "precision": args.precision,
-                   "step": "build+cells+density" + ("" if args.fwd_only else "+gradient+grid+backward")},
+                   "step": "build+cells+density" + ("" if args.fwd_only else "+gradient+grid+backward"),
+                   "launch_options": tuned or "defaults"},
         "fwd_cells_per_s": N / (fwd_ms * 1e-3),
         "bwd_cells_per_s": (N / (stage_ms[5] * 1e-3)) if not args.fwd_only else None,
         "stage_ms": {"build": stage_ms[0], "cells": stage_ms[1], "density": stage_ms[2],
@@ -316,20 +320,22 @@ def main():
         # forward-only comparison of the two precisions at the same accuracy bar
         var = {}
         for name, p in (("fp64", vt.PREC_FP64), ("mixed", vt.PREC_MIXED)):
+            opts = {} if args.no_tune else vt.autotune.tune(vt.Context, pos, items, precision=p, reps=1)[0]
             c2 = vt.Context()
             for _ in range(2):
-                c2.vt_build(pos, items, precision=p, want_faces=False)
+                c2.vt_build(pos, items, precision=p, want_faces=False, **opts)
             torch.cuda.synchronize()
             ta = time.perf_counter()
             reps = 5
             for _ in range(reps):
-                c2.vt_build(pos, items, precision=p, want_faces=False)
+                c2.vt_build(pos, items, precision=p, want_faces=False, **opts)
                 c2.vt_cells_into(vol, off, ids, st)
                 c2.vt_density(mass, out=rho)
             torch.cuda.synchronize()
             tb = time.perf_counter()
             code2 = c2.vt_query()[0]
-            var[name] = {"fwd_cells_per_s": N * reps / (tb - ta), "status": vt.STATUS_NAMES.get(code2)}
+            var[name] = {"fwd_cells_per_s": N * reps / (tb - ta), "status": vt.STATUS_NAMES.get(code2),
+                         "launch_options": opts or "defaults"}
             del c2
         out["precision_variants"] = var
 
