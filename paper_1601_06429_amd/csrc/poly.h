@@ -425,8 +425,26 @@ struct Poly {
             }
             S.ptag[q] = tag;
         }
-        // 4. cut edges -> staging triples (a, b, p) in rank order, then one new
-        //    vertex per lane: the intersection of its three planes
+        // 4. remove the clipped vertices from every face mask (the edge masks above were
+        //    read first; LDS operations of one wavefront execute in order), noting which
+        //    faces keep a vertex: those and the new face are the faces alive afterwards
+        wave_sync();
+        uint64_t keep[VPL];
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            const int f = r * 64 + lane;
+            bool kept = false;
+            if (fa[r] & mybit) {
+#pragma unroll
+                for (int ww = 0; ww < VPL; ++ww) {
+                    const uint64_t m = S.fm[f][ww] & ~Mk[ww];
+                    S.fm[f][ww] = m;
+                    kept |= m != 0ull;
+                }
+            }
+            keep[r] = __ballot(kept);
+        }
+        // 5. cut edges -> staging triples (a, b, p) in rank order
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             if (emask[s]) {
@@ -439,71 +457,46 @@ struct Poly {
             }
         }
         wave_sync();
-        for (int r0 = 0; r0 < NB; r0 += 64) {
-            const int k = r0 + lane;
-            if (k < NB) {
-                const uint32_t t = S.stt[k];
-                const int fa_ = t & 0xFF, fb_ = (t >> 8) & 0xFF;
-                T wx, wy, wz;
-                if constexpr (MIXED) {
-                    P4<float> pa = S.pl32[fa_], pb = S.pl32[fb_];
-                    float det = intersect3<float>(pa, pb, p, wx, wy, wz);
-                    float kap = S.pln[fa_] * S.pln[fb_] * pnorm / fabsf(det);
-                    float wn = sqrtf(wx * wx + wy * wy + wz * wz);
-                    float err = 16.f * U32 * (kap * (S.plh[fa_] + S.plh[fb_] + ph + wn) + wn);
-                    if (!(err < 1e30f)) err = 1e30f;
-                    S.ste[k] = err;
-                } else {
-                    P4<double> pa = S.pl64[fa_], pb = S.pl64[fb_];
-                    intersect3<double>(pa, pb, p64, wx, wy, wz);
-                }
-                S.st[k][0] = wx;
-                S.st[k][1] = wy;
-                S.st[k][2] = wz;
-            }
-        }
-        wave_sync();
-        // 5. remove the clipped vertices from every face mask
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            int f = r * 64 + lane;
-            if (fa[r] & mybit) {
-#pragma unroll
-                for (int ww = 0; ww < VPL; ++ww) S.fm[f][ww] &= ~Mk[ww];
-            }
-        }
-        wave_sync();
-        // 6. new vertices into free lanes; their faces gain them
+        // 6. the r-th free lane takes the r-th new vertex: it computes the vertex itself as
+        //    the intersection of its three planes, and joins the masks of its two old faces
         int rank0 = 0;
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
-            uint64_t F = ~alive[s] | Mk[s];
-            int r = rank0 + __popcll(F & lt);
-            bool got = ((F & mybit) != 0) && r < NB;
+            const uint64_t F = ~alive[s] | Mk[s];
+            const int r = rank0 + __popcll(F & lt);
+            const bool got = ((F & mybit) != 0) && r < NB;
             if (got) {
-                vx[s] = S.st[r][0];
-                vy[s] = S.st[r][1];
-                vz[s] = S.st[r][2];
-                vt[s] = S.stt[r];
-                if constexpr (MIXED) ve[s] = S.ste[r];
-                atomicOr((unsigned long long *)&S.fm[vt[s] & 0xFF][s], (unsigned long long)mybit);
-                atomicOr((unsigned long long *)&S.fm[(vt[s] >> 8) & 0xFF][s], (unsigned long long)mybit);
+                const uint32_t t = S.stt[r];
+                const int fa_ = t & 0xFF, fb_ = (t >> 8) & 0xFF;
+                T wx, wy, wz;
+                if constexpr (MIXED) {
+                    const P4<float> pa = S.pl32[fa_], pb = S.pl32[fb_];
+                    const float det = intersect3<float>(pa, pb, p, wx, wy, wz);
+                    const float kap = S.pln[fa_] * S.pln[fb_] * pnorm / fabsf(det);
+                    const float wn = sqrtf(wx * wx + wy * wy + wz * wz);
+                    float err = 16.f * U32 * (kap * (S.plh[fa_] + S.plh[fb_] + ph + wn) + wn);
+                    if (!(err < 1e30f)) err = 1e30f;
+                    ve[s] = err;
+                } else {
+                    const P4<double> pa = S.pl64[fa_], pb = S.pl64[fb_];
+                    intersect3<double>(pa, pb, p64, wx, wy, wz);
+                }
+                vx[s] = wx;
+                vy[s] = wy;
+                vz[s] = wz;
+                vt[s] = t;
+                atomicOr((unsigned long long *)&S.fm[fa_][s], (unsigned long long)mybit);
+                atomicOr((unsigned long long *)&S.fm[fb_][s], (unsigned long long)mybit);
             }
-            uint64_t nm = __ballot(got);
+            const uint64_t nm = __ballot(got);
             alive[s] = (alive[s] & ~Mk[s]) | nm;
             if (lane == 0) S.fm[q][s] = nm;
             rank0 += __popcll(F);
         }
         wave_sync();
-        // 7. faces still alive
+        // 7. faces alive: those that kept a vertex, and the new one
 #pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            int f = r * 64 + lane;
-            bool al = false;
-#pragma unroll
-            for (int ww = 0; ww < VPL; ++ww) al |= S.fm[f][ww] != 0ull;
-            fa[r] = __ballot(al);
-        }
+        for (int r = 0; r < VPL; ++r) fa[r] = keep[r] | ((q >> 6) == r ? (1ull << (q & 63)) : 0ull);
         // R2 is left as it was: an upper bound (the cell only shrinks); callers
         // refresh it with update_r2() when they need the tighter value
         return CLIP_CUT;
