@@ -59,6 +59,8 @@ struct ClipArgs {
     int64_t *crow;
     uint8_t *cstat;
     int32_t *cnv, *cnp, *cnt;
+    int32_t *ctopo;           // fast kernel: topology record per cell (VT_TOPO_STRIDE words)
+    int32_t *cnf;             // faces in the record, 0 = no record
     int32_t *stage_ids;
     double *stage_area;
     double *stage_cen;
@@ -595,6 +597,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         if (overflow && !RETRY) {
             // hand the cell to the large-capacity kernel
             if (lane == 0) {
+                A.cnf[cslot] = 0;
                 uint32_t qi = atomicAdd(&A.counters[CTR_QUEUE], 1u);
                 if ((int64_t)qi < A.queue_cap) A.queue_out[qi] = cslot;
                 else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
@@ -613,6 +616,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 A.crow[cslot] = row;
                 A.cstat[cslot] = VT_CELL_FAILED | (RETRY ? VT_CELL_RETRIED : 0);
                 A.cnv[cslot] = 0;
+                A.cnf[cslot] = 0;
                 A.cnp[cslot] = nplanes;
                 A.cnt[cslot] = ntested;
             }
@@ -735,6 +739,25 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             }
         }
         const bool any_wall = __ballot(wall) != 0;
+        // topology record for the grid deposit, which then rebuilds the cell without clipping:
+        // the tags of the faces in slot order, then each vertex's face triple as ranks in that
+        // order (the triple's order, which fixes the orientation, is kept)
+        int32_t nf_rec = 0;
+        if constexpr (!RETRY && VPL == 1) {
+            const uint64_t fam = P.fa[0];
+            const int nf = __popcll(fam);
+            if (nf <= VT_TOPO_FACES) {
+                const int64_t tb = (int64_t)cslot * VT_TOPO_STRIDE;
+                if (fam & mybit) A.ctopo[tb + __popcll(fam & lt)] = S.P.ptag[lane];
+                if (P.alive[0] & mybit) {
+                    const uint32_t t = P.vt[0];
+                    auto rk = [&](uint32_t f) -> uint32_t { return (uint32_t)__popcll(fam & ((1ull << (f & 63u)) - 1ull)); };
+                    const uint32_t tr = rk(t & 0xFFu) | (rk((t >> 8) & 0xFFu) << 8) | (rk((t >> 16) & 0xFFu) << 16);
+                    A.ctopo[tb + VT_TOPO_FACES + __popcll(P.alive[0] & lt)] = (int32_t)tr;
+                }
+                nf_rec = nf;
+            }
+        }
         if (lane == 0) {
             uint8_t st = RETRY ? VT_CELL_RETRIED : 0;
             bool incomplete = false;
@@ -764,6 +787,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             A.crow[cslot] = row;
             A.cstat[cslot] = st;
             A.cnv[cslot] = nvert;
+            A.cnf[cslot] = nf_rec;
             A.cnp[cslot] = nplanes;
             A.cnt[cslot] = ntested;
             atomicAdd((unsigned long long *)&A.counters[CTR_NNZ_LO], (unsigned long long)kept);
@@ -839,6 +863,8 @@ hipError_t vt_launch_clip(vt_ctx *c) {
     a.cnv = c->cnv;
     a.cnp = c->cnp;
     a.cnt = c->cnt;
+    a.ctopo = c->ctopo;
+    a.cnf = c->cnf;
     a.stage_ids = c->stage_ids;
     a.stage_area = c->stage_area;
     a.stage_cen = c->stage_cen;

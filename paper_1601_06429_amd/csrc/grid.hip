@@ -29,7 +29,7 @@ struct GridMem {
     static constexpr int LOOP = 3 * 64 * VPL;  // vertex-face incidences (3 per vertex)
     double vp[64 * VPL][3];  // vertex positions, grid frame (box origin at 0)
     uint32_t vt[64 * VPL];   // vertex triples
-    int16_t loop[LOOP];      // face vertex loops, counter-clockwise in (y, z)
+    double lp[LOOP][3];      // face vertex loops (seed-relative x, y, z), counter-clockwise in (y, z)
     int32_t loff[FMAX + 1];
     double fn[FMAX][4];      // face plane in the grid frame: n.g = d
     int32_t frect[FMAX][4];  // y range (j0, nj), z range (k0, nk)
@@ -53,6 +53,10 @@ struct GridArgs {
     const uint8_t *cstat;
     const double *cvol;
     const double *crad;
+    const int32_t *ctopo;     // topology records of the fast clip kernel
+    const int32_t *cnf;
+    const int32_t *cnv;
+    int64_t npos;             // sorted particles (bound of a record's face tags)
     const int32_t *stage_ids;
     const int32_t *srow;
     const double *value;
@@ -72,6 +76,37 @@ __device__ __forceinline__ void gpos(const void *spos, int32_t j, double &x, dou
 __device__ __forceinline__ int64_t wrapi(int64_t i, int n) {
     int64_t r = i % n;
     return r < 0 ? r + n : r;
+}
+
+// A cell is smaller than a quarter of the box, so its voxel indices lie within one period of
+// [0, n); the exact reduction runs only for an index that does not.
+__device__ __forceinline__ int64_t wrap1(int64_t i, int n) {
+    int64_t r = i < 0 ? i + n : (i >= n ? i - n : i);
+    if (r < 0 || r >= n) r = wrapi(i, n);
+    return r;
+}
+
+// q = a / b and a % b for 0 <= a, 1 <= b: a float quotient, then one correction step (exact for
+// a < 2^22, where the float quotient is within one of the true one); integer division above
+__device__ __forceinline__ int divmod_small(int a, int b, int &rem) {
+    int q, r;
+    if (a < (1 << 22)) {
+        q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+        r = a - q * b;
+        if (r < 0) {
+            --q;
+            r += b;
+        }
+        if (r >= b) {
+            ++q;
+            r -= b;
+        }
+    } else {
+        q = a / b;
+        r = a - q * b;
+    }
+    rem = r;
+    return q;
 }
 
 // Area A of a region D in the (y, z) plane and G = ∫∫_D (x - X) dy dz, x the
@@ -103,51 +138,82 @@ __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, dou
 }
 
 // D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0): Omega the
-// counter-clockwise loop loop[o .. o+m) of seed-relative vertices vp,
+// counter-clockwise loop lp[o .. o+m) of seed-relative vertices,
 // R = [Y0, Y0 + hy] x [Z0, Z0 + hz], H = {hs (e - ny y - nz z) > 0} if useH (the
 // part of the face above x = X), with e given for the shifted coordinates and
-// rnx = 1 / n_x.
+// rnx = 1 / n_x.  One pass over Omega's edges clips each edge to R ∩ H and, for
+// every edge, restricts R's four edges and the chord to its inner side; those
+// segments are integrated after the pass.
 template <int VPL>
 __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
                                 bool useH, double hs, double e, double ny, double nz, double X, double rnx) {
     Reg D = {0.0, 0.0};
     auto gH = [&](double y, double z) { return hs * (e - ny * y - nz * z); };
-    auto vy = [&](int k) { return S.vp[S.loop[o + k]][1] - Y0; };
-    auto vz = [&](int k) { return S.vp[S.loop[o + k]][2] - Z0; };
-    auto vx = [&](int k) { return S.vp[S.loop[o + k]][0] - X; };
-    const double Oy = vy(0), Oz = vz(0), gO = vx(0);
+    const double Oy = S.lp[o][1] - Y0, Oz = S.lp[o][2] - Z0, gO = S.lp[o][0] - X;
     auto tri = [&](double y0, double z0, double g0, double y1, double z1, double g1) {
         const double cr = (y0 - Oy) * (z1 - Oz) - (y1 - Oy) * (z0 - Oz);
         D.A += 0.5 * cr;
         D.G += cr * (gO + g0 + g1) * (1.0 / 6.0);
     };
     auto gplane = [&](double y, double z) { return gO - (ny * (y - Oy) + nz * (z - Oz)) * rnx; };
-    // (a) edges of Omega inside R ∩ H
+    // R's edges run counter-clockwise from corner r to corner r + 1
+    const double ry[5] = {0.0, hy, hy, 0.0, 0.0}, rz[5] = {0.0, 0.0, hz, hz, 0.0};
+    double rt0[4] = {0.0, 0.0, 0.0, 0.0}, rt1[4] = {1.0, 1.0, 1.0, 1.0};
+    // the chord x = X: a segment through the point of the line nearest R's centre, long
+    // enough to cross R, directed with H on its left (x - X = 0 on it), clipped to R
+    double cy0 = 0.0, cz0 = 0.0, cy1 = 0.0, cz1 = 0.0, ct0 = 0.0, ct1 = 0.0;
+    if (useH) {
+        const double nn = ny * ny + nz * nz;
+        const double cy = 0.5 * hy, cz = 0.5 * hz;
+        const double sft = (ny * cy + nz * cz - e) / nn;
+        const double py = cy - sft * ny, pz = cz - sft * nz;
+        const double L = 4.0 * (hy + hz) / sqrt(nn);
+        const double dy = -hs * nz * L, dz = hs * ny * L;
+        cy0 = py - dy;
+        cz0 = pz - dz;
+        cy1 = py + dy;
+        cz1 = pz + dz;
+        ct1 = 1.0;
+        cyrus_beck(cy0, cy1, ct0, ct1);
+        cyrus_beck(hy - cy0, hy - cy1, ct0, ct1);
+        cyrus_beck(cz0, cz1, ct0, ct1);
+        cyrus_beck(hz - cz0, hz - cz1, ct0, ct1);
+    }
+    double y0 = Oy, z0 = Oz, xa = gO;
     for (int k = 0; k < m; ++k) {
         const int k1 = (k + 1 == m) ? 0 : k + 1;
-        const double y0 = vy(k), z0 = vz(k), y1 = vy(k1), z1 = vz(k1);
-        double t0 = 0.0, t1 = 1.0;
-        cyrus_beck(y0, y1, t0, t1);
-        cyrus_beck(hy - y0, hy - y1, t0, t1);
-        cyrus_beck(z0, z1, t0, t1);
-        cyrus_beck(hz - z0, hz - z1, t0, t1);
-        if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
-        if (t0 < t1) {
-            const double dy = y1 - y0, dz = z1 - z0, xa = vx(k), dx = vx(k1) - xa;
-            tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
+        const double y1 = S.lp[o + k1][1] - Y0, z1 = S.lp[o + k1][2] - Z0, xb = S.lp[o + k1][0] - X;
+        // (a) the edge of Omega inside R ∩ H
+        {
+            double t0 = 0.0, t1 = 1.0;
+            cyrus_beck(y0, y1, t0, t1);
+            cyrus_beck(hy - y0, hy - y1, t0, t1);
+            cyrus_beck(z0, z1, t0, t1);
+            cyrus_beck(hz - z0, hz - z1, t0, t1);
+            if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
+            if (t0 < t1) {
+                const double dy = y1 - y0, dz = z1 - z0, dx = xb - xa;
+                tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
+            }
         }
+        // (b), (c): R's edges and the chord restricted to the inner side of this edge
+        const double du = y1 - y0, dv = z1 - z0;
+        auto inner = [&](double qy, double qz) { return du * (qz - z0) - dv * (qy - y0); };
+        double gc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gc[r] = inner(ry[r], rz[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cyrus_beck(gc[r], gc[(r + 1) & 3], rt0[r], rt1[r]);
+        if (useH) cyrus_beck(inner(cy0, cz0), inner(cy1, cz1), ct0, ct1);
+        y0 = y1;
+        z0 = z1;
+        xa = xb;
     }
     // (b) edges of R inside Omega ∩ H
-    const double ry[5] = {0.0, hy, hy, 0.0, 0.0}, rz[5] = {0.0, 0.0, hz, hz, 0.0};
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
         const double qy0 = ry[r], qz0 = rz[r], qy1 = ry[r + 1], qz1 = rz[r + 1];
-        double t0 = 0.0, t1 = 1.0;
-        for (int k = 0; k < m && t0 < t1; ++k) {
-            const int k1 = (k + 1 == m) ? 0 : k + 1;
-            const double py = vy(k), pz = vz(k);
-            const double du = vy(k1) - py, dv = vz(k1) - pz;
-            cyrus_beck(du * (qz0 - pz) - dv * (qy0 - py), du * (qz1 - pz) - dv * (qy1 - py), t0, t1);
-        }
+        double t0 = rt0[r], t1 = rt1[r];
         if (useH) cyrus_beck(gH(qy0, qz0), gH(qy1, qz1), t0, t1);
         if (t0 < t1) {
             const double dy = qy1 - qy0, dz = qz1 - qz0;
@@ -155,30 +221,10 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
             tri(ya, za, gplane(ya, za), yb, zb, gplane(yb, zb));
         }
     }
-    // (c) the chord x = X inside Omega ∩ R, directed with H on its left (x - X = 0 on it)
-    if (useH) {
-        const double nn = ny * ny + nz * nz;
-        const double cy = 0.5 * hy, cz = 0.5 * hz;
-        const double sft = (ny * cy + nz * cz - e) / nn;
-        const double py = cy - sft * ny, pz = cz - sft * nz;  // point of the line nearest R's centre
-        const double L = 4.0 * (hy + hz) / sqrt(nn);
-        const double dy = -hs * nz * L, dz = hs * ny * L;      // direction with H on the left
-        const double qy0 = py - dy, qz0 = pz - dz, qy1 = py + dy, qz1 = pz + dz;
-        double t0 = 0.0, t1 = 1.0;
-        cyrus_beck(qy0, qy1, t0, t1);
-        cyrus_beck(hy - qy0, hy - qy1, t0, t1);
-        cyrus_beck(qz0, qz1, t0, t1);
-        cyrus_beck(hz - qz0, hz - qz1, t0, t1);
-        for (int k = 0; k < m && t0 < t1; ++k) {
-            const int k1 = (k + 1 == m) ? 0 : k + 1;
-            const double vy0 = vy(k), vz0 = vz(k);
-            const double du = vy(k1) - vy0, dv = vz(k1) - vz0;
-            cyrus_beck(du * (qz0 - vz0) - dv * (qy0 - vy0), du * (qz1 - vz0) - dv * (qy1 - vy0), t0, t1);
-        }
-        if (t0 < t1) {
-            const double ey = qy1 - qy0, ez = qz1 - qz0;
-            tri(qy0 + t0 * ey, qz0 + t0 * ez, 0.0, qy0 + t1 * ey, qz0 + t1 * ez, 0.0);
-        }
+    // (c) the chord inside Omega ∩ R
+    if (useH && ct0 < ct1) {
+        const double ey = cy1 - cy0, ez = cz1 - cz0;
+        tri(cy0 + ct0 * ey, cz0 + ct0 * ez, 0.0, cy0 + ct1 * ey, cz0 + ct1 * ez, 0.0);
     }
     return D;
 }
@@ -246,15 +292,90 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 bhi[a] = it.lo[a] + it.L[a] - xs[a];
             }
         }
-        // ---- rebuild the cell from its facets.  The planes are loaded lane-parallel; the
-        // normal kernel applies them nearest first (the cell then stays close to its final
+        Poly<double, VPL> P;
+        bool bad = false, over = false, have = false;
+        // ---- the clip kernel's topology record, if the cell has a well-formed one: every face
+        // plane comes from its tag, every vertex is the intersection of its three planes (in the
+        // triple's order, as the clip kernel computes it), and the face masks follow from the
+        // triples.  Any index out of range sends the cell to the rebuild below.
+        if constexpr (!RETRY && VPL == 1) {
+            const int nf = A.cnf[c], nv = A.cnv[c];
+            if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64) {
+                const int64_t tb = (int64_t)c * VT_TOPO_STRIDE;
+                bool ok = true;
+                if (lane < nf) {
+                    const int32_t tag = A.ctopo[tb + lane];
+                    P4<double> p;
+                    if (tag >= 0 && (int64_t)tag < A.npos) {
+                        double qx, qy, qz;
+                        gpos<PT4>(A.spos, tag, qx, qy, qz);
+                        qx -= sx;
+                        qy -= sy;
+                        qz -= sz;
+                        if (it.periodic) {
+                            qx -= it.L[0] * rint(qx * (1.0 / it.L[0]));
+                            qy -= it.L[1] * rint(qy * (1.0 / it.L[1]));
+                            qz -= it.L[2] * rint(qz * (1.0 / it.L[2]));
+                        }
+                        p.x = qx;
+                        p.y = qy;
+                        p.z = qz;
+                        p.d = 0.5 * (qx * qx + qy * qy + qz * qz);
+                    } else if (tag < 0 && tag >= -6) {
+                        // wall -1 .. -6: -x, +x, -y, +y, -z, +z of the seed-relative box
+                        const int b = -1 - tag, a = b >> 1;
+                        const bool pos = b & 1;
+                        p.x = (a == 0) ? (pos ? 1.0 : -1.0) : 0.0;
+                        p.y = (a == 1) ? (pos ? 1.0 : -1.0) : 0.0;
+                        p.z = (a == 2) ? (pos ? 1.0 : -1.0) : 0.0;
+                        p.d = pos ? bhi[a] : -blo[a];
+                    } else {
+                        ok = false;
+                        p.x = p.y = p.z = p.d = 0.0;
+                    }
+                    S.P.pl64[lane] = p;
+                    S.P.fm[lane][0] = 0ull;
+                }
+                uint32_t t = 0, k0 = 0, k1 = 0, k2 = 0;
+                if (lane < nv) {
+                    t = (uint32_t)A.ctopo[tb + VT_TOPO_FACES + lane];
+                    k0 = t & 0xFFu;
+                    k1 = (t >> 8) & 0xFFu;
+                    k2 = (t >> 16) & 0xFFu;
+                    if ((t >> 24) || k0 >= (uint32_t)nf || k1 >= (uint32_t)nf || k2 >= (uint32_t)nf || k0 == k1 ||
+                        k1 == k2 || k0 == k2)
+                        ok = false;
+                }
+                if (__ballot(!ok) == 0ull) {
+                    wave_sync();
+                    double x = 0.0, y = 0.0, z = 0.0;
+                    if (lane < nv) {
+                        intersect3<double>(S.P.pl64[k0], S.P.pl64[k1], S.P.pl64[k2], x, y, z);
+                        atomicOr((unsigned long long *)&S.P.fm[k0][0], (unsigned long long)mybit);
+                        atomicOr((unsigned long long *)&S.P.fm[k1][0], (unsigned long long)mybit);
+                        atomicOr((unsigned long long *)&S.P.fm[k2][0], (unsigned long long)mybit);
+                    }
+                    const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
+                    if (__ballot(!fin) == 0ull) {
+                        P.vx[0] = x;
+                        P.vy[0] = y;
+                        P.vz[0] = z;
+                        P.vt[0] = t;
+                        P.alive[0] = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
+                        P.fa[0] = (1ull << nf) - 1ull;
+                        have = true;
+                    }
+                    wave_sync();
+                }
+            }
+        }
+        // ---- otherwise rebuild the cell from its facets.  The planes are loaded lane-parallel;
+        // the normal kernel applies them nearest first (the cell then stays close to its final
         // size, 64 vertices suffice), the large kernel in stored order.  A cell that still
         // outgrows the normal kernel goes to the large one.
-        Poly<double, VPL> P;
-        P.init_box(S.P, blo, bhi);
-        bool bad = false, over = false;
+        if (!have) P.init_box(S.P, blo, bhi);
         const int64_t row = A.crow[c];
-        const int32_t cnt = A.ccnt[c];
+        const int32_t cnt = have ? 0 : A.ccnt[c];
         for (int32_t t0 = 0; t0 < cnt && !bad && !over; t0 += 64) {
             const int32_t t = t0 + lane;
             double qx = 0.0, qy = 0.0, qz = 0.0;
@@ -424,9 +545,10 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 double b[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
                 int u = u0;
                 for (int k = 0; k < m && u >= 0; ++k) {
-                    S.loop[o + (rev ? m - 1 - k : k)] = (int16_t)u;
                     const double *p = S.vp[u];
+                    double *lq = S.lp[o + (rev ? m - 1 - k : k)];
                     for (int a = 0; a < 3; ++a) {
+                        lq[a] = p[a];
                         b[2 * a] = fmin(b[2 * a], p[a]);
                         b[2 * a + 1] = fmax(b[2 * a + 1], p[a]);
                     }
@@ -462,7 +584,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
         // ---- work items
         auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
             if (v == 0.0) return;
-            int64_t g = (wrapi(i, dims[0]) * dims[1] + wrapi(j, dims[1])) * dims[2] + wrapi(k, dims[2]);
+            int64_t g = (wrap1(i, dims[0]) * dims[1] + wrap1(j, dims[1])) * dims[2] + wrap1(k, dims[2]);
             unsafeAtomicAdd(&A.grid[g], val * v / hv);
         };
         for (int base = 0; base < nitem; base += 64) {
@@ -474,12 +596,11 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                     if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
                 }
                 const int q = lo;
-                int r = item - S.ipre[q];
-                const int nplane = 1 + S.fpl[q][1];
-                const int pi = r % nplane;
-                r /= nplane;
-                const int64_t jj = S.frect[q][0] + (r % S.frect[q][1]);
-                const int64_t kk = S.frect[q][2] + (r / S.frect[q][1]);
+                int pi, rj;
+                const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
+                const int rk = divmod_small(r, S.frect[q][1], rj);
+                const int64_t jj = S.frect[q][0] + rj;
+                const int64_t kk = S.frect[q][2] + rk;
                 // rectangle corner (seed-relative); integrals are taken relative to it
                 const double Y0 = jj * h[1] + del[1] - g0[1];
                 const double Z0 = kk * h[2] + del[2] - g0[2];
@@ -553,6 +674,10 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.cstat = c->cstat;
     a.cvol = c->cvol;
     a.crad = c->crad;
+    a.ctopo = c->ctopo;
+    a.cnf = c->cnf;
+    a.cnv = c->cnv;
+    a.npos = c->n_total;
     a.stage_ids = c->stage_ids;
     a.srow = c->srow;
     a.value = value;

@@ -50,6 +50,8 @@ void free_all(vt_ctx *c) {
     dfree(c->cnv);
     dfree(c->cnp);
     dfree(c->cnt);
+    dfree(c->ctopo);
+    dfree(c->cnf);
     dfree(c->stage_ids);
     dfree(c->stage_area);
     dfree(c->stage_cen);
@@ -206,6 +208,8 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
         TRY(dalloc(&c->cnv, NO));
         TRY(dalloc(&c->cnp, NO));
         TRY(dalloc(&c->cnt, NO));
+        TRY(dalloc(&c->ctopo, NO * VT_TOPO_STRIDE));
+        TRY(dalloc(&c->cnf, NO));
         const int64_t slots = NO * VT_FSTRIDE_FAST + retry_need * VT_FSTRIDE_BIG;
         TRY(dalloc(&c->stage_ids, slots));
         if (need_faces) {

@@ -12,6 +12,8 @@
 #define VT_CAND_MAX 128            // candidates per clipping pass held in LDS
 #define VT_FSTRIDE_FAST 40         // facet slots per cell, fast kernel (F <= 34 when V <= 64)
 #define VT_FSTRIDE_BIG 136         // facet slots per cell, large kernel (F <= 130 when V <= 256)
+#define VT_TOPO_FACES 40           // face-table words of a topology record (F <= 34 when V <= 64)
+#define VT_TOPO_STRIDE 104         // topology record: VT_TOPO_FACES face tags + 64 vertex triples
 
 // device status word bits
 #define VT_DEV_DUPLICATE 1u
@@ -88,6 +90,10 @@ struct vt_ctx {
     int64_t *crow = nullptr;       // staging row start
     uint8_t *cstat = nullptr;
     int32_t *cnv = nullptr, *cnp = nullptr, *cnt = nullptr;
+    // topology of each cell the fast clip kernel finished (VT_TOPO_STRIDE words per cell):
+    // face tags in face order, then vertex triples as face ranks; cnf = number of faces, 0 = none
+    int32_t *ctopo = nullptr;
+    int32_t *cnf = nullptr;
     int32_t *stage_ids = nullptr;
     double *stage_area = nullptr;
     double *stage_cen = nullptr;   // 3 per facet
