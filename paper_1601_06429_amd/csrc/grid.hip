@@ -65,6 +65,13 @@ struct GridArgs {
     int nx, ny, nz;
 };
 
+// a double held by lane l (l the same in every lane)
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = readlane_u32((uint32_t)u, l), hi = readlane_u32((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 template <typename PT4>
 __device__ __forceinline__ void gpos(const void *spos, int32_t j, double &x, double &y, double &z) {
     PT4 p = ((const PT4 *)spos)[j];
@@ -248,391 +255,420 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
     const int64_t ntodo =
         RETRY ? nq + (int64_t)min((uint64_t)A.counters[CTR_GRID_Q], (uint64_t)A.gqueue_cap) : A.ncells;
 
+    // Cells are taken GB at a time: lane l loads the scalars of the batch's cell l (the latency
+    // of those dependent loads is paid once per batch), a cell inside one voxel (its ball of
+    // radius R, the largest vertex distance, is) deposits its whole volume from its lane, and
+    // the wave then rebuilds the other cells one after another.
+    constexpr int GB = 16;
     for (;;) {
-        int64_t w = 0;
-        if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_GRID_RETRY : CTR_GRID], 1u);
-        w = (int64_t)uni_i((int)__shfl((long long)w, 0));
-        if (w >= ntodo) break;
-        const int32_t c = uni_i(RETRY ? (w < nq ? A.queue[w] : A.gqueue[w - nq]) : (int32_t)w);
-        const uint8_t st = A.cstat[c];
-        if (!RETRY && (st & VT_CELL_RETRIED)) continue;
-        if (st & VT_CELL_FAILED) continue;
-        const int32_t j0 = A.cells[c];
-        const double val = A.value[A.srow[j0]];
-        if (val == 0.0) continue;
-        double sx, sy, sz;
-        gpos<PT4>(A.spos, j0, sx, sy, sz);
-        const double xs[3] = {sx, sy, sz};
-        {
-            // a cell inside one voxel (its ball of radius R, the largest vertex distance, is)
-            // deposits its whole volume without being rebuilt
-            const double rc = A.crad[c];
-            int64_t va[3];
-            bool one = true;
-            for (int a = 0; a < 3; ++a) {
-                const double g = xs[a] - it.lo[a];
-                va[a] = (int64_t)floor((g - rc - del[a]) * ih[a]);
-                one = one && va[a] == (int64_t)floor((g + rc - del[a]) * ih[a]);
+        int64_t wb = 0;
+        if (lane == 0) wb = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_GRID_RETRY : CTR_GRID], (uint32_t)GB);
+        wb = (int64_t)uni_i((int)__shfl((long long)wb, 0));
+        if (wb >= ntodo) break;
+        const int64_t wl = wb + lane;
+        int32_t cl = 0;
+        double vl = 0.0, xl = 0.0, yl = 0.0, zl = 0.0;
+        bool todo = false;
+        if (lane < GB && wl < ntodo) {
+            cl = RETRY ? (wl < nq ? A.queue[wl] : A.gqueue[wl - nq]) : (int32_t)wl;
+            const uint8_t st = A.cstat[cl];
+            if ((RETRY || !(st & VT_CELL_RETRIED)) && !(st & VT_CELL_FAILED)) {
+                const int32_t j0 = A.cells[cl];
+                vl = A.value[A.srow[j0]];
+                if (vl != 0.0) {
+                    gpos<PT4>(A.spos, j0, xl, yl, zl);
+                    const double xq[3] = {xl, yl, zl};
+                    const double rc = A.crad[cl];
+                    int64_t va[3];
+                    bool one = true;
+                    for (int a = 0; a < 3; ++a) {
+                        const double g = xq[a] - it.lo[a];
+                        va[a] = (int64_t)floor((g - rc - del[a]) * ih[a]);
+                        one = one && va[a] == (int64_t)floor((g + rc - del[a]) * ih[a]);
+                    }
+                    if (one) {
+                        int64_t g = (wrapi(va[0], dims[0]) * dims[1] + wrapi(va[1], dims[1])) * dims[2] + wrapi(va[2], dims[2]);
+                        unsafeAtomicAdd(&A.grid[g], vl * A.cvol[cl] / hv);
+                    } else {
+                        todo = true;
+                    }
+                }
             }
-            if (one) {
+        }
+        uint64_t tm = __ballot(todo);
+        while (tm) {
+            const int l = __builtin_ctzll(tm);
+            tm &= tm - 1ull;
+            const int32_t c = (int32_t)readlane_u32((uint32_t)cl, l);
+            const double val = readlane_d(vl, l);
+            const double sx = readlane_d(xl, l), sy = readlane_d(yl, l), sz = readlane_d(zl, l);
+            const double xs[3] = {sx, sy, sz};
+            const double vscale = val / hv;
+            double blo[3], bhi[3];
+            for (int a = 0; a < 3; ++a) {
+                if (it.periodic) {
+                    blo[a] = -0.5 * it.L[a];
+                    bhi[a] = 0.5 * it.L[a];
+                } else {
+                    blo[a] = it.lo[a] - xs[a];
+                    bhi[a] = it.lo[a] + it.L[a] - xs[a];
+                }
+            }
+            Poly<double, VPL> P;
+            bool bad = false, over = false, have = false;
+            // ---- the clip kernel's topology record, if the cell has a well-formed one: every face
+            // plane comes from its tag, every vertex is the intersection of its three planes (in the
+            // triple's order, as the clip kernel computes it), and the face masks follow from the
+            // triples.  Any index out of range sends the cell to the rebuild below.
+            if constexpr (!RETRY && VPL == 1) {
+                const int nf = A.cnf[c], nv = A.cnv[c];
+                if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64) {
+                    const int64_t tb = (int64_t)c * VT_TOPO_STRIDE;
+                    bool ok = true;
+                    if (lane < nf) {
+                        const int32_t tag = A.ctopo[tb + lane];
+                        P4<double> p;
+                        if (tag >= 0 && (int64_t)tag < A.npos) {
+                            double qx, qy, qz;
+                            gpos<PT4>(A.spos, tag, qx, qy, qz);
+                            qx -= sx;
+                            qy -= sy;
+                            qz -= sz;
+                            if (it.periodic) {
+                                qx -= it.L[0] * rint(qx * (1.0 / it.L[0]));
+                                qy -= it.L[1] * rint(qy * (1.0 / it.L[1]));
+                                qz -= it.L[2] * rint(qz * (1.0 / it.L[2]));
+                            }
+                            p.x = qx;
+                            p.y = qy;
+                            p.z = qz;
+                            p.d = 0.5 * (qx * qx + qy * qy + qz * qz);
+                        } else if (tag < 0 && tag >= -6) {
+                            // wall -1 .. -6: -x, +x, -y, +y, -z, +z of the seed-relative box
+                            const int b = -1 - tag, a = b >> 1;
+                            const bool pos = b & 1;
+                            p.x = (a == 0) ? (pos ? 1.0 : -1.0) : 0.0;
+                            p.y = (a == 1) ? (pos ? 1.0 : -1.0) : 0.0;
+                            p.z = (a == 2) ? (pos ? 1.0 : -1.0) : 0.0;
+                            p.d = pos ? bhi[a] : -blo[a];
+                        } else {
+                            ok = false;
+                            p.x = p.y = p.z = p.d = 0.0;
+                        }
+                        S.P.pl64[lane] = p;
+                        S.P.fm[lane][0] = 0ull;
+                    }
+                    uint32_t t = 0, k0 = 0, k1 = 0, k2 = 0;
+                    if (lane < nv) {
+                        t = (uint32_t)A.ctopo[tb + VT_TOPO_FACES + lane];
+                        k0 = t & 0xFFu;
+                        k1 = (t >> 8) & 0xFFu;
+                        k2 = (t >> 16) & 0xFFu;
+                        if ((t >> 24) || k0 >= (uint32_t)nf || k1 >= (uint32_t)nf || k2 >= (uint32_t)nf || k0 == k1 ||
+                            k1 == k2 || k0 == k2)
+                            ok = false;
+                    }
+                    if (__ballot(!ok) == 0ull) {
+                        wave_sync();
+                        double x = 0.0, y = 0.0, z = 0.0;
+                        if (lane < nv) {
+                            intersect3<double>(S.P.pl64[k0], S.P.pl64[k1], S.P.pl64[k2], x, y, z);
+                            atomicOr((unsigned long long *)&S.P.fm[k0][0], (unsigned long long)mybit);
+                            atomicOr((unsigned long long *)&S.P.fm[k1][0], (unsigned long long)mybit);
+                            atomicOr((unsigned long long *)&S.P.fm[k2][0], (unsigned long long)mybit);
+                        }
+                        const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
+                        if (__ballot(!fin) == 0ull) {
+                            P.vx[0] = x;
+                            P.vy[0] = y;
+                            P.vz[0] = z;
+                            P.vt[0] = t;
+                            P.alive[0] = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
+                            P.fa[0] = (1ull << nf) - 1ull;
+                            have = true;
+                        }
+                        wave_sync();
+                    }
+                }
+            }
+            // ---- otherwise rebuild the cell from its facets.  The planes are loaded lane-parallel;
+            // the normal kernel applies them nearest first (the cell then stays close to its final
+            // size, 64 vertices suffice), the large kernel in stored order.  A cell that still
+            // outgrows the normal kernel goes to the large one.
+            if (!have) P.init_box(S.P, blo, bhi);
+            const int64_t row = A.crow[c];
+            const int32_t cnt = have ? 0 : A.ccnt[c];
+            for (int32_t t0 = 0; t0 < cnt && !bad && !over; t0 += 64) {
+                const int32_t t = t0 + lane;
+                double qx = 0.0, qy = 0.0, qz = 0.0;
+                int32_t qj = -1;
+                uint64_t key = ~0ull;
+                if (t < cnt) {
+                    qj = A.stage_ids[row + t];
+                    gpos<PT4>(A.spos, qj, qx, qy, qz);
+                    qx -= sx;
+                    qy -= sy;
+                    qz -= sz;
+                    if (it.periodic) {
+                        qx -= it.L[0] * rint(qx / it.L[0]);
+                        qy -= it.L[1] * rint(qy / it.L[1]);
+                        qz -= it.L[2] * rint(qz / it.L[2]);
+                    }
+                    const float d2f = (float)(qx * qx + qy * qy + qz * qz);
+                    key = RETRY ? (uint64_t)lane : (((uint64_t)__float_as_uint(d2f) << 32) | (uint64_t)lane);
+                }
+                if (!RETRY) {
+                    uint64_t kk[1] = {key};
+                    bitonic_u64<1>(kk);
+                    key = kk[0];
+                }
+                const int nin = min(64, cnt - t0);
+                for (int i = 0; i < nin; ++i) {
+                    const int src = (int)(readlane_u32((uint32_t)(key & 0xFFFFFFFFull), i) & 63u);
+                    P4<double> p;
+                    p.x = __shfl(qx, src);
+                    p.y = __shfl(qy, src);
+                    p.z = __shfl(qz, src);
+                    p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
+                    const int32_t j = __shfl(qj, src);
+                    const int rc = P.clip(S.P, p, j);
+                    if (rc == CLIP_OVERFLOW && !RETRY) {
+                        over = true;
+                        break;
+                    }
+                    if (rc < 0) {
+                        if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
+                        bad = true;
+                        break;
+                    }
+                }
+            }
+            if (over) {
                 if (lane == 0) {
-                    int64_t g = (wrapi(va[0], dims[0]) * dims[1] + wrapi(va[1], dims[1])) * dims[2] + wrapi(va[2], dims[2]);
+                    const uint32_t qi = atomicAdd(&A.counters[CTR_GRID_Q], 1u);
+                    if ((int64_t)qi < A.gqueue_cap) A.gqueue[qi] = c;
+                    else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                }
+                continue;
+            }
+            if (bad) {
+                if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                continue;
+            }
+            // ---- vertices in the grid frame, bounding box, voxel ranges
+            double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) {
+                if (P.alive[s] & mybit) {
+                    const double v[3] = {P.vx[s], P.vy[s], P.vz[s]};
+                    for (int a = 0; a < 3; ++a) {
+                        S.vp[s * 64 + lane][a] = v[a];
+                        mn[a] = fmin(mn[a], v[a]);
+                        mx[a] = fmax(mx[a], v[a]);
+                    }
+                    S.vt[s * 64 + lane] = P.vt[s];
+                }
+            }
+            // seed position in the grid frame; grid line m of axis a lies at m h + del - g0 from the seed
+            const double g0[3] = {xs[0] - it.lo[0], xs[1] - it.lo[1], xs[2] - it.lo[2]};
+            int64_t i0[3], i1[3];
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = uni_d(wave_min(mn[a]));
+                mx[a] = uni_d(wave_max(mx[a]));
+                i0[a] = (int64_t)floor((g0[a] + mn[a] - del[a]) * ih[a]);
+                i1[a] = (int64_t)floor((g0[a] + mx[a] - del[a]) * ih[a]);
+            }
+            if (i0[0] == i1[0] && i0[1] == i1[1] && i0[2] == i1[2]) {
+                if (lane == 0) {
+                    int64_t g = (wrapi(i0[0], dims[0]) * dims[1] + wrapi(i0[1], dims[1])) * dims[2] + wrapi(i0[2], dims[2]);
                     unsafeAtomicAdd(&A.grid[g], val * A.cvol[c] / hv);
                 }
                 continue;
             }
-        }
-        double blo[3], bhi[3];
-        for (int a = 0; a < 3; ++a) {
-            if (it.periodic) {
-                blo[a] = -0.5 * it.L[a];
-                bhi[a] = 0.5 * it.L[a];
-            } else {
-                blo[a] = it.lo[a] - xs[a];
-                bhi[a] = it.lo[a] + it.L[a] - xs[a];
+            // ---- faces: compact the alive ones
+            int nf = 0;
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) {
+                const uint64_t m = P.fa[r];
+                if (m & mybit) S.fid[nf + __popcll(m & lt)] = r * 64 + lane;
+                nf += __popcll(m);
             }
-        }
-        Poly<double, VPL> P;
-        bool bad = false, over = false, have = false;
-        // ---- the clip kernel's topology record, if the cell has a well-formed one: every face
-        // plane comes from its tag, every vertex is the intersection of its three planes (in the
-        // triple's order, as the clip kernel computes it), and the face masks follow from the
-        // triples.  Any index out of range sends the cell to the rebuild below.
-        if constexpr (!RETRY && VPL == 1) {
-            const int nf = A.cnf[c], nv = A.cnv[c];
-            if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64) {
-                const int64_t tb = (int64_t)c * VT_TOPO_STRIDE;
-                bool ok = true;
-                if (lane < nf) {
-                    const int32_t tag = A.ctopo[tb + lane];
-                    P4<double> p;
-                    if (tag >= 0 && (int64_t)tag < A.npos) {
-                        double qx, qy, qz;
-                        gpos<PT4>(A.spos, tag, qx, qy, qz);
-                        qx -= sx;
-                        qy -= sy;
-                        qz -= sz;
-                        if (it.periodic) {
-                            qx -= it.L[0] * rint(qx * (1.0 / it.L[0]));
-                            qy -= it.L[1] * rint(qy * (1.0 / it.L[1]));
-                            qz -= it.L[2] * rint(qz * (1.0 / it.L[2]));
+            wave_sync();
+            // the vertex after u on face f, counter-clockwise seen from outside
+            auto next_on = [&](int f, const uint64_t *mf, int u) -> int {
+                const uint32_t t = S.vt[u];
+                const int t0 = t & 0xFF, t1 = (t >> 8) & 0xFF, t2 = (t >> 16) & 0xFF;
+                const int cf = (t0 == f) ? t2 : (t1 == f) ? t0 : t1;
+                int nx_ = -1;
+#pragma unroll
+                for (int ww = 0; ww < VPL; ++ww) {
+                    uint64_t x = mf[ww] & S.P.fm[cf][ww];
+                    if (ww == (u >> 6)) x &= ~(1ull << (u & 63));
+                    if (nx_ < 0 && x) nx_ = ww * 64 + __builtin_ctzll(x);
+                }
+                return nx_;
+            };
+            // loop lengths and planes in the grid frame
+            int carry = 0;
+            for (int base = 0; base < nf; base += 64) {
+                const int q = base + lane;
+                int len = 0, f = 0;
+                if (q < nf) {
+                    f = S.fid[q];
+                    uint64_t mf[VPL];
+                    int u0 = -1;
+#pragma unroll
+                    for (int ww = 0; ww < VPL; ++ww) {
+                        mf[ww] = S.P.fm[f][ww];
+                        if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
+                    }
+                    int u = u0;
+                    do {
+                        ++len;
+                        u = next_on(f, mf, u);
+                    } while (u >= 0 && u != u0 && len < 64 * VPL);
+                }
+                if constexpr (VPL == 1) {
+                    // faces in order of loop length: the work items a wave takes at once then
+                    // mostly share a loop length, and fewer lanes idle in the loop over edges
+                    uint64_t kk[1] = {q < nf ? (((uint64_t)len << 8) | (uint64_t)lane) : ~0ull};
+                    bitonic_u64<1>(kk);
+                    const int src = (int)(kk[0] & 63ull);
+                    const int len_s = __shfl(len, src), f_s = __shfl(f, src);
+                    len = q < nf ? len_s : 0;
+                    f = f_s;
+                    if (q < nf) S.fid[q] = f;
+                }
+                if (q < nf) {
+                    const P4<double> &pf = S.P.pl64[f];
+                    S.fn[q][0] = pf.x;
+                    S.fn[q][1] = pf.y;
+                    S.fn[q][2] = pf.z;
+                    S.fn[q][3] = pf.d;  // seed-relative plane n.v = d
+                }
+                int tot;
+                const int pre = wave_excl_scan(len, &tot);
+                if (q < nf) S.loff[q] = carry + pre;
+                carry += tot;
+            }
+            if (lane == 0) S.loff[nf] = carry;
+            wave_sync();
+            if (carry > M::LOOP) {
+                if (lane == 0) {
+                    atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                    atomicOr(&A.counters[CTR_DEBUG], 1u << 16);
+                }
+                continue;
+            }
+            // loops, counter-clockwise in the (y, z) projection (faces seen from -x are reversed);
+            // extents and work items: rectangles x (1 + planes strictly inside the face's x range)
+            int nitem = 0;
+            for (int base = 0; base < nf; base += 64) {
+                const int q = base + lane;
+                int items = 0;
+                if (q < nf) {
+                    const int f = S.fid[q];
+                    uint64_t mf[VPL];
+                    int u0 = -1;
+#pragma unroll
+                    for (int ww = 0; ww < VPL; ++ww) {
+                        mf[ww] = S.P.fm[f][ww];
+                        if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
+                    }
+                    const int o = S.loff[q], m = S.loff[q + 1] - o;
+                    const bool rev = S.fn[q][0] < 0.0;
+                    double b[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
+                    int u = u0;
+                    for (int k = 0; k < m && u >= 0; ++k) {
+                        const double *p = S.vp[u];
+                        double *lq = S.lp[o + (rev ? m - 1 - k : k)];
+                        for (int a = 0; a < 3; ++a) {
+                            lq[a] = p[a];
+                            b[2 * a] = fmin(b[2 * a], p[a]);
+                            b[2 * a + 1] = fmax(b[2 * a + 1], p[a]);
                         }
-                        p.x = qx;
-                        p.y = qy;
-                        p.z = qz;
-                        p.d = 0.5 * (qx * qx + qy * qy + qz * qz);
-                    } else if (tag < 0 && tag >= -6) {
-                        // wall -1 .. -6: -x, +x, -y, +y, -z, +z of the seed-relative box
-                        const int b = -1 - tag, a = b >> 1;
-                        const bool pos = b & 1;
-                        p.x = (a == 0) ? (pos ? 1.0 : -1.0) : 0.0;
-                        p.y = (a == 1) ? (pos ? 1.0 : -1.0) : 0.0;
-                        p.z = (a == 2) ? (pos ? 1.0 : -1.0) : 0.0;
-                        p.d = pos ? bhi[a] : -blo[a];
-                    } else {
-                        ok = false;
-                        p.x = p.y = p.z = p.d = 0.0;
+                        u = next_on(f, mf, u);
                     }
-                    S.P.pl64[lane] = p;
-                    S.P.fm[lane][0] = 0ull;
-                }
-                uint32_t t = 0, k0 = 0, k1 = 0, k2 = 0;
-                if (lane < nv) {
-                    t = (uint32_t)A.ctopo[tb + VT_TOPO_FACES + lane];
-                    k0 = t & 0xFFu;
-                    k1 = (t >> 8) & 0xFFu;
-                    k2 = (t >> 16) & 0xFFu;
-                    if ((t >> 24) || k0 >= (uint32_t)nf || k1 >= (uint32_t)nf || k2 >= (uint32_t)nf || k0 == k1 ||
-                        k1 == k2 || k0 == k2)
-                        ok = false;
-                }
-                if (__ballot(!ok) == 0ull) {
-                    wave_sync();
-                    double x = 0.0, y = 0.0, z = 0.0;
-                    if (lane < nv) {
-                        intersect3<double>(S.P.pl64[k0], S.P.pl64[k1], S.P.pl64[k2], x, y, z);
-                        atomicOr((unsigned long long *)&S.P.fm[k0][0], (unsigned long long)mybit);
-                        atomicOr((unsigned long long *)&S.P.fm[k1][0], (unsigned long long)mybit);
-                        atomicOr((unsigned long long *)&S.P.fm[k2][0], (unsigned long long)mybit);
+                    const double nlen = sqrt(S.fn[q][0] * S.fn[q][0] + S.fn[q][1] * S.fn[q][1] + S.fn[q][2] * S.fn[q][2]);
+                    // faces parallel to x add nothing (n_x = 0); nearly parallel ones are bounded by 1e-12 of a voxel
+                    if (fabs(S.fn[q][0]) > 1e-12 * nlen) {
+                        const int64_t ja = (int64_t)floor((g0[1] + b[2] - del[1]) * ih[1]);
+                        const int64_t jb = (int64_t)floor((g0[1] + b[3] - del[1]) * ih[1]);
+                        const int64_t ka = (int64_t)floor((g0[2] + b[4] - del[2]) * ih[2]);
+                        const int64_t kb = (int64_t)floor((g0[2] + b[5] - del[2]) * ih[2]);
+                        // planes X_m = m h + del with xmin < X_m < xmax (grid frame)
+                        const int64_t m0 = (int64_t)floor((g0[0] + b[0] - del[0]) * ih[0]) + 1;
+                        const int64_t m1 = (int64_t)ceil((g0[0] + b[1] - del[0]) * ih[0]);
+                        S.frect[q][0] = (int)ja;
+                        S.frect[q][1] = (int)(jb - ja + 1);
+                        S.frect[q][2] = (int)ka;
+                        S.frect[q][3] = (int)(kb - ka + 1);
+                        S.fpl[q][0] = (int)m0;
+                        S.fpl[q][1] = (int)(m1 > m0 ? m1 - m0 : 0);
+                        items = S.frect[q][1] * S.frect[q][3] * (1 + S.fpl[q][1]);
                     }
-                    const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
-                    if (__ballot(!fin) == 0ull) {
-                        P.vx[0] = x;
-                        P.vy[0] = y;
-                        P.vz[0] = z;
-                        P.vt[0] = t;
-                        P.alive[0] = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
-                        P.fa[0] = (1ull << nf) - 1ull;
-                        have = true;
+                }
+                int tot;
+                const int pre = wave_excl_scan(items, &tot);
+                if (q < nf) S.ipre[q] = nitem + pre;
+                nitem += tot;
+            }
+            if (lane == 0) S.ipre[nf] = nitem;
+            wave_sync();
+            nitem = uni_i(nitem);
+            // ---- work items
+            auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
+                if (v == 0.0) return;
+                int64_t g = (wrap1(i, dims[0]) * dims[1] + wrap1(j, dims[1])) * dims[2] + wrap1(k, dims[2]);
+                unsafeAtomicAdd(&A.grid[g], v * vscale);
+            };
+            for (int base = 0; base < nitem; base += 64) {
+                const int item = base + lane;
+                if (item < nitem) {
+                    int lo = 0, hi = nf - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
                     }
-                    wave_sync();
-                }
-            }
-        }
-        // ---- otherwise rebuild the cell from its facets.  The planes are loaded lane-parallel;
-        // the normal kernel applies them nearest first (the cell then stays close to its final
-        // size, 64 vertices suffice), the large kernel in stored order.  A cell that still
-        // outgrows the normal kernel goes to the large one.
-        if (!have) P.init_box(S.P, blo, bhi);
-        const int64_t row = A.crow[c];
-        const int32_t cnt = have ? 0 : A.ccnt[c];
-        for (int32_t t0 = 0; t0 < cnt && !bad && !over; t0 += 64) {
-            const int32_t t = t0 + lane;
-            double qx = 0.0, qy = 0.0, qz = 0.0;
-            int32_t qj = -1;
-            uint64_t key = ~0ull;
-            if (t < cnt) {
-                qj = A.stage_ids[row + t];
-                gpos<PT4>(A.spos, qj, qx, qy, qz);
-                qx -= sx;
-                qy -= sy;
-                qz -= sz;
-                if (it.periodic) {
-                    qx -= it.L[0] * rint(qx / it.L[0]);
-                    qy -= it.L[1] * rint(qy / it.L[1]);
-                    qz -= it.L[2] * rint(qz / it.L[2]);
-                }
-                const float d2f = (float)(qx * qx + qy * qy + qz * qz);
-                key = RETRY ? (uint64_t)lane : (((uint64_t)__float_as_uint(d2f) << 32) | (uint64_t)lane);
-            }
-            if (!RETRY) {
-                uint64_t kk[1] = {key};
-                bitonic_u64<1>(kk);
-                key = kk[0];
-            }
-            const int nin = min(64, cnt - t0);
-            for (int i = 0; i < nin; ++i) {
-                const int src = (int)(readlane_u32((uint32_t)(key & 0xFFFFFFFFull), i) & 63u);
-                P4<double> p;
-                p.x = __shfl(qx, src);
-                p.y = __shfl(qy, src);
-                p.z = __shfl(qz, src);
-                p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
-                const int32_t j = __shfl(qj, src);
-                const int rc = P.clip(S.P, p, j);
-                if (rc == CLIP_OVERFLOW && !RETRY) {
-                    over = true;
-                    break;
-                }
-                if (rc < 0) {
-                    if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
-                    bad = true;
-                    break;
-                }
-            }
-        }
-        if (over) {
-            if (lane == 0) {
-                const uint32_t qi = atomicAdd(&A.counters[CTR_GRID_Q], 1u);
-                if ((int64_t)qi < A.gqueue_cap) A.gqueue[qi] = c;
-                else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
-            }
-            continue;
-        }
-        if (bad) {
-            if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
-            continue;
-        }
-        // ---- vertices in the grid frame, bounding box, voxel ranges
-        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-#pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            if (P.alive[s] & mybit) {
-                const double v[3] = {P.vx[s], P.vy[s], P.vz[s]};
-                for (int a = 0; a < 3; ++a) {
-                    S.vp[s * 64 + lane][a] = v[a];
-                    mn[a] = fmin(mn[a], v[a]);
-                    mx[a] = fmax(mx[a], v[a]);
-                }
-                S.vt[s * 64 + lane] = P.vt[s];
-            }
-        }
-        // seed position in the grid frame; grid line m of axis a lies at m h + del - g0 from the seed
-        const double g0[3] = {xs[0] - it.lo[0], xs[1] - it.lo[1], xs[2] - it.lo[2]};
-        int64_t i0[3], i1[3];
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = uni_d(wave_min(mn[a]));
-            mx[a] = uni_d(wave_max(mx[a]));
-            i0[a] = (int64_t)floor((g0[a] + mn[a] - del[a]) * ih[a]);
-            i1[a] = (int64_t)floor((g0[a] + mx[a] - del[a]) * ih[a]);
-        }
-        if (i0[0] == i1[0] && i0[1] == i1[1] && i0[2] == i1[2]) {
-            if (lane == 0) {
-                int64_t g = (wrapi(i0[0], dims[0]) * dims[1] + wrapi(i0[1], dims[1])) * dims[2] + wrapi(i0[2], dims[2]);
-                unsafeAtomicAdd(&A.grid[g], val * A.cvol[c] / hv);
-            }
-            continue;
-        }
-        // ---- faces: compact the alive ones
-        int nf = 0;
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            const uint64_t m = P.fa[r];
-            if (m & mybit) S.fid[nf + __popcll(m & lt)] = r * 64 + lane;
-            nf += __popcll(m);
-        }
-        wave_sync();
-        // the vertex after u on face f, counter-clockwise seen from outside
-        auto next_on = [&](int f, const uint64_t *mf, int u) -> int {
-            const uint32_t t = S.vt[u];
-            const int t0 = t & 0xFF, t1 = (t >> 8) & 0xFF, t2 = (t >> 16) & 0xFF;
-            const int cf = (t0 == f) ? t2 : (t1 == f) ? t0 : t1;
-            int nx_ = -1;
-#pragma unroll
-            for (int ww = 0; ww < VPL; ++ww) {
-                uint64_t x = mf[ww] & S.P.fm[cf][ww];
-                if (ww == (u >> 6)) x &= ~(1ull << (u & 63));
-                if (nx_ < 0 && x) nx_ = ww * 64 + __builtin_ctzll(x);
-            }
-            return nx_;
-        };
-        // loop lengths and planes in the grid frame
-        int carry = 0;
-        for (int base = 0; base < nf; base += 64) {
-            const int q = base + lane;
-            int len = 0;
-            if (q < nf) {
-                const int f = S.fid[q];
-                uint64_t mf[VPL];
-                int u0 = -1;
-#pragma unroll
-                for (int ww = 0; ww < VPL; ++ww) {
-                    mf[ww] = S.P.fm[f][ww];
-                    if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
-                }
-                int u = u0;
-                do {
-                    ++len;
-                    u = next_on(f, mf, u);
-                } while (u >= 0 && u != u0 && len < 64 * VPL);
-                const P4<double> &pf = S.P.pl64[f];
-                S.fn[q][0] = pf.x;
-                S.fn[q][1] = pf.y;
-                S.fn[q][2] = pf.z;
-                S.fn[q][3] = pf.d;  // seed-relative plane n.v = d
-            }
-            int tot;
-            const int pre = wave_excl_scan(len, &tot);
-            if (q < nf) S.loff[q] = carry + pre;
-            carry += tot;
-        }
-        if (lane == 0) S.loff[nf] = carry;
-        wave_sync();
-        if (carry > M::LOOP) {
-            if (lane == 0) {
-                atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
-                atomicOr(&A.counters[CTR_DEBUG], 1u << 16);
-            }
-            continue;
-        }
-        // loops, counter-clockwise in the (y, z) projection (faces seen from -x are reversed);
-        // extents and work items: rectangles x (1 + planes strictly inside the face's x range)
-        int nitem = 0;
-        for (int base = 0; base < nf; base += 64) {
-            const int q = base + lane;
-            int items = 0;
-            if (q < nf) {
-                const int f = S.fid[q];
-                uint64_t mf[VPL];
-                int u0 = -1;
-#pragma unroll
-                for (int ww = 0; ww < VPL; ++ww) {
-                    mf[ww] = S.P.fm[f][ww];
-                    if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
-                }
-                const int o = S.loff[q], m = S.loff[q + 1] - o;
-                const bool rev = S.fn[q][0] < 0.0;
-                double b[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
-                int u = u0;
-                for (int k = 0; k < m && u >= 0; ++k) {
-                    const double *p = S.vp[u];
-                    double *lq = S.lp[o + (rev ? m - 1 - k : k)];
-                    for (int a = 0; a < 3; ++a) {
-                        lq[a] = p[a];
-                        b[2 * a] = fmin(b[2 * a], p[a]);
-                        b[2 * a + 1] = fmax(b[2 * a + 1], p[a]);
-                    }
-                    u = next_on(f, mf, u);
-                }
-                const double nlen = sqrt(S.fn[q][0] * S.fn[q][0] + S.fn[q][1] * S.fn[q][1] + S.fn[q][2] * S.fn[q][2]);
-                // faces parallel to x add nothing (n_x = 0); nearly parallel ones are bounded by 1e-12 of a voxel
-                if (fabs(S.fn[q][0]) > 1e-12 * nlen) {
-                    const int64_t ja = (int64_t)floor((g0[1] + b[2] - del[1]) * ih[1]);
-                    const int64_t jb = (int64_t)floor((g0[1] + b[3] - del[1]) * ih[1]);
-                    const int64_t ka = (int64_t)floor((g0[2] + b[4] - del[2]) * ih[2]);
-                    const int64_t kb = (int64_t)floor((g0[2] + b[5] - del[2]) * ih[2]);
-                    // planes X_m = m h + del with xmin < X_m < xmax (grid frame)
-                    const int64_t m0 = (int64_t)floor((g0[0] + b[0] - del[0]) * ih[0]) + 1;
-                    const int64_t m1 = (int64_t)ceil((g0[0] + b[1] - del[0]) * ih[0]);
-                    S.frect[q][0] = (int)ja;
-                    S.frect[q][1] = (int)(jb - ja + 1);
-                    S.frect[q][2] = (int)ka;
-                    S.frect[q][3] = (int)(kb - ka + 1);
-                    S.fpl[q][0] = (int)m0;
-                    S.fpl[q][1] = (int)(m1 > m0 ? m1 - m0 : 0);
-                    items = S.frect[q][1] * S.frect[q][3] * (1 + S.fpl[q][1]);
-                }
-            }
-            int tot;
-            const int pre = wave_excl_scan(items, &tot);
-            if (q < nf) S.ipre[q] = nitem + pre;
-            nitem += tot;
-        }
-        if (lane == 0) S.ipre[nf] = nitem;
-        wave_sync();
-        nitem = uni_i(nitem);
-        // ---- work items
-        auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
-            if (v == 0.0) return;
-            int64_t g = (wrap1(i, dims[0]) * dims[1] + wrap1(j, dims[1])) * dims[2] + wrap1(k, dims[2]);
-            unsafeAtomicAdd(&A.grid[g], val * v / hv);
-        };
-        for (int base = 0; base < nitem; base += 64) {
-            const int item = base + lane;
-            if (item < nitem) {
-                int lo = 0, hi = nf - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
-                }
-                const int q = lo;
-                int pi, rj;
-                const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
-                const int rk = divmod_small(r, S.frect[q][1], rj);
-                const int64_t jj = S.frect[q][0] + rj;
-                const int64_t kk = S.frect[q][2] + rk;
-                // rectangle corner (seed-relative); integrals are taken relative to it
-                const double Y0 = jj * h[1] + del[1] - g0[1];
-                const double Z0 = kk * h[2] + del[2] - g0[2];
-                const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2], dg = S.fn[q][3];
-                const double hs = nx_ > 0.0 ? 1.0 : -1.0, rnx = 1.0 / nx_;
-                const int o = S.loff[q], m = S.loff[q + 1] - o;
-                const int64_t m0 = S.fpl[q][0];
-                // on the face n.v = d; with y, z relative to the corner, the plane's value at
-                // (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0
-                // pi == 0: the face over this rectangle against the plane below its x minimum
-                // (full voxels below it, and the voxel holding its x minimum); pi > 0: G at the
-                // plane X_m inside the face's x range, -G to voxel m-1 and +G to voxel m
-                const int64_t mm = m0 + pi - 1;
-                const double X = mm * h[0] + del[0] - g0[0];
-                const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
-                const bool useH = pi > 0 && !(ny_ == 0.0 && nz_ == 0.0);
-                if (pi == 0 || useH || hs * e > 0.0) {
-                    const Reg Rg = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
-                    const double G = hs * Rg.G;
-                    if (pi == 0) {
-                        if (Rg.A != 0.0) {
-                            for (int64_t i = i0[0]; i < mm; ++i) emit(i, jj, kk, hs * h[0] * Rg.A);
+                    const int q = lo;
+                    int pi, rj;
+                    const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
+                    const int rk = divmod_small(r, S.frect[q][1], rj);
+                    const int64_t jj = S.frect[q][0] + rj;
+                    const int64_t kk = S.frect[q][2] + rk;
+                    // rectangle corner (seed-relative); integrals are taken relative to it
+                    const double Y0 = jj * h[1] + del[1] - g0[1];
+                    const double Z0 = kk * h[2] + del[2] - g0[2];
+                    const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2], dg = S.fn[q][3];
+                    const double hs = nx_ > 0.0 ? 1.0 : -1.0, rnx = 1.0 / nx_;
+                    const int o = S.loff[q], m = S.loff[q + 1] - o;
+                    const int64_t m0 = S.fpl[q][0];
+                    // on the face n.v = d; with y, z relative to the corner, the plane's value at
+                    // (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0
+                    // pi == 0: the face over this rectangle against the plane below its x minimum
+                    // (full voxels below it, and the voxel holding its x minimum); pi > 0: G at the
+                    // plane X_m inside the face's x range, -G to voxel m-1 and +G to voxel m
+                    const int64_t mm = m0 + pi - 1;
+                    const double X = mm * h[0] + del[0] - g0[0];
+                    const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
+                    const bool useH = pi > 0 && !(ny_ == 0.0 && nz_ == 0.0);
+                    if (pi == 0 || useH || hs * e > 0.0) {
+                        const Reg Rg = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
+                        const double G = hs * Rg.G;
+                        if (pi == 0) {
+                            if (Rg.A != 0.0) {
+                                for (int64_t i = i0[0]; i < mm; ++i) emit(i, jj, kk, hs * h[0] * Rg.A);
+                                emit(mm, jj, kk, G);
+                            }
+                        } else {
+                            emit(mm - 1, jj, kk, -G);
                             emit(mm, jj, kk, G);
                         }
-                    } else {
-                        emit(mm - 1, jj, kk, -G);
-                        emit(mm, jj, kk, G);
                     }
                 }
             }
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
