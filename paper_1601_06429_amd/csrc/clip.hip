@@ -363,10 +363,34 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 }
                 const double pd = 0.5 * d2;
                 const double nn = sqrt(d2);
+                // Only a vertex whose empty sphere (centre v, radius |v|) reaches the chunk's
+                // bounding box can be cut by one of its particles.  A vertex with
+                // dist(v, box)^2 - |v|^2 above the margin gives sv < -marg for every particle of
+                // the chunk, so skipping it leaves each lane's answer unchanged; the particles of
+                // a chunk are close together (consecutive Morton ranges), so few vertices remain.
+                const double bx0 = uni_d(wave_min(keep ? dx : 1e300)), bx1 = uni_d(wave_max(keep ? dx : -1e300));
+                const double by0 = uni_d(wave_min(keep ? dy : 1e300)), by1 = uni_d(wave_max(keep ? dy : -1e300));
+                const double bz0 = uni_d(wave_min(keep ? dz : 1e300)), bz1 = uni_d(wave_max(keep ? dz : -1e300));
+                const double pmax = uni_d(sqrt(wave_max(keep ? d2 : 0.0)));
+                uint64_t vm[VPL];
+#pragma unroll
+                for (int s = 0; s < VPL; ++s) {
+                    bool rel = false;
+                    if (P.alive[s] & mybit) {
+                        const double x = (double)P.vx[s], y = (double)P.vy[s], z = (double)P.vz[s];
+                        const double ex = fmax(0.0, fmax(bx0 - x, x - bx1));
+                        const double ey = fmax(0.0, fmax(by0 - y, y - by1));
+                        const double ez = fmax(0.0, fmax(bz0 - z, z - bz1));
+                        const double r2v = x * x + y * y + z * z;
+                        const double mg = 2.0 * pmax * ((double)P.ve[s] + 1e-6 * (sqrt(r2v) + pmax));
+                        rel = ex * ex + ey * ey + ez * ez - r2v <= mg;
+                    }
+                    vm[s] = __ballot(rel);
+                }
                 bool act = false;
 #pragma unroll
                 for (int s = 0; s < VPL; ++s) {
-                    uint64_t m = P.alive[s];
+                    uint64_t m = vm[s];
                     while (m) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
