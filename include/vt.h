@@ -93,7 +93,7 @@ typedef struct {
 typedef struct {
     int32_t precision;     /* vt_precision, default VT_PREC_FP64 */
     int32_t want_faces;    /* keep facet areas and centroids (needed by vt_backward) */
-    float radius_factor;   /* first search radius in local mean spacings (default 2.6) */
+    float radius_factor;   /* first search radius in local mean spacings (default 2.0) */
     float area_eps;        /* facets with area <= area_eps * V^(2/3) are not facets (default 1e-12) */
     int32_t waves_per_cu;  /* persistent clip kernel occupancy (default 16) */
     int32_t timing;        /* record HIP events around the sort and clip kernels (see vt_timings) */

@@ -16,8 +16,8 @@ from __future__ import annotations
 
 import itertools
 
-RADIUS_FACTORS = (2.0, 2.6, 3.4)
-WAVES_PER_CU = (8, 16, 24)
+RADIUS_FACTORS = (1.8, 2.0, 2.3, 2.6)
+WAVES_PER_CU = (8, 12)
 
 _cache = {}
 

@@ -893,7 +893,7 @@ hipError_t vt_launch_clip(vt_ctx *c) {
     a.stage_area = c->stage_area;
     a.stage_cen = c->stage_cen;
     a.want_faces = c->opts.want_faces ? 1 : 0;
-    a.radius_factor = c->opts.radius_factor > 0 ? c->opts.radius_factor : 2.6f;
+    a.radius_factor = c->opts.radius_factor > 0 ? c->opts.radius_factor : 2.0f;
     a.area_eps = c->opts.area_eps > 0 ? c->opts.area_eps : 1e-12f;
     const bool mixed = c->opts.precision == VT_PREC_MIXED;
     if (c->dtype == VT_F32) return mixed ? launch_prec<float, float4>(c, a) : launch_prec<double, float4>(c, a);
