@@ -651,8 +651,14 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                     const int64_t mm = m0 + pi - 1;
                     const double X = mm * h[0] + del[0] - g0[0];
                     const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
-                    const bool useH = pi > 0 && !(ny_ == 0.0 && nz_ == 0.0);
-                    if (pi == 0 || useH || hs * e > 0.0) {
+                    // hs (e - ny y - nz z), positive where the face lies above X, is affine over R,
+                    // so its extremes are at R's corners: a face entirely below X over R adds
+                    // nothing, and one entirely above it is not clipped by H
+                    const double cy_ = -hs * ny_ * h[1], cz_ = -hs * nz_ * h[2];
+                    const double above_max = hs * e + fmax(0.0, cy_) + fmax(0.0, cz_);
+                    const double above_min = hs * e + fmin(0.0, cy_) + fmin(0.0, cz_);
+                    const bool useH = pi > 0 && above_min < 0.0;
+                    if (pi == 0 || above_max > 0.0) {
                         const Reg Rg = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
                         const double G = hs * Rg.G;
                         if (pi == 0) {
