@@ -36,6 +36,7 @@ struct GridMem {
     int32_t fpl[FMAX][2];    // planes strictly inside the face's x range: m0, count
     int32_t ipre[FMAX + 1];  // prefix of work items per face
     int32_t fid[FMAX];       // compacted face slots
+    uint64_t iq[128];        // work items queued for integration (face, plane, rectangle offsets)
     PolyMem<double, VPL> P;
 };
 
@@ -563,6 +564,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             // loops, counter-clockwise in the (y, z) projection (faces seen from -x are reversed);
             // extents and work items: rectangles x (1 + planes strictly inside the face's x range)
             int nitem = 0;
+            bool big = false;
             for (int base = 0; base < nf; base += 64) {
                 const int q = base + lane;
                 int items = 0;
@@ -605,7 +607,9 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                         S.frect[q][3] = (int)(kb - ka + 1);
                         S.fpl[q][0] = (int)m0;
                         S.fpl[q][1] = (int)(m1 > m0 ? m1 - m0 : 0);
-                        items = S.frect[q][1] * S.frect[q][3] * (1 + S.fpl[q][1]);
+                        // queued items hold the rectangle offsets in 20 bits and the plane index in 16
+                        if (jb - ja + 1 >= (1 << 20) || kb - ka + 1 >= (1 << 20) || m1 - m0 + 1 >= (1 << 16)) big = true;
+                        else items = S.frect[q][1] * S.frect[q][3] * (1 + S.fpl[q][1]);
                     }
                 }
                 int tot;
@@ -616,14 +620,47 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             if (lane == 0) S.ipre[nf] = nitem;
             wave_sync();
             nitem = uni_i(nitem);
+            if (__ballot(big)) {
+                if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                continue;
+            }
             // ---- work items
             auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
                 if (v == 0.0) return;
                 int64_t g = (wrap1(i, dims[0]) * dims[1] + wrap1(j, dims[1])) * dims[2] + wrap1(k, dims[2]);
                 unsafeAtomicAdd(&A.grid[g], v * vscale);
             };
+            // The item's geometry: rectangle corner (seed-relative; integrals are taken relative
+            // to it), the face plane n.v = d, and the plane X.  With y, z relative to the corner the
+            // plane's value at (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0.  pi == 0: the face over
+            // this rectangle against the plane below its x minimum (full voxels below it, and the
+            // voxel holding its x minimum); pi > 0: G at the plane X_m inside the face's x range,
+            // -G to voxel m-1 and +G to voxel m.
+            struct ItemGeo {
+                double Y0, Z0, X, e, hs;
+                int64_t jj, kk, mm;
+            };
+            auto geometry = [&](int q, int pi, int rj, int rk) -> ItemGeo {
+                ItemGeo G_;
+                G_.jj = S.frect[q][0] + rj;
+                G_.kk = S.frect[q][2] + rk;
+                G_.Y0 = G_.jj * h[1] + del[1] - g0[1];
+                G_.Z0 = G_.kk * h[2] + del[2] - g0[2];
+                G_.mm = (int64_t)S.fpl[q][0] + pi - 1;
+                G_.X = G_.mm * h[0] + del[0] - g0[0];
+                G_.e = S.fn[q][3] - S.fn[q][0] * G_.X - S.fn[q][1] * G_.Y0 - S.fn[q][2] * G_.Z0;
+                G_.hs = S.fn[q][0] > 0.0 ? 1.0 : -1.0;
+                return G_;
+            };
+            // Items are classified 64 at a time: hs (e - ny y - nz z), positive where the face lies
+            // above X, is affine over R, so its extremes are at R's corners; a face entirely below X
+            // over R adds nothing.  The others are queued and integrated 64 at a time, so the lanes
+            // of an integration pass all have an item.
+            int head = 0, qn = 0;
             for (int base = 0; base < nitem; base += 64) {
                 const int item = base + lane;
+                bool need = false;
+                uint64_t desc = 0;
                 if (item < nitem) {
                     int lo = 0, hi = nf - 1;
                     while (lo < hi) {
@@ -634,43 +671,47 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                     int pi, rj;
                     const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
                     const int rk = divmod_small(r, S.frect[q][1], rj);
-                    const int64_t jj = S.frect[q][0] + rj;
-                    const int64_t kk = S.frect[q][2] + rk;
-                    // rectangle corner (seed-relative); integrals are taken relative to it
-                    const double Y0 = jj * h[1] + del[1] - g0[1];
-                    const double Z0 = kk * h[2] + del[2] - g0[2];
-                    const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2], dg = S.fn[q][3];
-                    const double hs = nx_ > 0.0 ? 1.0 : -1.0, rnx = 1.0 / nx_;
-                    const int o = S.loff[q], m = S.loff[q + 1] - o;
-                    const int64_t m0 = S.fpl[q][0];
-                    // on the face n.v = d; with y, z relative to the corner, the plane's value at
-                    // (X, Y0, Z0) is e = d - nx X - ny Y0 - nz Z0
-                    // pi == 0: the face over this rectangle against the plane below its x minimum
-                    // (full voxels below it, and the voxel holding its x minimum); pi > 0: G at the
-                    // plane X_m inside the face's x range, -G to voxel m-1 and +G to voxel m
-                    const int64_t mm = m0 + pi - 1;
-                    const double X = mm * h[0] + del[0] - g0[0];
-                    const double e = dg - nx_ * X - ny_ * Y0 - nz_ * Z0;
-                    // hs (e - ny y - nz z), positive where the face lies above X, is affine over R,
-                    // so its extremes are at R's corners: a face entirely below X over R adds
-                    // nothing, and one entirely above it is not clipped by H
-                    const double cy_ = -hs * ny_ * h[1], cz_ = -hs * nz_ * h[2];
-                    const double above_max = hs * e + fmax(0.0, cy_) + fmax(0.0, cz_);
-                    const double above_min = hs * e + fmin(0.0, cy_) + fmin(0.0, cz_);
-                    const bool useH = pi > 0 && above_min < 0.0;
-                    if (pi == 0 || above_max > 0.0) {
-                        const Reg Rg = region_integrals<VPL>(S, o, m, Y0, Z0, h[1], h[2], useH, hs, e, ny_, nz_, X, rnx);
+                    const ItemGeo g = geometry(q, pi, rj, rk);
+                    const double cy_ = -g.hs * S.fn[q][1] * h[1], cz_ = -g.hs * S.fn[q][2] * h[2];
+                    const double above_max = g.hs * g.e + fmax(0.0, cy_) + fmax(0.0, cz_);
+                    need = pi == 0 || above_max > 0.0;
+                    desc = (uint64_t)q | ((uint64_t)pi << 8) | ((uint64_t)rj << 24) | ((uint64_t)rk << 44);
+                }
+                const uint64_t nb = __ballot(need);
+                if (need) S.iq[(head + qn + __popcll(nb & lt)) & 127] = desc;
+                qn += __popcll(nb);
+                const bool last = base + 64 >= nitem;
+                while (qn >= 64 || (last && qn > 0)) {
+                    wave_sync();
+                    const int take = qn < 64 ? qn : 64;
+                    if (lane < take) {
+                        const uint64_t d = S.iq[(head + lane) & 127];
+                        const int q = (int)(d & 0xFFull), pi = (int)((d >> 8) & 0xFFFFull);
+                        const int rj = (int)((d >> 24) & 0xFFFFFull), rk = (int)((d >> 44) & 0xFFFFFull);
+                        const ItemGeo g = geometry(q, pi, rj, rk);
+                        const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2];
+                        const double hs = g.hs, rnx = 1.0 / nx_;
+                        const int o = S.loff[q], m = S.loff[q + 1] - o;
+                        // a face entirely above X over R is not clipped by H
+                        const double cy_ = -hs * ny_ * h[1], cz_ = -hs * nz_ * h[2];
+                        const double above_min = hs * g.e + fmin(0.0, cy_) + fmin(0.0, cz_);
+                        const bool useH = pi > 0 && above_min < 0.0;
+                        const Reg Rg =
+                            region_integrals<VPL>(S, o, m, g.Y0, g.Z0, h[1], h[2], useH, hs, g.e, ny_, nz_, g.X, rnx);
                         const double G = hs * Rg.G;
                         if (pi == 0) {
                             if (Rg.A != 0.0) {
-                                for (int64_t i = i0[0]; i < mm; ++i) emit(i, jj, kk, hs * h[0] * Rg.A);
-                                emit(mm, jj, kk, G);
+                                for (int64_t i = i0[0]; i < g.mm; ++i) emit(i, g.jj, g.kk, hs * h[0] * Rg.A);
+                                emit(g.mm, g.jj, g.kk, G);
                             }
                         } else {
-                            emit(mm - 1, jj, kk, -G);
-                            emit(mm, jj, kk, G);
+                            emit(g.mm - 1, g.jj, g.kk, -G);
+                            emit(g.mm, g.jj, g.kk, G);
                         }
                     }
+                    head += take;
+                    qn -= take;
+                    wave_sync();
                 }
             }
             wave_sync();
