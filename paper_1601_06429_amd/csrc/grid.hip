@@ -509,25 +509,17 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
                 return nx_;
             };
-            // loop lengths and planes in the grid frame
+            // loop lengths (every vertex on a face is in its mask, so a face's loop has as many
+            // vertices as its mask has bits; the loop walk below checks that it closes after as
+            // many steps) and planes in the grid frame
             int carry = 0;
             for (int base = 0; base < nf; base += 64) {
                 const int q = base + lane;
                 int len = 0, f = 0;
                 if (q < nf) {
                     f = S.fid[q];
-                    uint64_t mf[VPL];
-                    int u0 = -1;
 #pragma unroll
-                    for (int ww = 0; ww < VPL; ++ww) {
-                        mf[ww] = S.P.fm[f][ww];
-                        if (u0 < 0 && mf[ww]) u0 = ww * 64 + __builtin_ctzll(mf[ww]);
-                    }
-                    int u = u0;
-                    do {
-                        ++len;
-                        u = next_on(f, mf, u);
-                    } while (u >= 0 && u != u0 && len < 64 * VPL);
+                    for (int ww = 0; ww < VPL; ++ww) len += __popcll(S.P.fm[f][ww]);
                 }
                 if constexpr (VPL == 1) {
                     // faces in order of loop length: the work items a wave takes at once then
@@ -564,7 +556,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             // loops, counter-clockwise in the (y, z) projection (faces seen from -x are reversed);
             // extents and work items: rectangles x (1 + planes strictly inside the face's x range)
             int nitem = 0;
-            bool big = false;
+            bool big = false, open_loop = false;
             for (int base = 0; base < nf; base += 64) {
                 const int q = base + lane;
                 int items = 0;
@@ -580,8 +572,8 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                     const int o = S.loff[q], m = S.loff[q + 1] - o;
                     const bool rev = S.fn[q][0] < 0.0;
                     double b[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
-                    int u = u0;
-                    for (int k = 0; k < m && u >= 0; ++k) {
+                    int u = u0, k = 0;
+                    for (; k < m && u >= 0; ++k) {
                         const double *p = S.vp[u];
                         double *lq = S.lp[o + (rev ? m - 1 - k : k)];
                         for (int a = 0; a < 3; ++a) {
@@ -591,6 +583,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                         }
                         u = next_on(f, mf, u);
                     }
+                    if (k != m || u != u0) open_loop = true;
                     const double nlen = sqrt(S.fn[q][0] * S.fn[q][0] + S.fn[q][1] * S.fn[q][1] + S.fn[q][2] * S.fn[q][2]);
                     // faces parallel to x add nothing (n_x = 0); nearly parallel ones are bounded by 1e-12 of a voxel
                     if (fabs(S.fn[q][0]) > 1e-12 * nlen) {
@@ -622,6 +615,10 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             nitem = uni_i(nitem);
             if (__ballot(big)) {
                 if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                continue;
+            }
+            if (__ballot(open_loop)) {
+                if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_TOPOLOGY);
                 continue;
             }
             // ---- work items
