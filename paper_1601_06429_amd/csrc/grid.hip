@@ -132,17 +132,27 @@ struct Reg {
     double A, G;
 };
 
-// restrict the parameter interval [t0, t1] of a segment to g >= 0, g affine along it
+// 1 / d from the hardware reciprocal and two Newton steps (each squares the relative error):
+// within a few ulps of the correctly rounded quotient, without the division's branches
+__device__ __forceinline__ double rcp_nr(double d) {
+    double x = __builtin_amdgcn_rcp(d);
+    x = fma(x, fma(-d, x, 1.0), x);
+    x = fma(x, fma(-d, x, 1.0), x);
+    return x;
+}
+
+// restrict the parameter interval [t0, t1] of a segment to g >= 0, g affine along it.  Free of
+// branches: the lanes of a wave clip different segments, and a branch around the quotient
+// would be taken by the whole wave whenever one lane needs it.  The quotient is used only when
+// g0 and g1 differ in sign, so g0 - g1 is then not zero.
 __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, double &t1) {
-    if (g0 >= 0.0 && g1 >= 0.0) return;
-    if (g0 < 0.0 && g1 < 0.0) {
-        t0 = 1.0;
-        t1 = 0.0;
-        return;
-    }
-    const double t = g0 / (g0 - g1);
-    if (g0 < 0.0) t0 = fmax(t0, t);
-    else t1 = fmin(t1, t);
+    const bool in0 = g0 >= 0.0, in1 = g1 >= 0.0;
+    const double t = g0 * rcp_nr(g0 - g1);
+    const double n0 = (!in0 && in1) ? fmax(t0, t) : t0;
+    const double n1 = (in0 && !in1) ? fmin(t1, t) : t1;
+    const bool none = !in0 && !in1;
+    t0 = none ? 1.0 : n0;
+    t1 = none ? 0.0 : n1;
 }
 
 // D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0): Omega the
