@@ -518,80 +518,92 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     const uint32_t key = (i < n) ? (c0 == 0 ? k0 : k1) : 0xFFFFFFFFu;
                     const bool near = i < n && (key >> 8) <= Q4R;
                     if (__ballot(near) == 0) break;
+                    // Candidates of this chunk still to apply or drop.  After a few cuts the cell
+                    // has shrunk, and testing the rest against it again, in parallel, drops more
+                    // of them than applying them one by one would find cutting.
+                    uint64_t pend = __ballot(near);
+                    while (pend && !done) {
 #pragma unroll
-                    for (int s = 0; s < VPL; ++s)
-                        if (P.alive[s] & mybit) {
-                            S.P.st[s * 64 + lane][0] = P.vx[s];
-                            S.P.st[s * 64 + lane][1] = P.vy[s];
-                            S.P.st[s * 64 + lane][2] = P.vz[s];
-                            if constexpr (std::is_same<T, float>::value) S.P.ste[s * 64 + lane] = P.ve[s];
-                        }
-                    wave_sync();
-                    bool act = false;
-                    if (near) {
-                        const int slot = (int)(key & 0xFFu);
-                        const double dx = S.u.c.cd[slot][0], dy = S.u.c.cd[slot][1], dz = S.u.c.cd[slot][2];
-                        const double d2 = dx * dx + dy * dy + dz * dz;
-                        const double pd = 0.5 * d2;
-                        const double nn = sqrt(d2);
+                        for (int s = 0; s < VPL; ++s)
+                            if (P.alive[s] & mybit) {
+                                S.P.st[s * 64 + lane][0] = P.vx[s];
+                                S.P.st[s * 64 + lane][1] = P.vy[s];
+                                S.P.st[s * 64 + lane][2] = P.vz[s];
+                                if constexpr (std::is_same<T, float>::value) S.P.ste[s * 64 + lane] = P.ve[s];
+                            }
+                        wave_sync();
+                        bool act = false;
+                        if (pend & mybit) {
+                            const int slot = (int)(key & 0xFFu);
+                            const double dx = S.u.c.cd[slot][0], dy = S.u.c.cd[slot][1], dz = S.u.c.cd[slot][2];
+                            const double d2 = dx * dx + dy * dy + dz * dz;
+                            const double pd = 0.5 * d2;
+                            const double nn = sqrt(d2);
 #pragma unroll
-                        for (int s = 0; s < VPL; ++s) {
-                            uint64_t m = P.alive[s];
-                            while (m && !act) {
-                                const int k = __builtin_ctzll(m);
-                                m &= m - 1;
-                                const double vx = (double)S.P.st[s * 64 + k][0], vy = (double)S.P.st[s * 64 + k][1],
-                                             vz = (double)S.P.st[s * 64 + k][2];
-                                // same rounding as the clip's own side test
-                                const double sv = fma(vx, dx, fma(vy, dy, vz * dz)) - pd;
-                                // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
-                                double marg = 0.0;
-                                if (std::is_same<T, float>::value)
-                                    marg = nn * ((double)S.P.ste[s * 64 + k] +
-                                                 1e-6 * (sqrt(vx * vx + vy * vy + vz * vz) + 0.5 * nn));
-                                act = sv > -marg;
+                            for (int s = 0; s < VPL; ++s) {
+                                uint64_t m = P.alive[s];
+                                while (m && !act) {
+                                    const int k = __builtin_ctzll(m);
+                                    m &= m - 1;
+                                    const double vx = (double)S.P.st[s * 64 + k][0], vy = (double)S.P.st[s * 64 + k][1],
+                                                 vz = (double)S.P.st[s * 64 + k][2];
+                                    // same rounding as the clip's own side test
+                                    const double sv = fma(vx, dx, fma(vy, dy, vz * dz)) - pd;
+                                    // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
+                                    double marg = 0.0;
+                                    if (std::is_same<T, float>::value)
+                                        marg = nn * ((double)S.P.ste[s * 64 + k] +
+                                                     1e-6 * (sqrt(vx * vx + vy * vy + vz * vz) + 0.5 * nn));
+                                    act = sv > -marg;
+                                }
                             }
                         }
-                    }
-                    uint64_t am = __ballot(near && act);
-                    while (am) {
-                        const int k = __builtin_ctzll(am);
-                        am &= am - 1;
-                        const uint32_t kk = readlane_u32(key, k);
-                        if ((kk >> 8) > Q4R) {
-                            if (!stale) {
-                                done = true;
-                                break;
-                            }
-                            P.update_r2();
-                            Q4R = q4r(P.R2);
-                            stale = false;
+                        uint64_t am = __ballot((pend & mybit) && act);
+                        pend = 0;
+                        int cuts = 0;
+                        while (am) {
+                            const int k = __builtin_ctzll(am);
+                            am &= am - 1;
+                            const uint32_t kk = readlane_u32(key, k);
                             if ((kk >> 8) > Q4R) {
+                                if (!stale) {
+                                    done = true;
+                                    break;
+                                }
+                                P.update_r2();
+                                Q4R = q4r(P.R2);
+                                stale = false;
+                                if ((kk >> 8) > Q4R) {
+                                    done = true;
+                                    break;
+                                }
+                            }
+                            const int slot = (int)(kk & 0xFFu);
+                            ++ntested;
+                            P4<double> p64;
+                            p64.x = S.u.c.cd[slot][0];
+                            p64.y = S.u.c.cd[slot][1];
+                            p64.z = S.u.c.cd[slot][2];
+                            p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
+                            const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
+                            if (rc == CLIP_CUT) {
+                                stale = true;
+                                if (!RETRY && ++cuts == 8 && __popcll(am) >= 16) {
+                                    pend = am;
+                                    break;
+                                }
+                            } else if (rc == CLIP_OVERFLOW) {
+                                overflow = true;
+                                done = true;
+                                break;
+                            } else if (rc < 0) {
+                                corrupt = true;
                                 done = true;
                                 break;
                             }
                         }
-                        const int slot = (int)(kk & 0xFFu);
-                        ++ntested;
-                        P4<double> p64;
-                        p64.x = S.u.c.cd[slot][0];
-                        p64.y = S.u.c.cd[slot][1];
-                        p64.z = S.u.c.cd[slot][2];
-                        p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
-                        const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
-                        if (rc == CLIP_CUT) {
-                            stale = true;
-                        } else if (rc == CLIP_OVERFLOW) {
-                            overflow = true;
-                            done = true;
-                            break;
-                        } else if (rc < 0) {
-                            corrupt = true;
-                            done = true;
-                            break;
-                        }
+                        wave_sync();
                     }
-                    wave_sync();
                 }
                 if (stale) P.update_r2();
                 // particles the security criterion had to examine in this shell
