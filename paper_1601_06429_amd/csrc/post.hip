@@ -12,21 +12,26 @@ __global__ void k_row_counts(const int32_t *row2cell, const int32_t *ccnt, int64
     if (r < n) cnt[r] = ccnt[row2cell[r]];
 }
 
+// a group of 16 lanes per output row: the row's staging slots are read, and its CSR entries
+// written, contiguously
 __global__ void k_fill(const int32_t *row2cell, const int64_t *crow, const int32_t *ccnt, const double *cvol,
                        const uint8_t *cstat, const int32_t *stage_ids, const int32_t *sgid, const int64_t *off,
                        int64_t n, double *volume, int32_t *nbr_ids, int64_t cap, uint8_t *status, uint32_t *counters) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 16;
     if (r >= n) return;
-    int32_t c = row2cell[r];
-    volume[r] = cvol[c];
-    if (status) status[r] = cstat[c];
-    int64_t o = off[r], src = crow[c];
+    const int sub = threadIdx.x & 15;
+    const int32_t c = row2cell[r];
+    const int64_t o = off[r], src = crow[c];
     int32_t k = ccnt[c];
+    if (sub == 0) {
+        volume[r] = cvol[c];
+        if (status) status[r] = cstat[c];
+    }
     if (o + k > cap) {
-        atomicOr(&counters[CTR_STATUS], VT_DEV_NBR_CAP);
+        if (sub == 0) atomicOr(&counters[CTR_STATUS], VT_DEV_NBR_CAP);
         k = o >= cap ? 0 : (int32_t)(cap - o);
     }
-    for (int32_t i = 0; i < k; ++i) nbr_ids[o + i] = sgid[stage_ids[src + i]];
+    for (int32_t i = sub; i < k; i += 16) nbr_ids[o + i] = sgid[stage_ids[src + i]];
 }
 
 hipError_t vt_launch_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
@@ -37,7 +42,7 @@ hipError_t vt_launch_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t 
     k_row_counts<<<g, tpb, 0, c->stream>>>(c->row2cell, c->ccnt, n, c->rowoff);
     hipError_t e = vt_launch_scan_i64(c->rowoff, nbr_off, n, c->scan_tmp, c->stream);
     if (e != hipSuccess) return e;
-    k_fill<<<g, tpb, 0, c->stream>>>(c->row2cell, c->crow, c->ccnt, c->cvol, c->cstat, c->stage_ids, c->sgid, nbr_off,
+    k_fill<<<(n * 16 + tpb - 1) / tpb, tpb, 0, c->stream>>>(c->row2cell, c->crow, c->ccnt, c->cvol, c->cstat, c->stage_ids, c->sgid, nbr_off,
                                      n, volume, nbr_ids, nbr_cap, cell_status, c->counters);
     return hipGetLastError();
 }
@@ -89,24 +94,36 @@ __device__ __forceinline__ void sep(const PT4 *spos, int32_t i, int32_t j, const
 }
 
 // grad_i = G^-1 b, G = sum D D^T, b = sum (rho_j - rho_i) D  (least squares over Voronoi neighbours)
+// The gradient and the adjoint take a group of 16 lanes per cell, in Morton order: the lanes
+// read the cell's facet slots together (one contiguous row; a cell has about 15 facets), and the
+// neighbours of consecutive cells lie close together, so their positions and values stay in cache.
+constexpr int CG = 16;
+
+__device__ __forceinline__ double group_sum(double v) {
+    for (int o = CG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 template <typename PT4>
-__global__ void k_gradient(const int32_t *row2cell, const int32_t *cells, const int32_t *sorig, const int64_t *crow,
-                           const int32_t *ccnt, const int32_t *stage_ids, const PT4 *spos, const DevItem *items,
-                           int n_items, const double *rho, int64_t n, double *grad) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int32_t c = row2cell[r];
-    int32_t i = cells[c];
+__global__ void __launch_bounds__(256) k_gradient(const int32_t *cells, const int32_t *srow, const int32_t *sorig,
+                                                  const int64_t *crow, const int32_t *ccnt, const int32_t *stage_ids,
+                                                  const PT4 *spos, const DevItem *items, int n_items,
+                                                  const double *rho, int64_t n, double *grad) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / CG;
+    if (c >= n) return;
+    const int lane = threadIdx.x & (CG - 1);
+    const int32_t i = cells[c];
+    const int32_t r = srow[i];
     const DevItem &it = items[find_item_p(items, n_items, i)];
-    double ri = rho[sorig[i]];
+    const double ri = rho[sorig[i]];
     double g00 = 0, g01 = 0, g02 = 0, g11 = 0, g12 = 0, g22 = 0, b0 = 0, b1 = 0, b2 = 0;
-    int64_t src = crow[c];
-    int32_t k = ccnt[c];
-    for (int32_t t = 0; t < k; ++t) {
-        int32_t j = stage_ids[src + t];
+    const int64_t src = crow[c];
+    const int32_t k = ccnt[c];
+    for (int32_t t = lane; t < k; t += CG) {
+        const int32_t j = stage_ids[src + t];
         double dx, dy, dz;
         sep<PT4>(spos, i, j, it, dx, dy, dz);
-        double dr = rho[sorig[j]] - ri;
+        const double dr = rho[sorig[j]] - ri;
         g00 += dx * dx;
         g01 += dx * dy;
         g02 += dx * dz;
@@ -117,75 +134,90 @@ __global__ void k_gradient(const int32_t *row2cell, const int32_t *cells, const 
         b1 += dr * dy;
         b2 += dr * dz;
     }
-    // symmetric 3x3 solve by the adjugate
-    double a00 = g11 * g22 - g12 * g12, a01 = g02 * g12 - g01 * g22, a02 = g01 * g12 - g02 * g11;
-    double a11 = g00 * g22 - g02 * g02, a12 = g01 * g02 - g00 * g12, a22 = g00 * g11 - g01 * g01;
-    double det = g00 * a00 + g01 * a01 + g02 * a02;
-    double inv = det != 0.0 ? 1.0 / det : 0.0;
-    grad[3 * r + 0] = (a00 * b0 + a01 * b1 + a02 * b2) * inv;
-    grad[3 * r + 1] = (a01 * b0 + a11 * b1 + a12 * b2) * inv;
-    grad[3 * r + 2] = (a02 * b0 + a12 * b1 + a22 * b2) * inv;
+    g00 = group_sum(g00);
+    g01 = group_sum(g01);
+    g02 = group_sum(g02);
+    g11 = group_sum(g11);
+    g12 = group_sum(g12);
+    g22 = group_sum(g22);
+    b0 = group_sum(b0);
+    b1 = group_sum(b1);
+    b2 = group_sum(b2);
+    if (lane == 0) {
+        // symmetric 3x3 solve by the adjugate
+        const double a00 = g11 * g22 - g12 * g12, a01 = g02 * g12 - g01 * g22, a02 = g01 * g12 - g02 * g11;
+        const double a11 = g00 * g22 - g02 * g02, a12 = g01 * g02 - g00 * g12, a22 = g00 * g11 - g01 * g01;
+        const double det = g00 * a00 + g01 * a01 + g02 * a02;
+        const double inv = det != 0.0 ? 1.0 / det : 0.0;
+        grad[3 * (int64_t)r + 0] = (a00 * b0 + a01 * b1 + a02 * b2) * inv;
+        grad[3 * (int64_t)r + 1] = (a01 * b0 + a11 * b1 + a12 * b2) * inv;
+        grad[3 * (int64_t)r + 2] = (a02 * b0 + a12 * b1 + a22 * b2) * inv;
+    }
 }
 
 hipError_t vt_launch_gradient(vt_ctx *c, const double *rho, double *grad) {
     const int64_t n = c->n_owned;
-    const int tpb = 256;
-    const int64_t g = (n + tpb - 1) / tpb;
+    const int64_t g = (n * CG + 255) / 256;
     if (c->dtype == VT_F32)
-        k_gradient<float4><<<g, tpb, 0, c->stream>>>(c->row2cell, c->cells, c->sorig, c->crow, c->ccnt, c->stage_ids,
+        k_gradient<float4><<<g, 256, 0, c->stream>>>(c->cells, c->srow, c->sorig, c->crow, c->ccnt, c->stage_ids,
                                                      (const float4 *)c->spos, c->items, c->n_items, rho, n, grad);
     else
-        k_gradient<double4><<<g, tpb, 0, c->stream>>>(c->row2cell, c->cells, c->sorig, c->crow, c->ccnt,
-                                                      c->stage_ids, (const double4 *)c->spos, c->items, c->n_items,
-                                                      rho, n, grad);
+        k_gradient<double4><<<g, 256, 0, c->stream>>>(c->cells, c->srow, c->sorig, c->crow, c->ccnt, c->stage_ids,
+                                                      (const double4 *)c->spos, c->items, c->n_items, rho, n, grad);
     return hipGetLastError();
 }
 
 // dL/dx_k = sum_j (g_k - g_j) A_kj (c_kj - x_k) / d_kj, c seed-relative
 template <typename PT4>
-__global__ void k_backward(const int32_t *row2cell, const int32_t *cells, const int32_t *srow, const int64_t *crow,
-                           const int32_t *ccnt, const int32_t *stage_ids, const double *stage_area,
-                           const double *stage_cen, const PT4 *spos, const DevItem *items, int n_items,
-                           const double *g, int64_t n, double *out) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int32_t c = row2cell[r];
-    int32_t i = cells[c];
+__global__ void __launch_bounds__(256) k_backward(const int32_t *cells, const int32_t *srow, const int64_t *crow,
+                                                  const int32_t *ccnt, const int32_t *stage_ids,
+                                                  const double *stage_area, const double *stage_cen, const PT4 *spos,
+                                                  const DevItem *items, int n_items, const double *g, int64_t n,
+                                                  double *out) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / CG;
+    if (c >= n) return;
+    const int lane = threadIdx.x & (CG - 1);
+    const int32_t i = cells[c];
+    const int32_t r = srow[i];
     const DevItem &it = items[find_item_p(items, n_items, i)];
-    double gk = g[r];
+    const double gk = g[r];
     double ox = 0, oy = 0, oz = 0;
-    int64_t src = crow[c];
-    int32_t k = ccnt[c];
-    for (int32_t t = 0; t < k; ++t) {
-        int64_t f = src + t;
-        int32_t j = stage_ids[f];
-        int32_t rj = srow[j];
-        double gj = rj >= 0 ? g[rj] : 0.0;
+    const int64_t src = crow[c];
+    const int32_t k = ccnt[c];
+    for (int32_t t = lane; t < k; t += CG) {
+        const int64_t f = src + t;
+        const int32_t j = stage_ids[f];
+        const int32_t rj = srow[j];
+        const double gj = rj >= 0 ? g[rj] : 0.0;
         double dx, dy, dz;
         sep<PT4>(spos, i, j, it, dx, dy, dz);
-        double d = sqrt(dx * dx + dy * dy + dz * dz);
-        double w = (gk - gj) * stage_area[f] / d;
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double w = (gk - gj) * stage_area[f] / d;
         ox += w * stage_cen[3 * f + 0];
         oy += w * stage_cen[3 * f + 1];
         oz += w * stage_cen[3 * f + 2];
     }
-    out[3 * r + 0] = ox;
-    out[3 * r + 1] = oy;
-    out[3 * r + 2] = oz;
+    ox = group_sum(ox);
+    oy = group_sum(oy);
+    oz = group_sum(oz);
+    if (lane == 0) {
+        out[3 * (int64_t)r + 0] = ox;
+        out[3 * (int64_t)r + 1] = oy;
+        out[3 * (int64_t)r + 2] = oz;
+    }
 }
 
 hipError_t vt_launch_backward(vt_ctx *c, const double *g, double *out) {
     const int64_t n = c->n_owned;
-    const int tpb = 256;
-    const int64_t gr = (n + tpb - 1) / tpb;
+    const int64_t gr = (n * CG + 255) / 256;
     if (c->dtype == VT_F32)
-        k_backward<float4><<<gr, tpb, 0, c->stream>>>(c->row2cell, c->cells, c->srow, c->crow, c->ccnt, c->stage_ids,
+        k_backward<float4><<<gr, 256, 0, c->stream>>>(c->cells, c->srow, c->crow, c->ccnt, c->stage_ids,
                                                       c->stage_area, c->stage_cen, (const float4 *)c->spos, c->items,
                                                       c->n_items, g, n, out);
     else
-        k_backward<double4><<<gr, tpb, 0, c->stream>>>(c->row2cell, c->cells, c->srow, c->crow, c->ccnt,
-                                                       c->stage_ids, c->stage_area, c->stage_cen,
-                                                       (const double4 *)c->spos, c->items, c->n_items, g, n, out);
+        k_backward<double4><<<gr, 256, 0, c->stream>>>(c->cells, c->srow, c->crow, c->ccnt, c->stage_ids,
+                                                       c->stage_area, c->stage_cen, (const double4 *)c->spos,
+                                                       c->items, c->n_items, g, n, out);
     return hipGetLastError();
 }
 
