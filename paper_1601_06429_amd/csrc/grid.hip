@@ -155,6 +155,17 @@ __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, dou
     t1 = none ? 0.0 : n1;
 }
 
+// restrict [t0, t1] to lo <= a + t b <= hi (one coordinate of a segment against a slab), with
+// one reciprocal for both sides; a segment parallel to the slab is kept or emptied whole
+__device__ __forceinline__ void slab(double a, double b, double lo, double hi, double &t0, double &t1) {
+    const double ib = rcp_nr(b);
+    const double ta = (lo - a) * ib, tb = (hi - a) * ib;
+    const bool flat = b == 0.0, inside = a >= lo && a <= hi;
+    const double n0 = fmax(t0, fmin(ta, tb)), n1 = fmin(t1, fmax(ta, tb));
+    t0 = flat ? (inside ? t0 : 1.0) : n0;
+    t1 = flat ? (inside ? t1 : 0.0) : n1;
+}
+
 // D = Omega ∩ R ∩ H in coordinates relative to R's corner (Y0, Z0): Omega the
 // counter-clockwise loop lp[o .. o+m) of seed-relative vertices,
 // R = [Y0, Y0 + hy] x [Z0, Z0 + hz], H = {hs (e - ny y - nz z) > 0} if useH (the
@@ -192,10 +203,8 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
         cy1 = py + dy;
         cz1 = pz + dz;
         ct1 = 1.0;
-        cyrus_beck(cy0, cy1, ct0, ct1);
-        cyrus_beck(hy - cy0, hy - cy1, ct0, ct1);
-        cyrus_beck(cz0, cz1, ct0, ct1);
-        cyrus_beck(hz - cz0, hz - cz1, ct0, ct1);
+        slab(cy0, cy1 - cy0, 0.0, hy, ct0, ct1);
+        slab(cz0, cz1 - cz0, 0.0, hz, ct0, ct1);
     }
     double y0 = Oy, z0 = Oz, xa = gO;
     for (int k = 0; k < m; ++k) {
@@ -204,10 +213,8 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
         // (a) the edge of Omega inside R ∩ H
         {
             double t0 = 0.0, t1 = 1.0;
-            cyrus_beck(y0, y1, t0, t1);
-            cyrus_beck(hy - y0, hy - y1, t0, t1);
-            cyrus_beck(z0, z1, t0, t1);
-            cyrus_beck(hz - z0, hz - z1, t0, t1);
+            slab(y0, y1 - y0, 0.0, hy, t0, t1);
+            slab(z0, z1 - z0, 0.0, hz, t0, t1);
             if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
             if (t0 < t1) {
                 const double dy = y1 - y0, dz = z1 - z0, dx = xb - xa;
