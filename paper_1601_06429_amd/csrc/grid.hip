@@ -156,9 +156,8 @@ __device__ __forceinline__ void cyrus_beck(double g0, double g1, double &t0, dou
 }
 
 // restrict [t0, t1] to lo <= a + t b <= hi (one coordinate of a segment against a slab), with
-// one reciprocal for both sides; a segment parallel to the slab is kept or emptied whole
-__device__ __forceinline__ void slab(double a, double b, double lo, double hi, double &t0, double &t1) {
-    const double ib = rcp_nr(b);
+// ib = 1 / b for both sides; a segment parallel to the slab is kept or emptied whole
+__device__ __forceinline__ void slab(double a, double b, double ib, double lo, double hi, double &t0, double &t1) {
     const double ta = (lo - a) * ib, tb = (hi - a) * ib;
     const bool flat = b == 0.0, inside = a >= lo && a <= hi;
     const double n0 = fmax(t0, fmin(ta, tb)), n1 = fmin(t1, fmax(ta, tb));
@@ -203,36 +202,64 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
         cy1 = py + dy;
         cz1 = pz + dz;
         ct1 = 1.0;
-        slab(cy0, cy1 - cy0, 0.0, hy, ct0, ct1);
-        slab(cz0, cz1 - cz0, 0.0, hz, ct0, ct1);
+        slab(cy0, cy1 - cy0, rcp_nr(cy1 - cy0), 0.0, hy, ct0, ct1);
+        slab(cz0, cz1 - cz0, rcp_nr(cz1 - cz0), 0.0, hz, ct0, ct1);
     }
+    // (b) R's edges inside Omega come from where Omega's boundary crosses R's four lines.  Omega
+    // is convex and counter-clockwise, so crossing a line z = c upwards bounds its chord on the
+    // right and downwards on the left; crossing y = c rightwards bounds it from below and
+    // leftwards from above.  A line that no edge crosses misses Omega.  Edge r of R runs from
+    // corner r to corner r + 1 (counter-clockwise), t along it.
+    const double ihy = 1.0 / hy, ihz = 1.0 / hz;
+    int crossed[4] = {0, 0, 0, 0};
     double y0 = Oy, z0 = Oz, xa = gO;
     for (int k = 0; k < m; ++k) {
         const int k1 = (k + 1 == m) ? 0 : k + 1;
         const double y1 = S.lp[o + k1][1] - Y0, z1 = S.lp[o + k1][2] - Z0, xb = S.lp[o + k1][0] - X;
+        const double dy = y1 - y0, dz = z1 - z0, dx = xb - xa;
+        const double iby = rcp_nr(dy), ibz = rcp_nr(dz);
         // (a) the edge of Omega inside R ∩ H
         {
             double t0 = 0.0, t1 = 1.0;
-            slab(y0, y1 - y0, 0.0, hy, t0, t1);
-            slab(z0, z1 - z0, 0.0, hz, t0, t1);
+            slab(y0, dy, iby, 0.0, hy, t0, t1);
+            slab(z0, dz, ibz, 0.0, hz, t0, t1);
             if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
-            if (t0 < t1) {
-                const double dy = y1 - y0, dz = z1 - z0, dx = xb - xa;
-                tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
-            }
+            if (t0 < t1) tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
         }
-        // (b), (c): R's edges and the chord restricted to the inner side of this edge
-        const double du = y1 - y0, dv = z1 - z0;
-        auto inner = [&](double qy, double qz) { return du * (qz - z0) - dv * (qy - y0); };
-        double gc[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gc[r] = inner(ry[r], rz[r]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cyrus_beck(gc[r], gc[(r + 1) & 3], rt0[r], rt1[r]);
-        if (useH) cyrus_beck(inner(cy0, cz0), inner(cy1, cz1), ct0, ct1);
+        // (b) crossings with z = 0 (edge 0, t = y / hy), y = hy (edge 1, t = z / hz),
+        // z = hz (edge 2, t = (hy - y) / hy) and y = 0 (edge 3, t = (hz - z) / hz)
+        {
+            const bool up0 = z0 < 0.0 && !(z1 < 0.0), dn0 = !(z0 < 0.0) && z1 < 0.0;
+            const bool up2 = z0 < hz && !(z1 < hz), dn2 = !(z0 < hz) && z1 < hz;
+            const bool rt1_ = y0 < hy && !(y1 < hy), lf1 = !(y0 < hy) && y1 < hy;
+            const bool rt3 = y0 < 0.0 && !(y1 < 0.0), lf3 = !(y0 < 0.0) && y1 < 0.0;
+            const double yc0 = (y0 + (0.0 - z0) * ibz * dy) * ihy;
+            const double yc2 = (hy - (y0 + (hz - z0) * ibz * dy)) * ihy;
+            const double zc1 = (z0 + (hy - y0) * iby * dz) * ihz;
+            const double zc3 = (hz - (z0 + (0.0 - y0) * iby * dz)) * ihz;
+            rt1[0] = up0 ? fmin(rt1[0], yc0) : rt1[0];
+            rt0[0] = dn0 ? fmax(rt0[0], yc0) : rt0[0];
+            rt0[2] = up2 ? fmax(rt0[2], yc2) : rt0[2];
+            rt1[2] = dn2 ? fmin(rt1[2], yc2) : rt1[2];
+            rt0[1] = rt1_ ? fmax(rt0[1], zc1) : rt0[1];
+            rt1[1] = lf1 ? fmin(rt1[1], zc1) : rt1[1];
+            rt1[3] = rt3 ? fmin(rt1[3], zc3) : rt1[3];
+            rt0[3] = lf3 ? fmax(rt0[3], zc3) : rt0[3];
+            crossed[0] |= (up0 || dn0) ? 1 : 0;
+            crossed[1] |= (rt1_ || lf1) ? 1 : 0;
+            crossed[2] |= (up2 || dn2) ? 1 : 0;
+            crossed[3] |= (rt3 || lf3) ? 1 : 0;
+        }
+        // (c) the chord restricted to the inner side of this edge
+        cyrus_beck(dy * (cz0 - z0) - dz * (cy0 - y0), dy * (cz1 - z0) - dz * (cy1 - y0), ct0, ct1);
         y0 = y1;
         z0 = z1;
         xa = xb;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        rt0[r] = crossed[r] ? rt0[r] : 1.0;
+        rt1[r] = crossed[r] ? rt1[r] : 0.0;
     }
     // (b) edges of R inside Omega ∩ H
 #pragma unroll
