@@ -2,6 +2,9 @@
 
 * lattice+halos 16M (FP32, mixed and FP64 paths): sampled cells against the oracle, plus
   volume conservation over the whole box;
+* clustered 2M at 256^3 (the benchmark's deposit): a field that is zero except on 96 sampled
+  cells (random ones and cells the large kernels handle), every voxel against the oracle's
+  exact overlaps of those cells;
 * diff262k: the adjoint gradient of a density-matching loss at full size against central
   finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
   perturbed loss is evaluated exactly on a small bounded world around the moved particle
@@ -45,6 +48,28 @@ def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, precision
         assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
         assert abs(vol[i] - ref.volume[q]) <= tol * ref.volume[q], i
     del ctx, cells, t
+    torch_cuda.cuda.empty_cache()
+
+
+def test_clustered2m_grid_sampled_cells(vt, torch_cuda, oracle):
+    w = wl.clustered2m()
+    n = w.n
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(n, w.box_lo, w.box_hi), want_faces=True)
+    assert ctx.vt_query()[0] == 0
+    st = ctx.vt_cells().status.cpu().numpy()
+    rng = np.random.default_rng(4004)
+    retried = np.nonzero(st & 2)[0]
+    sample = np.unique(np.concatenate([rng.choice(n, 80, replace=False),
+                                       rng.choice(retried, min(16, retried.size), replace=False)]))
+    val = np.zeros(n)
+    val[sample] = rng.uniform(0.5, 2.0, sample.size)
+    dims = (256, 256, 256)
+    g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
+    assert ctx.vt_query()[0] == 0
+    gref = oracle.grid(w.pos.astype(np.float64), w.box_lo, w.box_hi, True, val, dims, query=sample)
+    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    del ctx, t
     torch_cuda.cuda.empty_cache()
 
 
