@@ -202,6 +202,66 @@ vt_status vt_stats(vt_ctx *ctx, int32_t *n_vertices, int32_t *n_planes, int32_t 
  */
 vt_status vt_timings(vt_ctx *ctx, float ms[3]);
 
+/*
+ * Domain decomposition with AUTOBORDER (section 2: the volume is split into
+ * sub-volumes, each with a buffer zone of boundary particles; the buffer
+ * starts at BORDERFACTOR times the mean inter-particle distance and, where the
+ * particle density in it is below the mean, grows until it holds the number of
+ * particles the mean density puts in the initial zone).  On one GPU the tasks
+ * become the items of one batched vt_build.
+ *
+ * The periodic box [lo, hi)^3 is split into nt[0] x nt[1] x nt[2] equal tasks;
+ * task b = (ix * nt[1] + iy) * nt[2] + iz owns the particles whose cell index
+ * floor((x - lo) / w) (clamped to the grid) is (ix, iy, iz), w = (hi - lo) / nt.
+ * The buffer zone of a face is the slab beyond it over the face's extent.
+ * Reading of the growth rule: the thickness is thresholds[k] for the smallest k
+ * whose slab holds at least nbar * A_face * thresholds[0] particles (nbar = n
+ * over the box volume, A_face the face's area; a particle counts if its
+ * distance beyond the face is below thresholds[k]); thresholds[n_thr - 1] if
+ * no k does.  Thicknesses are capped below (L - w) / 2 per axis (L / 2 when
+ * nt = 1 there) so that a buffered task spans less than one period.
+ */
+
+/*
+ * vt_decompose -- the AUTOBORDER thicknesses and the task sizes.
+ *   ctx          in/out as for vt_build (the decomposition keeps its own
+ *                scratch in the context).
+ *   pos          device, n x 3 positions (dtype), every particle in [lo, hi).
+ *   nt           host, tasks per axis, each >= 1.
+ *   thresholds   host, n_thr (1..64) increasing positive thicknesses.
+ *   thick        host out, 6 per task: faces -x, +x, -y, +y, -z, +z.
+ *   n_owned      host out, per task: owned particles.
+ *   n_ghost      host out, per task: buffer particles (particle images inside
+ *                the buffered box that the task does not own).
+ * Synchronises the stream.  Errors: VT_ERR_ARG, VT_ERR_OOM, VT_ERR_HIP.
+ */
+vt_status vt_decompose(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n, const double lo[3],
+                       const double hi[3], const int32_t nt[3], const double *thresholds, int32_t n_thr,
+                       double *thick, int64_t *n_owned, int64_t *n_ghost, void *stream);
+
+/*
+ * vt_decompose_pack -- the batch for vt_build: for each listed task (in list
+ * order), its owned particles and then its buffer particles, shifted by whole
+ * periods next to the task, as FP64 (exact: the shifts are multiples of L).
+ *   thick        host, 6 per task (as from vt_decompose, or widened).
+ *   own_mask     device, n bytes or NULL: if given, a task owns only its
+ *                particles with a nonzero byte, and its other particles are
+ *                buffer particles (to re-run the incomplete cells of a first
+ *                pass with wider buffers).
+ *   tasks        host, n_list task indices, or NULL for every task in order.
+ *   out_pos      device, cap x 3 doubles; out_gid device, cap int32 (the
+ *                particle's index in pos).
+ *   items        host out, n_list bounded items (box = the buffered box).
+ *   n_out        host out, particles written (or needed, if above cap).
+ * A listed task must own at least one particle.  Synchronises the stream.
+ * Errors: VT_ERR_ARG, VT_ERR_CAPACITY (cap too small; *n_out is the size
+ * needed and nothing was written), VT_ERR_OOM, VT_ERR_HIP.
+ */
+vt_status vt_decompose_pack(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n, const double lo[3],
+                            const double hi[3], const int32_t nt[3], const double *thick, const uint8_t *own_mask,
+                            const int32_t *tasks, int32_t n_list, double *out_pos, int32_t *out_gid, int64_t cap,
+                            vt_item *items, int64_t *n_out, void *stream);
+
 /* n_owned_total and n_total of the last build (host, no sync). */
 vt_status vt_sizes(vt_ctx *ctx, int64_t *n_owned_total, int64_t *n_total);
 

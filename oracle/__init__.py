@@ -21,6 +21,13 @@ Readings where the paper is silent (documented with the design notes):
     zero gradient on lattices);
   * grid: exact volume average of the piecewise-constant Voronoi density over
     each voxel (pinned by mass conservation and exact lattice cases);
+  * AUTOBORDER (section 2, buffer zones between tasks): per face of each task of
+    an equal split of the box, the buffer is the slab beyond the face over the
+    face's extent; its thickness is the first of a growing list of thicknesses
+    at which the slab holds the mean density times the face area times the
+    first thickness (pinned by uniform lattices, where the first thickness
+    already suffices, by empty regions, which reach the cap, and by hand-counted
+    small sets);
   * adjoint: dV_i/dx_j = A_ij (x_j - c_ij) / d_ij and
     dV_i/dx_i = sum_j A_ij (c_ij - x_i) / d_ij (derived from the motion of the
     bisector plane; pinned by central finite differences of the oracle's own
@@ -206,3 +213,95 @@ def adjoint(c: Cells, dL_dV, rows_pos=None):
         w = (g[k] - g[ids]) * A / d
         out[q] = (w[:, None] * C).sum(axis=0)
     return out
+
+
+def task_index(pos, box_lo, box_hi, nt):
+    """Owner cell index of every particle: floor((x - lo) / w), w = L / nt, clamped to the grid."""
+    x = np.asarray(pos, np.float64)
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    nt = np.asarray(nt, np.int64)
+    return np.clip(np.floor((x - lo) / (L / nt)).astype(np.int64), 0, nt - 1)
+
+
+def thickness_cap(box_lo, box_hi, nt):
+    """Largest buffer thickness per axis: a buffered task must span less than one period."""
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    nt = np.asarray(nt)
+    return np.where(nt >= 2, 0.5 * (L - L / nt), 0.5 * L) * (1.0 - 1e-12)
+
+
+def autoborder(pos, box_lo, box_hi, nt, thresholds):
+    """AUTOBORDER thicknesses, n_tasks x 6 (faces -x, +x, -y, +y, -z, +z), section 2.
+
+    For the face of task (i0, i1, i2) normal to axis a on side +/-: the particles
+    in the face's column (same cell index on the two other axes) at periodic
+    distance d beyond the face, d = (x_a - F) mod L_a (+) or (F - x_a) mod L_a (-),
+    F the face's coordinate; the slab of thickness t holds those with
+    d < min(t, cap_a).  The thickness is the first threshold whose slab holds at
+    least n / V * A_face * thresholds[0] particles, the last threshold if none
+    does, and at most cap_a.
+    """
+    x = np.asarray(pos, np.float64)
+    n = len(x)
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    nt = np.asarray(nt, np.int64)
+    w = L / nt
+    thr = np.asarray(thresholds, np.float64)
+    cap = thickness_cap(box_lo, box_hi, nt)
+    idx = task_index(x, box_lo, box_hi, nt)
+    nbar = n / float(np.prod(L))
+    out = np.zeros((int(np.prod(nt)), 6))
+    for i0 in range(nt[0]):
+        for i1 in range(nt[1]):
+            for i2 in range(nt[2]):
+                b = (i0 * nt[1] + i1) * nt[2] + i2
+                ii = (i0, i1, i2)
+                for a in range(3):
+                    c1, c2 = (a + 1) % 3, (a + 2) % 3
+                    col = (idx[:, c1] == ii[c1]) & (idx[:, c2] == ii[c2])
+                    expect = nbar * w[c1] * w[c2] * thr[0]
+                    for side in (0, 1):
+                        if side:
+                            F = lo[a] + (ii[a] + 1) * w[a]
+                            d = np.mod(x[col, a] - F, L[a])
+                        else:
+                            F = lo[a] + ii[a] * w[a]
+                            d = np.mod(F - x[col, a], L[a])
+                        t = thr[-1]
+                        for tk in thr:
+                            if np.count_nonzero(d < min(tk, cap[a])) >= expect:
+                                t = tk
+                                break
+                        out[b, 2 * a + side] = min(t, cap[a])
+    return out
+
+
+def task_members(pos, box_lo, box_hi, nt, thick, task):
+    """Owned particles of a task and the particle images x + s L (s in {-1, 0, 1}^3) inside its
+    buffered box that it does not own: (owned indices, buffer indices, buffer shifts)."""
+    x = np.asarray(pos, np.float64)
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    nt = np.asarray(nt, np.int64)
+    w = L / nt
+    idx = task_index(x, box_lo, box_hi, nt)
+    ii = np.array([task // (nt[1] * nt[2]), (task // nt[2]) % nt[1], task % nt[2]])
+    t = np.asarray(thick, np.float64).reshape(-1, 6)[task]
+    blo = lo + ii * w - t[0::2]
+    bhi = lo + (ii + 1) * w + t[1::2]
+    owner = np.all(idx == ii, axis=1)
+    buf_i, buf_s = [], []
+    for s0 in (-1, 0, 1):
+        for s1 in (-1, 0, 1):
+            for s2 in (-1, 0, 1):
+                sv = np.array([s0, s1, s2])
+                y = x + sv * L
+                inside = np.all((y >= blo) & (y < bhi), axis=1)
+                if s0 == 0 and s1 == 0 and s2 == 0:
+                    inside &= ~owner
+                k = np.nonzero(inside)[0]
+                buf_i.append(k)
+                buf_s.append(np.repeat(sv[None, :], len(k), axis=0))
+    return np.nonzero(owner)[0], np.concatenate(buf_i), np.concatenate(buf_s)

@@ -27,6 +27,7 @@ _lib = None
 _lock = threading.Lock()
 
 VT_OK = 0
+VT_ERR_CAPACITY = 6
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out of device memory",
                 4: "duplicate particles", 5: "periodic box too small", 6: "capacity exceeded",
                 7: "invalid call order", 8: "inconsistent clipping topology"}
@@ -83,12 +84,18 @@ def lib():
             L.vt_stats.argtypes = [P, P, P, P, P]
             L.vt_sizes.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
             L.vt_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+            D3 = ctypes.POINTER(ctypes.c_double)
+            L.vt_decompose.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, ctypes.POINTER(I32), D3, I32, D3,
+                                       ctypes.POINTER(I64), ctypes.POINTER(I64), P]
+            L.vt_decompose_pack.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, ctypes.POINTER(I32), D3, P,
+                                            ctypes.POINTER(I32), I32, P, P, I64, ctypes.POINTER(vt_item),
+                                            ctypes.POINTER(I64), P]
             L.vt_destroy.argtypes = [P]
             L.vt_destroy.restype = None
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
-                      "vt_query", "vt_stats", "vt_sizes", "vt_timings"):
+                      "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -142,6 +149,27 @@ def pack_worlds(worlds):
         off += len(owned) + len(ghosts)
     pos = np.ascontiguousarray(np.concatenate(parts))
     return pos, items, np.arange(off, dtype=np.int32)
+
+
+def _pos_dtype(pos):
+    import torch
+
+    _require_cuda(pos, "pos")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be n x 3")
+    if pos.dtype == torch.float32:
+        return VT_F32
+    if pos.dtype == torch.float64:
+        return VT_F64
+    raise ValueError("pos must be float32 or float64")
+
+
+def _box3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in np.broadcast_to(np.asarray(v, np.float64), 3)])
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _items(items):
@@ -283,6 +311,53 @@ class Context:
         _check(lib().vt_backward(self._ctx, _ptr(dL_dV), _ptr(g), _stream(stream)), "vt_backward")
         return g
 
+    def vt_decompose(self, pos, box_lo, box_hi, nt, thresholds, stream=None):
+        """AUTOBORDER thicknesses (n_tasks x 6: faces -x, +x, -y, +y, -z, +z) and the tasks'
+        owned and buffer counts, as numpy arrays."""
+        dt = _pos_dtype(pos)
+        lo, hi, ntc = _box3(box_lo), _box3(box_hi), (ctypes.c_int32 * 3)(*[int(x) for x in nt])
+        thr = np.ascontiguousarray(thresholds, np.float64)
+        n_tasks = int(np.prod(nt))
+        thick = np.zeros(6 * n_tasks)
+        n_own = np.zeros(n_tasks, np.int64)
+        n_gh = np.zeros(n_tasks, np.int64)
+        _check(lib().vt_decompose(ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, ntc, _dptr(thr),
+                                  len(thr), _dptr(thick), n_own.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  n_gh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(stream)),
+               "vt_decompose")
+        return thick.reshape(n_tasks, 6), n_own, n_gh
+
+    def vt_decompose_pack(self, pos, box_lo, box_hi, nt, thick, own_mask=None, tasks=None, stream=None):
+        """The batch of the listed tasks for vt_build: (positions float64 n x 3, int32 global ids,
+        item list)."""
+        import torch
+
+        dt = _pos_dtype(pos)
+        if own_mask is not None:
+            _require_cuda(own_mask, "own_mask")
+            if own_mask.dtype != torch.uint8 or own_mask.shape[0] != pos.shape[0]:
+                raise ValueError("own_mask must be uint8 with one byte per particle")
+        lo, hi, ntc = _box3(box_lo), _box3(box_hi), (ctypes.c_int32 * 3)(*[int(x) for x in nt])
+        th = np.ascontiguousarray(np.asarray(thick, np.float64).reshape(-1))
+        n_tasks = int(np.prod(nt))
+        tl = None if tasks is None else np.ascontiguousarray(tasks, np.int32)
+        n_list = n_tasks if tl is None else len(tl)
+        arr = (vt_item * n_list)()
+        n_out = ctypes.c_int64()
+        tptr = None if tl is None else tl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        args = (ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, ntc, _dptr(th), _ptr(own_mask), tptr,
+                n_list)
+        code = lib().vt_decompose_pack(*args, None, None, 0, arr, ctypes.byref(n_out), _stream(stream))
+        if code not in (VT_OK, VT_ERR_CAPACITY):
+            _check(code, "vt_decompose_pack")
+        out = torch.empty((max(n_out.value, 1), 3), dtype=torch.float64, device=pos.device)
+        gid = torch.empty(max(n_out.value, 1), dtype=torch.int32, device=pos.device)
+        _check(lib().vt_decompose_pack(*args, _ptr(out), _ptr(gid), out.shape[0], arr, ctypes.byref(n_out),
+                                       _stream(stream)), "vt_decompose_pack")
+        items = [dict(offset=arr[k].offset, n_owned=arr[k].n_owned, n_ghost=arr[k].n_ghost, periodic=False,
+                      lo=np.array(arr[k].lo[:]), hi=np.array(arr[k].hi[:])) for k in range(n_list)]
+        return out[:n_out.value], gid[:n_out.value], items
+
     def vt_stats(self, stream=None):
         import torch
 
@@ -291,6 +366,107 @@ class Context:
         nt = torch.empty_like(nv)
         _check(lib().vt_stats(self._ctx, _ptr(nv), _ptr(np_), _ptr(nt), _stream(stream)), "vt_stats")
         return nv, np_, nt
+
+
+def autoborder_thresholds(n, box_lo, box_hi, border_factor=1.5, growth=1.1, steps=48):
+    """Buffer thicknesses tried by AUTOBORDER: border_factor times the mean inter-particle
+    distance (V / n)^(1/3), grown by the factor ``growth`` per step."""
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    s = (float(np.prod(L)) / n) ** (1.0 / 3.0)
+    return border_factor * s * growth ** np.arange(steps, dtype=np.float64)
+
+
+def task_limits(box_lo, box_hi, nt):
+    """Largest buffer thickness per axis (a buffered task spans less than one period)."""
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    nt = np.asarray(nt)
+    w = L / nt
+    return np.where(nt >= 2, 0.5 * (L - w), 0.5 * L) * (1.0 - 1e-12)
+
+
+def owner_tasks(pos_np, box_lo, box_hi, nt):
+    """Owner task of every particle (the library's rule: cell index floor((x - lo) / w))."""
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    nt = np.asarray(nt)
+    w = L / nt
+    i = np.clip(np.floor((np.asarray(pos_np, np.float64) - lo) / w).astype(np.int64), 0, nt - 1)
+    return (i[:, 0] * nt[1] + i[:, 1]) * nt[2] + i[:, 2]
+
+
+def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, steps=48, reruns=3, widen=2.0,
+                     ctx=None, **build_opts):
+    """Tessellate a periodic box as nt[0] x nt[1] x nt[2] tasks with AUTOBORDER buffers, all
+    tasks in one batched build; cells still incomplete are built again, owned alone, with their
+    tasks' buffers widened ``widen`` times (up to ``reruns`` passes).
+
+    Returns a dict with per-particle ``volume`` (numpy), ``status`` (numpy uint8: the last pass
+    that computed the cell), the neighbour CSR ``nbr_off``/``nbr_ids`` in particle order (numpy),
+    the thicknesses ``thick`` (n_tasks x 6) of the first pass and per-pass ``passes`` records.
+    """
+    import torch
+
+    n = pos.shape[0]
+    ctx = ctx or Context()
+    thr = autoborder_thresholds(n, box_lo, box_hi, border_factor, growth, steps)
+    thick, n_own, n_gh = ctx.vt_decompose(pos, box_lo, box_hi, nt, thr)
+    tmax = task_limits(box_lo, box_hi, nt)
+    vol = np.full(n, np.nan)
+    status = np.full(n, 255, np.uint8)
+    last = np.full(n, -1, np.int64)     # pass that computed the cell
+    row = np.full(n, -1, np.int64)      # its row there
+    csr = []                            # per pass: (nbr_off, nbr_ids)
+    passes = []
+    cur = thick.copy()
+    mask, tasks = None, None
+    for rnd in range(reruns + 1):
+        bpos, gid, items = ctx.vt_decompose_pack(pos, box_lo, box_hi, nt, cur, own_mask=mask, tasks=tasks)
+        bctx = Context().vt_build(bpos, items, global_id=gid, **build_opts)
+        cells = bctx.vt_cells()
+        g = gid.cpu().numpy()
+        own_gid = np.concatenate([g[it["offset"]:it["offset"] + it["n_owned"]] for it in items])
+        v = cells.volume.cpu().numpy()
+        st = cells.status.cpu().numpy()
+        off = cells.nbr_off.cpu().numpy()
+        ids = cells.nbr_ids.cpu().numpy()
+        vol[own_gid] = v
+        status[own_gid] = st
+        last[own_gid] = rnd
+        row[own_gid] = np.arange(len(own_gid))
+        csr.append((off, ids))
+        inc = own_gid[(st & CELL_INCOMPLETE) != 0]
+        passes.append(dict(tasks=len(items), particles=int(bpos.shape[0]), owned=int(len(own_gid)),
+                           incomplete=int(len(inc))))
+        del bctx, cells
+        if len(inc) == 0 or rnd == reruns:
+            break
+        # the incomplete cells again, owned alone, with their tasks' buffers widened
+        own = owner_tasks(pos.cpu().numpy(), box_lo, box_hi, nt)
+        tl = np.unique(own[inc]).astype(np.int32)
+        m = np.zeros(n, np.uint8)
+        m[inc] = 1
+        mask = torch.from_numpy(m).to(pos.device)
+        tasks = tl
+        cur = cur.copy()
+        cur[tl] = np.minimum(cur[tl] * widen, np.repeat(tmax, 2)[None, :])
+    # neighbour rows in particle order, each from the last pass that computed the cell
+    cnt = np.zeros(n, np.int64)
+    for k, (off, _) in enumerate(csr):
+        sel = last == k
+        cnt[sel] = off[row[sel] + 1] - off[row[sel]]
+    nbr_off = np.zeros(n + 1, np.int64)
+    nbr_off[1:] = np.cumsum(cnt)
+    nbr_ids = np.zeros(int(nbr_off[-1]), np.int32)
+    for k, (off, ids) in enumerate(csr):
+        p = np.nonzero(last == k)[0]
+        if len(p) == 0:
+            continue
+        ln = cnt[p]
+        src = np.repeat(off[row[p]] - np.cumsum(ln) + ln, ln) + np.arange(ln.sum())
+        dst = np.repeat(nbr_off[p] - np.cumsum(ln) + ln, ln) + np.arange(ln.sum())
+        nbr_ids[dst] = ids[src]
+    return dict(volume=vol, status=status, nbr_off=nbr_off, nbr_ids=nbr_ids, thick=thick, n_owned=n_own,
+                n_ghost=n_gh, passes=passes)
 
 
 def tessellate(pos, box_lo, box_hi, periodic=True, precision=PREC_FP64, want_faces=False, **kw):

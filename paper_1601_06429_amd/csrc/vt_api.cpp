@@ -338,6 +338,7 @@ void vt_destroy(vt_ctx *c) {
     if (!c) return;
     hipDeviceSynchronize();
     free_all(c);
+    vt_dec_free(c);
     for (int k = 0; k < 4; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);
     delete c;

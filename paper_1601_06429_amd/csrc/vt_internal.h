@@ -104,6 +104,14 @@ struct vt_ctx {
     int64_t *rowoff = nullptr;     // facet offsets in output-row order (n_owned + 1)
     int32_t *row2cell = nullptr;   // cell slot of each output row
     uint32_t *h_counters = nullptr;
+    // domain decomposition (decomp.hip)
+    uint32_t *dec_hist = nullptr;  // per task face and threshold: particles in that distance bin
+    int64_t *dec_cnt = nullptr;    // per listed task: owned, buffer counts (then write cursors)
+    int64_t *dec_base = nullptr;   // per listed task: output offsets of its owned and buffer particles
+    double *dec_thick = nullptr;   // 6 per task
+    int32_t *dec_tpos = nullptr;   // task -> position in the list, -1 if not listed
+    double *dec_thr = nullptr;     // thresholds (64)
+    int64_t cap_dec_tasks = 0, cap_dec_hist = 0;
     // optional stage timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
@@ -124,6 +132,7 @@ hipError_t vt_launch_stats(vt_ctx *c, int32_t *nv, int32_t *np, int32_t *nt);
 hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 
 int64_t vt_scan_tmp_elems(int64_t n);
+void vt_dec_free(vt_ctx *c);
 
 // ---------------------------------------------------------------- device helpers
 #ifdef __HIP_DEVICE_COMPILE__

@@ -467,3 +467,56 @@ def test_workload_shapes():
     w5 = wl.diff262k(n=4096)
     assert w5.pos.dtype == np.float32 and np.all((w5.pos >= 0) & (w5.pos < 1))
     assert wl.duplicate_rows(w5.pos).size == 0
+
+
+# ---- AUTOBORDER (section 2, buffer zones): pins of the reference rule
+
+
+def test_autoborder_lattice_at_mean_density_keeps_first_thickness(oracle):
+    # simple-cubic lattice, spacing 1/16: a slab of thickness 2 spacings beyond any face holds two
+    # full layers, exactly the mean density times the face area times the thickness
+    a = 1.0 / 16
+    g = (np.arange(16) + 0.5) * a
+    p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    thr = 2 * a * 1.1 ** np.arange(8)
+    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), thr)
+    assert np.all(t == thr[0])
+
+
+def test_autoborder_empty_neighbour_reaches_cap(oracle):
+    # every particle in the octant of task 0: the faces of the opposite task see empty slabs
+    rng = np.random.default_rng(7)
+    p = rng.random((4000, 3)) * 0.5
+    thr = 0.05 * 1.1 ** np.arange(30)
+    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), thr)
+    cap = oracle.thickness_cap(0.0, 1.0, (2, 2, 2))
+    assert np.all(t[7] == cap[0])
+
+
+def test_autoborder_hand_counted_slab(oracle):
+    # two slabs along x (one task along y and z): 32 particles, mean density 32, face area 1,
+    # expected 32 * 1 * 1/8 = 4 particles.  Beyond the +x face of task 0 (x = 1/2) lie particles
+    # at distances 1/16, 5/32, 11/64, 13/64, 7/32: slab counts 1 (< 1/8), 3 (< 3/16), 4 (< 7/32)
+    d = np.array([1 / 16, 5 / 32, 11 / 64, 13 / 64, 7 / 32])
+    rng = np.random.default_rng(3)
+    beyond = np.column_stack([0.5 + d, rng.random(5), rng.random(5)])
+    own = np.column_stack([rng.uniform(0.0, 0.25, 27), rng.random(27), rng.random(27)])
+    p = np.concatenate([own, beyond])
+    thr = np.array([1 / 8, 3 / 16, 7 / 32])
+    t = oracle.autoborder(p, 0.0, 1.0, (2, 1, 1), thr)
+    assert t[0, 1] == 7 / 32
+    # with 13/64 moved beyond the last threshold, no threshold reaches 4: the last one is taken
+    p2 = p.copy()
+    p2[-2, 0] = 0.5 + 15 / 64
+    assert oracle.autoborder(p2, 0.0, 1.0, (2, 1, 1), thr)[0, 1] == 7 / 32
+    assert oracle.autoborder(p2, 0.0, 1.0, (2, 1, 1), thr[:2])[0, 1] == 3 / 16
+
+
+def test_task_members_images_and_ownership(oracle):
+    # 2 x 2 x 2 tasks of the unit box, buffers 0.1: a particle near the far corner is a buffer
+    # particle of task 0 through its image shifted by -1 on every axis
+    p = np.array([[0.25, 0.25, 0.25], [0.95, 0.95, 0.95], [0.55, 0.25, 0.25]])
+    thick = np.full((8, 6), 0.1)
+    own, buf, sh = oracle.task_members(p, 0.0, 1.0, (2, 2, 2), thick, 0)
+    assert list(own) == [0]
+    assert sorted(zip(buf.tolist(), map(tuple, sh.tolist()))) == [(1, (-1, -1, -1)), (2, (0, 0, 0))]
