@@ -402,7 +402,8 @@ def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, ste
 
     Returns a dict with per-particle ``volume`` (numpy), ``status`` (numpy uint8: the last pass
     that computed the cell), the neighbour CSR ``nbr_off``/``nbr_ids`` in particle order (numpy),
-    the thicknesses ``thick`` (n_tasks x 6) of the first pass and per-pass ``passes`` records.
+    the thicknesses ``thick`` (n_tasks x 6) of the first pass, per-pass ``passes`` records and the
+    ``plan`` of each pass (thicknesses, owner mask, task list) to replay it.
     """
     import torch
 
@@ -416,10 +417,11 @@ def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, ste
     last = np.full(n, -1, np.int64)     # pass that computed the cell
     row = np.full(n, -1, np.int64)      # its row there
     csr = []                            # per pass: (nbr_off, nbr_ids)
-    passes = []
+    passes, plan = [], []
     cur = thick.copy()
     mask, tasks = None, None
     for rnd in range(reruns + 1):
+        plan.append((cur.copy(), mask, tasks))
         bpos, gid, items = ctx.vt_decompose_pack(pos, box_lo, box_hi, nt, cur, own_mask=mask, tasks=tasks)
         bctx = Context().vt_build(bpos, items, global_id=gid, **build_opts)
         cells = bctx.vt_cells()
@@ -466,7 +468,7 @@ def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, ste
         dst = np.repeat(nbr_off[p] - np.cumsum(ln) + ln, ln) + np.arange(ln.sum())
         nbr_ids[dst] = ids[src]
     return dict(volume=vol, status=status, nbr_off=nbr_off, nbr_ids=nbr_ids, thick=thick, n_owned=n_own,
-                n_ghost=n_gh, passes=passes)
+                n_ghost=n_gh, passes=passes, plan=plan)
 
 
 def tessellate(pos, box_lo, box_hi, periodic=True, precision=PREC_FP64, want_faces=False, **kw):

@@ -5,6 +5,9 @@
 * clustered 2M at 256^3 (the benchmark's deposit): a field that is zero except on 96 sampled
   cells (random ones and cells the large kernels handle), every voxel against the oracle's
   exact overlaps of those cells;
+* clustered 2M as 4 x 4 x 4 tasks with AUTOBORDER buffers (one batched build, incomplete cells
+  re-run with wider buffers): neighbour lists identical to the whole-box build, volumes within
+  1e-12;
 * diff262k: the adjoint gradient of a density-matching loss at full size against central
   finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
   perturbed loss is evaluated exactly on a small bounded world around the moved particle
@@ -70,6 +73,21 @@ def test_clustered2m_grid_sampled_cells(vt, torch_cuda, oracle):
     gref = oracle.grid(w.pos.astype(np.float64), w.box_lo, w.box_hi, True, val, dims, query=sample)
     assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
     del ctx, t
+    torch_cuda.cuda.empty_cache()
+
+
+def test_clustered2m_autoborder_decomposition_equals_whole_box(vt, torch_cuda):
+    w = wl.clustered2m()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    res = vt.decomposed_build(t, w.box_lo, w.box_hi, (4, 4, 4), border_factor=1.5)
+    print("passes", res["passes"])
+    assert np.all((res["status"] & (vt.CELL_INCOMPLETE | vt.CELL_FAILED)) == 0)
+    c = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi)).vt_cells()
+    assert np.array_equal(res["nbr_off"], c.nbr_off.cpu().numpy())
+    assert np.array_equal(res["nbr_ids"], c.nbr_ids.cpu().numpy())
+    v = c.volume.cpu().numpy()
+    assert np.max(np.abs(res["volume"] - v) / v) <= 1e-12
+    del c, t
     torch_cuda.cuda.empty_cache()
 
 
