@@ -360,6 +360,23 @@ def main():
                      "mean_tested": float(ntest.to(torch.float64).mean())},
     }
 
+    if not args.fwd_only:
+        # the cheaper grid variant: nearest-particle sampling at the same grid
+        samp = {}
+        for sub in (1, 2):
+            gs = ctx.vt_grid_sample(rho, grid_dims, sub=sub)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                ctx.vt_grid_sample(rho, grid_dims, sub=sub, out=gs)
+            e1.record()
+            e1.synchronize()
+            ms_s = e0.elapsed_time(e1) / 3
+            samp["sub%d" % sub] = {"ms": ms_s, "points_per_s": float(np.prod(grid_dims)) * sub ** 3 / (ms_s * 1e-3),
+                                   "mean_abs_diff_vs_exact_over_mean": float((gs - grid).abs().mean() / grid.mean())}
+        out["grid_sample"] = dict(samp, grid=list(grid_dims), exact_deposit_ms=stage_ms[4])
+
     if not args.no_variants:
         # forward-only comparison of the two precisions at the same accuracy bar
         var = {}

@@ -168,6 +168,25 @@ vt_status vt_grid_deposit(vt_ctx *ctx, const double *value, int32_t nx, int32_t 
                           void *stream);
 
 /*
+ * vt_grid_sample -- a cheaper grid than vt_grid_deposit (the paper lists grid
+ * variants as future work, section 4): every sample point takes the value of
+ * the particle nearest to it, i.e. of the Voronoi cell that contains it
+ * (periodic minimum image, FP64 squared distances; ties go to the smaller
+ * global id).  Voxel (a, b, c) averages the sub^3 points at the centres of its
+ * sub^3 equal sub-cells; sub = 1 samples the voxel centre.  Periodic
+ * single-item contexts only (vt_build takes periodic boxes cubic); anything
+ * else returns VT_ERR_ARG and writes nothing.
+ *   value       device, n_owned_total doubles (output rows).
+ *   sub         1 .. 16.
+ *   grid        device, nx*ny*nz doubles; overwritten.
+ *   nearest_id  device, nx*ny*nz int32 or NULL: the global id of the particle
+ *               nearest to the voxel's last sample point (its centre when
+ *               sub = 1).
+ */
+vt_status vt_grid_sample(vt_ctx *ctx, const double *value, int32_t nx, int32_t ny, int32_t nz, int32_t sub,
+                         double *grid, int32_t *nearest_id, void *stream);
+
+/*
  * vt_backward -- volume adjoint: given g = dL/dV (device, n_owned_total
  * doubles, output rows; ghost cells carry no volume), writes
  *   dL/dx_k = sum_{j in N(k)} (g_k - g_j) A_kj (c_kj - x_k) / |x_j - x_k|

@@ -28,6 +28,11 @@ Readings where the paper is silent (documented with the design notes):
     first thickness (pinned by uniform lattices, where the first thickness
     already suffices, by empty regions, which reach the cap, and by hand-counted
     small sets);
+  * nearest-particle grid sampling (a grid variant the paper leaves to future
+    work): a sample point takes the value of its nearest particle, ties to the
+    smaller index (pinned by lattice points at voxel centres, a two-particle
+    bisector, an exact tie, and convergence to the exact overlaps under finer
+    sub-sampling);
   * adjoint: dV_i/dx_j = A_ij (x_j - c_ij) / d_ij and
     dV_i/dx_i = sum_j A_ij (c_ij - x_i) / d_ij (derived from the motion of the
     bisector plane; pinned by central finite differences of the oracle's own
@@ -305,3 +310,34 @@ def task_members(pos, box_lo, box_hi, nt, thick, task):
                 buf_i.append(k)
                 buf_s.append(np.repeat(sv[None, :], len(k), axis=0))
     return np.nonzero(owner)[0], np.concatenate(buf_i), np.concatenate(buf_s)
+
+
+def grid_sample(pos, box_lo, box_hi, value, dims, sub=1, chunk=4096):
+    """Nearest-particle sampling of a periodic box (a cheaper grid; section 4 lists grid variants
+    as future work): every sample point takes the value of the particle nearest to it, by the
+    minimum-image squared distance ex*ex + ey*ey + ez*ez (FP64), ties to the smaller index.  A
+    voxel averages the sub^3 points at its sub-cell centres.  Brute force over all particles.
+    Returns (grid, index of the particle nearest to each voxel's last sample point)."""
+    x = np.asarray(pos, np.float64)
+    v = np.asarray(value, np.float64)
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    dims = np.asarray(dims, np.int64)
+    h = L / dims
+    ii = np.stack(np.meshgrid(*[np.arange(d) for d in dims], indexing="ij"), -1).reshape(-1, 3)
+    acc = np.zeros(len(ii))
+    last = np.zeros(len(ii), np.int64)
+    for s0 in range(sub):
+        for s1 in range(sub):
+            for s2 in range(sub):
+                ss = np.array([s0, s1, s2], np.float64)
+                q = lo + (ii + (ss + 0.5) / sub) * h
+                for c0 in range(0, len(q), chunk):
+                    qc = q[c0:c0 + chunk]
+                    e = x[None, :, :] - qc[:, None, :]
+                    e = e - L * np.rint(e / L)
+                    d2 = e[:, :, 0] * e[:, :, 0] + e[:, :, 1] * e[:, :, 1] + e[:, :, 2] * e[:, :, 2]
+                    j = np.argmin(d2, axis=1)        # the first (smallest index) of equal minima
+                    acc[c0:c0 + chunk] += v[j]
+                    last[c0:c0 + chunk] = j
+    return (acc / sub ** 3).reshape(tuple(dims)), last.reshape(tuple(dims))

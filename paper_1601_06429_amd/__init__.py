@@ -79,6 +79,7 @@ def lib():
             L.vt_density.argtypes = [P, P, I32, P, P]
             L.vt_gradient.argtypes = [P, P, P, P]
             L.vt_grid_deposit.argtypes = [P, P, I32, I32, I32, P, P]
+            L.vt_grid_sample.argtypes = [P, P, I32, I32, I32, I32, P, P, P]
             L.vt_backward.argtypes = [P, P, P, P]
             L.vt_query.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]
             L.vt_stats.argtypes = [P, P, P, P, P]
@@ -95,7 +96,8 @@ def lib():
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
-                      "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack"):
+                      "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack",
+                      "vt_grid_sample"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -302,6 +304,19 @@ class Context:
         _check(lib().vt_grid_deposit(self._ctx, _ptr(value), nx, ny, nz, _ptr(g), _stream(stream)),
                "vt_grid_deposit")
         return g
+
+    def vt_grid_sample(self, value, dims, sub=1, out=None, nearest=False, stream=None):
+        """Voxel values from the nearest particle of sub^3 points per voxel; with nearest=True
+        also the global id of the particle nearest to each voxel's last point."""
+        import torch
+
+        _require_cuda(value, "value")
+        nx, ny, nz = (int(d) for d in dims)
+        g = out if out is not None else torch.empty((nx, ny, nz), dtype=torch.float64, device=self.device)
+        nid = torch.empty((nx, ny, nz), dtype=torch.int32, device=self.device) if nearest else None
+        _check(lib().vt_grid_sample(self._ctx, _ptr(value), nx, ny, nz, int(sub), _ptr(g), _ptr(nid),
+                                    _stream(stream)), "vt_grid_sample")
+        return (g, nid) if nearest else g
 
     def vt_backward(self, dL_dV, out=None, stream=None):
         import torch

@@ -760,6 +760,354 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
     }
 }
 
+// ---------------------------------------------------------------- nearest-particle sampling
+// A cheaper grid (the paper lists grid variants as future work): every sample point takes the
+// value of the particle nearest to it (periodic minimum image, FP64 squared distances; ties to
+// the smaller global id), i.e. of the Voronoi cell that contains it.  A voxel averages the sub^3
+// points at its sub-cell centres.  One wavefront takes a 4 x 4 x 4 tile of sample points (a
+// lane each) and scans one candidate list for the whole tile: the particles of the Morton cells
+// that cover the tile widened by r, staged through LDS 64 at a time.  A lane is done when its
+// best distance is below r less two key quanta (every particle outside the covered region is
+// farther); otherwise the wave doubles r and scans again.  A tile whose region holds more than
+// 2048 particles (inside a dense halo) lets every lane search on its own through finer cells.
+// The minimum-image shift uses rint(e / L) with 1 / L precomputed; it can round differently
+// from the quotient only near |e| = L / 2, where no nearest particle lies.
+struct SampleArgs {
+    const void *spos;
+    const uint64_t *skey;
+    const int32_t *tab;
+    const int32_t *sgid;
+    const int32_t *srow;
+    const DevItem *items;
+    const double *value;
+    double *grid;
+    int32_t *nearest;   // sub = 1: global id per voxel
+    int32_t *fine;      // sub > 1: sorted index of the nearest particle per sample point
+    int nx, ny, nz, sub;
+    double r0;          // first widening (the mean inter-particle distance)
+};
+
+struct SampleMem {
+    int32_t rb[512];    // covering cells: range starts
+    int32_t rp[513];    // prefix of range lengths
+    double px[64], py[64], pz[64];
+    int32_t pg[64], pj[64];
+};
+
+__device__ __forceinline__ int32_t lower_key(const uint64_t *skey, int32_t a, int32_t c, uint64_t k) {
+    while (a < c) {
+        const int32_t mid = (a + c) >> 1;
+        if (skey[mid] < k) a = mid + 1; else c = mid;
+    }
+    return a;
+}
+
+// sorted-index range of Morton cell m at level l (dense table at levels <= T, binary search below)
+__device__ __forceinline__ void morton_range(const SampleArgs &A, const DevItem &it, int l, uint64_t m, int32_t &b,
+                                             int32_t &e) {
+    if (l <= it.T) {
+        const int sh = 3 * (it.T - l);
+        b = A.tab[it.tab_off + (int64_t)(m << sh)];
+        e = A.tab[it.tab_off + (int64_t)((m + 1) << sh)];
+    } else {
+        const uint64_t mT = m >> (3 * (l - it.T));
+        const int32_t lo = A.tab[it.tab_off + (int64_t)mT], hi = A.tab[it.tab_off + (int64_t)mT + 1];
+        const int sh = 3 * (VT_MORTON_BITS - l);
+        b = lower_key(A.skey, lo, hi, m << sh);
+        e = lower_key(A.skey, b, hi, (m + 1) << sh);
+    }
+}
+
+// One point's nearest particle by its own search (used where a tile's region is dense): from the
+// point's Morton cell (coarsened while empty, refined while it holds more than 32 particles),
+// shells of cells at growing Chebyshev distance k until the best distance is below k cell
+// sides less two key quanta.
+template <typename PT4>
+__device__ int32_t nearest_particle(const SampleArgs &A, const DevItem &it, const double q[3], const double invL[3],
+                                    int32_t &bg) {
+    int64_t qq[3];
+    for (int a = 0; a < 3; ++a) qq[a] = vt_qclamp(vt_qraw(q[a], it.lo[a], it.inv_res));
+    auto cell_at = [&](int l) -> uint64_t {
+        const int sh = VT_MORTON_BITS - l;
+        return vt_morton((uint64_t)qq[0] >> sh, (uint64_t)qq[1] >> sh, (uint64_t)qq[2] >> sh);
+    };
+    int l = it.T;
+    int32_t b, e;
+    morton_range(A, it, l, cell_at(l), b, e);
+    while (e == b && l > 1) {
+        --l;
+        morton_range(A, it, l, cell_at(l), b, e);
+    }
+    while (e - b > 32 && l < VT_MORTON_BITS) {
+        int32_t b2, e2;
+        morton_range(A, it, l + 1, cell_at(l + 1), b2, e2);
+        if (e2 == b2) break;
+        ++l;
+        b = b2;
+        e = e2;
+    }
+    const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
+    const double side = it.S / (double)(1ll << l);
+    const int64_t ncl = 1ll << l;
+    const int sh = VT_MORTON_BITS - l;
+    const int64_t cq[3] = {qq[0] >> sh, qq[1] >> sh, qq[2] >> sh};
+    double best = 1e300;
+    int32_t bj = -1;
+    bg = 0x7FFFFFFF;
+    for (int k = 0;; ++k) {
+        for (int dx = -k; dx <= k; ++dx)
+            for (int dy = -k; dy <= k; ++dy)
+                for (int dz = -k; dz <= k; ++dz) {
+                    if (max(abs(dx), max(abs(dy), abs(dz))) != k) continue;
+                    const uint64_t cx = (uint64_t)(((cq[0] + dx) % ncl + ncl) % ncl);
+                    const uint64_t cy = (uint64_t)(((cq[1] + dy) % ncl + ncl) % ncl);
+                    const uint64_t cz = (uint64_t)(((cq[2] + dz) % ncl + ncl) % ncl);
+                    int32_t cb, ce;
+                    morton_range(A, it, l, vt_morton(cx, cy, cz), cb, ce);
+                    for (int32_t j = cb; j < ce; ++j) {
+                        double px, py, pz;
+                        gpos<PT4>(A.spos, j, px, py, pz);
+                        double ex = px - q[0], ey = py - q[1], ez = pz - q[2];
+                        ex -= it.L[0] * rint(ex * invL[0]);
+                        ey -= it.L[1] * rint(ey * invL[1]);
+                        ez -= it.L[2] * rint(ez * invL[2]);
+                        const double d2 = ex * ex + ey * ey + ez * ez;
+                        const int32_t gj = A.sgid[j];
+                        if (d2 < best || (d2 == best && gj < bg)) {
+                            best = d2;
+                            bg = gj;
+                            bj = j;
+                        }
+                    }
+                }
+        const double reach = (double)k * side - 2.0 * quantum;
+        if (bj >= 0 && reach > 0.0 && best < reach * reach) break;
+        if (2 * k + 1 >= ncl) break;  // the block covers the whole box
+    }
+    return bj;
+}
+
+template <typename PT4>
+__global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
+    extern __shared__ char smem[];
+    SampleMem &S = *reinterpret_cast<SampleMem *>(smem + (size_t)(threadIdx.x >> 6) * sizeof(SampleMem));
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const DevItem &it = A.items[0];
+    const int sub = A.sub;
+    const int64_t fd[3] = {(int64_t)A.nx * sub, (int64_t)A.ny * sub, (int64_t)A.nz * sub};
+    const int64_t ntile[3] = {(fd[0] + 3) / 4, (fd[1] + 3) / 4, (fd[2] + 3) / 4};
+    const int64_t n_tiles = ntile[0] * ntile[1] * ntile[2];
+    const int dims[3] = {A.nx, A.ny, A.nz};
+    const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
+    const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tiles; t += nwaves) {
+        const int64_t tz = t % ntile[2], ty = (t / ntile[2]) % ntile[1], tx = t / (ntile[1] * ntile[2]);
+        const int64_t f[3] = {tx * 4 + (lane >> 4), ty * 4 + ((lane >> 2) & 3), tz * 4 + (lane & 3)};
+        const bool valid = f[0] < fd[0] && f[1] < fd[1] && f[2] < fd[2];
+        // the sample point: voxel i, sub-cell s (the reference's expression)
+        double q[3], tlo[3], thi[3];
+        for (int a = 0; a < 3; ++a) {
+            const double h = it.L[a] / dims[a];
+            const int64_t fa = valid ? f[a] : 0;
+            q[a] = it.lo[a] + ((double)(fa / sub) + ((double)(fa % sub) + 0.5) / (double)sub) * h;
+            // the tile's extent: its first and last points along a
+            const int64_t f0 = (a == 0 ? tx : a == 1 ? ty : tz) * 4;
+            const int64_t f1 = min(f0 + 3, fd[a] - 1);
+            tlo[a] = it.lo[a] + ((double)(f0 / sub) + ((double)(f0 % sub) + 0.5) / (double)sub) * h;
+            thi[a] = it.lo[a] + ((double)(f1 / sub) + ((double)(f1 % sub) + 0.5) / (double)sub) * h;
+        }
+        double best = 1e300;
+        int32_t bg = 0x7FFFFFFF, bj = -1;
+        for (double r = A.r0;; r *= 2.0) {
+            // covering Morton cells: side c >= r (coarser while more than 512 would be needed)
+            int l = 0;
+            double c = it.S;
+            while (l < VT_MORTON_BITS && 0.5 * c >= r) {
+                c *= 0.5;
+                ++l;
+            }
+            int64_t a0[3], na[3];
+            bool whole = false;
+            for (;;) {
+                const int64_t ncl = 1ll << l;
+                whole = true;
+                for (int a = 0; a < 3; ++a) {
+                    int64_t i0 = (int64_t)floor((tlo[a] - r - it.lo[a]) / c) - 1;
+                    int64_t i1 = (int64_t)floor((thi[a] + r - it.lo[a]) / c) + 1;
+                    if (i1 - i0 + 1 >= ncl) {
+                        i0 = 0;
+                        i1 = ncl - 1;
+                    } else {
+                        whole = false;
+                    }
+                    a0[a] = i0;
+                    na[a] = i1 - i0 + 1;
+                }
+                if (na[0] * na[1] * na[2] <= 512 || l == 0) break;
+                --l;
+                c *= 2.0;
+            }
+            const int64_t ncl = 1ll << l;
+            const int ncells = (int)(na[0] * na[1] * na[2]);
+            int count = 0;
+            for (int base = 0; base < ncells; base += 64) {
+                const int k = base + lane;
+                int32_t cb = 0, ce = 0;
+                if (k < ncells) {
+                    const int64_t u[3] = {a0[0] + k % na[0], a0[1] + (k / na[0]) % na[1], a0[2] + k / (na[0] * na[1])};
+                    const uint64_t cx = (uint64_t)((u[0] % ncl + ncl) % ncl), cy = (uint64_t)((u[1] % ncl + ncl) % ncl),
+                                   cz = (uint64_t)((u[2] % ncl + ncl) % ncl);
+                    morton_range(A, it, l, vt_morton(cx, cy, cz), cb, ce);
+                }
+                const bool keep = ce > cb;
+                const uint64_t km = __ballot(keep);
+                if (keep) {
+                    const int slot = count + __popcll(km & lt);
+                    S.rb[slot] = cb;
+                    S.rp[slot] = ce - cb;
+                }
+                count += __popcll(km);
+            }
+            wave_sync();
+            int carry = 0;
+            for (int base = 0; base < count; base += 64) {
+                const int k = base + lane;
+                const int len = k < count ? S.rp[k] : 0;
+                int tot;
+                const int pre = wave_excl_scan(len, &tot);
+                if (k < count) S.rp[k] = carry + pre;
+                carry += tot;
+            }
+            if (lane == 0) S.rp[count] = carry;
+            wave_sync();
+            const int total = carry;
+            if (total > 2048) {
+                // a dense region: every lane searches on its own, through finer cells
+                if (valid) bj = nearest_particle<PT4>(A, it, q, invL, bg);
+                break;
+            }
+            for (int c0 = 0; c0 < total; c0 += 64) {
+                const int fi = c0 + lane;
+                if (fi < total) {
+                    int lo = 0, hi = count - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (S.rp[mid] <= fi) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t j = S.rb[lo] + (fi - S.rp[lo]);
+                    double px, py, pz;
+                    gpos<PT4>(A.spos, j, px, py, pz);
+                    S.px[lane] = px;
+                    S.py[lane] = py;
+                    S.pz[lane] = pz;
+                    S.pg[lane] = A.sgid[j];
+                    S.pj[lane] = j;
+                }
+                wave_sync();
+                const int nc = min(64, total - c0);
+                for (int k = 0; k < nc; ++k) {
+                    double ex = S.px[k] - q[0], ey = S.py[k] - q[1], ez = S.pz[k] - q[2];
+                    ex -= it.L[0] * rint(ex * invL[0]);
+                    ey -= it.L[1] * rint(ey * invL[1]);
+                    ez -= it.L[2] * rint(ez * invL[2]);
+                    const double d2 = ex * ex + ey * ey + ez * ez;
+                    const int32_t gj = S.pg[k];
+                    if (d2 < best || (d2 == best && gj < bg)) {
+                        best = d2;
+                        bg = gj;
+                        bj = S.pj[k];
+                    }
+                }
+                wave_sync();
+            }
+            const double reach = r - 2.0 * quantum;
+            const bool done = whole || (bj >= 0 && reach > 0.0 && best < reach * reach);
+            if (__ballot(valid && !done) == 0ull) break;
+        }
+        if (valid) {
+            if (sub == 1) {
+                const int64_t v = (f[0] * A.ny + f[1]) * A.nz + f[2];
+                A.grid[v] = A.value[A.srow[bj]];
+                if (A.nearest) A.nearest[v] = bg;
+            } else {
+                A.fine[(f[0] * fd[1] + f[1]) * fd[2] + f[2]] = bj;
+            }
+        }
+    }
+}
+
+// sub > 1: each voxel averages its sub^3 points in the reference's order
+__global__ void k_sample_average(SampleArgs A) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nv = (int64_t)A.nx * A.ny * A.nz;
+    if (v >= nv) return;
+    const int sub = A.sub;
+    const int64_t iz = v % A.nz, iy = (v / A.nz) % A.ny, ix = v / ((int64_t)A.ny * A.nz);
+    const int64_t fy = (int64_t)A.ny * sub, fz = (int64_t)A.nz * sub;
+    double acc = 0.0;
+    int32_t last = 0;
+    for (int s0 = 0; s0 < sub; ++s0)
+        for (int s1 = 0; s1 < sub; ++s1)
+            for (int s2 = 0; s2 < sub; ++s2) {
+                const int32_t j = A.fine[((ix * sub + s0) * fy + (iy * sub + s1)) * fz + (iz * sub + s2)];
+                acc += A.value[A.srow[j]];
+                last = j;
+            }
+    A.grid[v] = acc / (double)(sub * sub * sub);
+    if (A.nearest) A.nearest[v] = A.sgid[last];
+}
+
+hipError_t vt_launch_grid_sample(vt_ctx *c, const double *value, int nx, int ny, int nz, int sub, double *grid,
+                                 int32_t *nearest) {
+    SampleArgs a;
+    a.spos = c->spos;
+    a.skey = c->skey;
+    a.tab = c->tab;
+    a.sgid = c->sgid;
+    a.srow = c->srow;
+    a.items = c->items;
+    a.value = value;
+    a.grid = grid;
+    a.nearest = nearest;
+    a.fine = nullptr;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.sub = sub;
+    const DevItem &it = c->h_items[0];
+    a.r0 = cbrt(it.L[0] * it.L[1] * it.L[2] / (double)c->n_total);
+    const int64_t nfine = (int64_t)nx * ny * nz * sub * sub * sub;
+    if (sub > 1) {
+        if (nfine > c->cap_samp) {
+            if (c->samp_fine) hipFree(c->samp_fine);
+            c->samp_fine = nullptr;
+            c->cap_samp = 0;
+            hipError_t e = hipMalloc((void **)&c->samp_fine, sizeof(int32_t) * (size_t)nfine);
+            if (e != hipSuccess) return e;
+            c->cap_samp = nfine;
+        }
+        a.fine = c->samp_fine;
+    }
+    const size_t lds = sizeof(SampleMem) * 4;
+    int ncu = 0;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (ncu <= 0) ncu = 256;
+    const int64_t tiles = ((int64_t)nx * sub + 3) / 4 * (((int64_t)ny * sub + 3) / 4) * (((int64_t)nz * sub + 3) / 4);
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > (int64_t)ncu * 64) blocks = (int64_t)ncu * 64;
+    if (c->dtype == VT_F32)
+        k_sample_tiles<float4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
+    else
+        k_sample_tiles<double4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sub == 1) return e;
+    const int64_t nv = (int64_t)nx * ny * nz;
+    k_sample_average<<<(nv + 255) / 256, 256, 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
 __global__ void k_zero_f64(double *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;

@@ -284,6 +284,17 @@ vt_status vt_grid_deposit(vt_ctx *c, const double *value, int32_t nx, int32_t ny
     return VT_OK;
 }
 
+vt_status vt_grid_sample(vt_ctx *c, const double *value, int32_t nx, int32_t ny, int32_t nz, int32_t sub,
+                         double *grid, int32_t *nearest_id, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!value || !grid || nx < 1 || ny < 1 || nz < 1 || sub < 1 || sub > 16 || c->n_items != 1) return VT_ERR_ARG;
+    if (!c->h_items || !c->h_items[0].periodic) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    clear_stale_error();
+    TRY(vt_launch_grid_sample(c, value, nx, ny, nz, sub, grid, nearest_id));
+    return VT_OK;
+}
+
 vt_status vt_backward(vt_ctx *c, const double *dL_dV, double *dL_dx, void *stream) {
     if (!c || !c->built) return VT_ERR_STATE;
     if (!c->faces_valid) return VT_ERR_STATE;
@@ -339,6 +350,7 @@ void vt_destroy(vt_ctx *c) {
     hipDeviceSynchronize();
     free_all(c);
     vt_dec_free(c);
+    if (c->samp_fine) hipFree(c->samp_fine);
     for (int k = 0; k < 4; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);
     delete c;

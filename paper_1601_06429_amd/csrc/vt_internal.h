@@ -112,6 +112,9 @@ struct vt_ctx {
     int32_t *dec_tpos = nullptr;   // task -> position in the list, -1 if not listed
     double *dec_thr = nullptr;     // thresholds (64)
     int64_t cap_dec_tasks = 0, cap_dec_hist = 0;
+    // nearest-particle sampling: per sample point, the nearest particle (sorted index)
+    int32_t *samp_fine = nullptr;
+    int64_t cap_samp = 0;
     // optional stage timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
@@ -127,6 +130,8 @@ hipError_t vt_launch_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t 
 hipError_t vt_launch_density(vt_ctx *c, const void *mass, vt_dtype dt, double *rho);
 hipError_t vt_launch_gradient(vt_ctx *c, const double *rho, double *grad);
 hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz, double *grid);
+hipError_t vt_launch_grid_sample(vt_ctx *c, const double *value, int nx, int ny, int nz, int sub, double *grid,
+                                 int32_t *nearest);
 hipError_t vt_launch_backward(vt_ctx *c, const double *g, double *out);
 hipError_t vt_launch_stats(vt_ctx *c, int32_t *nv, int32_t *np, int32_t *nt);
 hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);

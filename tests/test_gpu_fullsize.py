@@ -8,6 +8,8 @@
 * clustered 2M as 4 x 4 x 4 tasks with AUTOBORDER buffers (one batched build, incomplete cells
   re-run with wider buffers): neighbour lists identical to the whole-box build, volumes within
   1e-12;
+* clustered 2M sampled at 256^3 (nearest-particle grid variant): the nearest ids of 200k
+  random voxel centres against scipy's periodic k-d tree;
 * diff262k: the adjoint gradient of a density-matching loss at full size against central
   finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
   perturbed loss is evaluated exactly on a small bounded world around the moved particle
@@ -88,6 +90,33 @@ def test_clustered2m_autoborder_decomposition_equals_whole_box(vt, torch_cuda):
     v = c.volume.cpu().numpy()
     assert np.max(np.abs(res["volume"] - v) / v) <= 1e-12
     del c, t
+    torch_cuda.cuda.empty_cache()
+
+
+def test_clustered2m_grid_sample_against_kdtree(vt, torch_cuda):
+    from scipy.spatial import cKDTree
+
+    w = wl.clustered2m()
+    t = torch_cuda.from_numpy(w.pos).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
+    dims = (256, 256, 256)
+    val = torch_cuda.arange(w.n, dtype=torch_cuda.float64).cuda()
+    g, near = ctx.vt_grid_sample(val, dims, nearest=True)
+    assert ctx.vt_query()[0] == 0
+    near = near.cpu().numpy().reshape(-1)
+    rng = np.random.default_rng(6006)
+    v = rng.choice(near.size, 200_000, replace=False)
+    ii = np.stack(np.unravel_index(v, dims), -1)
+    q = (ii + 0.5) * (w.box_len / np.asarray(dims))
+    p = w.pos.astype(np.float64)
+    d, j = cKDTree(p, boxsize=w.box_len).query(q)
+    miss = np.nonzero(j != near[v])[0]
+    if len(miss):
+        e = p[near[v][miss]] - q[miss]
+        e -= w.box_len * np.rint(e / w.box_len)
+        assert np.allclose(np.sqrt((e * e).sum(1)), d[miss], rtol=1e-14, atol=0)
+    assert np.array_equal(g.cpu().numpy().reshape(-1)[v], near[v].astype(np.float64))
+    del ctx, t, g
     torch_cuda.cuda.empty_cache()
 
 

@@ -520,3 +520,46 @@ def test_task_members_images_and_ownership(oracle):
     own, buf, sh = oracle.task_members(p, 0.0, 1.0, (2, 2, 2), thick, 0)
     assert list(own) == [0]
     assert sorted(zip(buf.tolist(), map(tuple, sh.tolist()))) == [(1, (-1, -1, -1)), (2, (0, 0, 0))]
+
+
+# ---- nearest-particle grid sampling (grid variant): pins of the reference
+
+
+def test_grid_sample_lattice_points_at_voxel_centres(oracle):
+    # one lattice point at every voxel centre: each voxel takes its own point's value
+    n = 8
+    g = (np.arange(n) + 0.5) / n
+    p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    val = np.arange(len(p), dtype=np.float64)
+    grid, near = oracle.grid_sample(p, 0.0, 1.0, val, (n, n, n))
+    assert np.array_equal(near.reshape(-1), np.arange(len(p)))
+    assert np.array_equal(grid.reshape(-1), val)
+
+
+def test_grid_sample_two_particles_follow_the_bisector(oracle):
+    # two particles at x = 0.25 and 0.75: the periodic bisectors are x = 0.5 and x = 0 (mod 1),
+    # so voxel columns with centre x in (0, 0.5) take particle 0
+    p = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]])
+    grid, near = oracle.grid_sample(p, 0.0, 1.0, np.array([1.0, 2.0]), (8, 4, 4))
+    xc = (np.arange(8) + 0.5) / 8
+    want = np.where(xc < 0.5, 0, 1)
+    assert np.array_equal(near[:, 0, 0], want)
+    assert np.all(near == near[:, :1, :1])
+
+
+def test_grid_sample_tie_goes_to_smaller_index(oracle):
+    # the voxel centre (0.5, 0.5, 0.5) of a 1x1x1 grid is equidistant (exactly) from both
+    p = np.array([[0.75, 0.5, 0.5], [0.25, 0.5, 0.5]])
+    _, near = oracle.grid_sample(p, 0.0, 1.0, np.array([1.0, 2.0]), (1, 1, 1))
+    assert near[0, 0, 0] == 0
+
+
+def test_grid_sample_converges_to_exact_overlaps(oracle):
+    # finer sub-sampling approaches the exact volume average of the Voronoi field
+    rng = np.random.default_rng(11)
+    p = rng.random((60, 3))
+    val = rng.uniform(0.5, 2.0, len(p))
+    exact = oracle.grid(p, 0.0, 1.0, True, val, (4, 4, 4))
+    errs = [np.abs(oracle.grid_sample(p, 0.0, 1.0, val, (4, 4, 4), sub=s)[0] - exact).mean() for s in (1, 4, 16)]
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[2] < 0.05 * errs[0]
