@@ -767,11 +767,16 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
 // points at its sub-cell centres.  One wavefront takes a 4 x 4 x 4 tile of sample points (a
 // lane each) and scans one candidate list for the whole tile: the particles of the Morton cells
 // that cover the tile widened by r, staged through LDS 64 at a time.  A lane is done when its
-// best distance is below r less two key quanta (every particle outside the covered region is
-// farther); otherwise the wave doubles r and scans again.  A tile whose region holds more than
-// 2048 particles (inside a dense halo) lets every lane search on its own through finer cells.
+// best distance is below its distance to the sides of the covered cells less two key quanta
+// (every particle outside them is farther); otherwise the wave doubles r and scans again.  A
+// tile whose region holds more than VT_SAMPLE_DENSE particles (inside a dense halo) lets every
+// lane search on its own through finer cells.
 // The minimum-image shift uses rint(e / L) with 1 / L precomputed; it can round differently
 // from the quotient only near |e| = L / 2, where no nearest particle lies.
+#ifndef VT_SAMPLE_DENSE
+#define VT_SAMPLE_DENSE 4096   // candidates above which a tile's lanes search on their own
+#endif
+
 struct SampleArgs {
     const void *spos;
     const uint64_t *skey;
@@ -820,8 +825,8 @@ __device__ __forceinline__ void morton_range(const SampleArgs &A, const DevItem 
 
 // One point's nearest particle by its own search (used where a tile's region is dense): from the
 // point's Morton cell (coarsened while empty, refined while it holds more than 32 particles),
-// shells of cells at growing Chebyshev distance k until the best distance is below k cell
-// sides less two key quanta.
+// shells of cells at growing Chebyshev distance k until the best distance is below the point's
+// distance to the sides of the (2k+1)^3 block less two key quanta.
 template <typename PT4>
 __device__ int32_t nearest_particle(const SampleArgs &A, const DevItem &it, const double q[3], const double invL[3],
                                     int32_t &bg) {
@@ -851,6 +856,12 @@ __device__ int32_t nearest_particle(const SampleArgs &A, const DevItem &it, cons
     const int64_t ncl = 1ll << l;
     const int sh = VT_MORTON_BITS - l;
     const int64_t cq[3] = {qq[0] >> sh, qq[1] >> sh, qq[2] >> sh};
+    // the point's distance to the nearest side of its own cell
+    double edge = 1e300;
+    for (int a = 0; a < 3; ++a) {
+        const double b0 = it.lo[a] + (double)cq[a] * side;
+        edge = fmin(edge, fmin(q[a] - b0, b0 + side - q[a]));
+    }
     double best = 1e300;
     int32_t bj = -1;
     bg = 0x7FFFFFFF;
@@ -880,7 +891,7 @@ __device__ int32_t nearest_particle(const SampleArgs &A, const DevItem &it, cons
                         }
                     }
                 }
-        const double reach = (double)k * side - 2.0 * quantum;
+        const double reach = (double)k * side + edge - 2.0 * quantum;
         if (bj >= 0 && reach > 0.0 && best < reach * reach) break;
         if (2 * k + 1 >= ncl) break;  // the block covers the whole box
     }
@@ -929,18 +940,16 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
                 ++l;
             }
             int64_t a0[3], na[3];
-            bool whole = false;
+            bool whole[3];
             for (;;) {
                 const int64_t ncl = 1ll << l;
-                whole = true;
                 for (int a = 0; a < 3; ++a) {
-                    int64_t i0 = (int64_t)floor((tlo[a] - r - it.lo[a]) / c) - 1;
-                    int64_t i1 = (int64_t)floor((thi[a] + r - it.lo[a]) / c) + 1;
-                    if (i1 - i0 + 1 >= ncl) {
+                    int64_t i0 = (int64_t)floor((tlo[a] - r - it.lo[a]) / c);
+                    int64_t i1 = (int64_t)floor((thi[a] + r - it.lo[a]) / c);
+                    whole[a] = i1 - i0 + 1 >= ncl;
+                    if (whole[a]) {
                         i0 = 0;
                         i1 = ncl - 1;
-                    } else {
-                        whole = false;
                     }
                     a0[a] = i0;
                     na[a] = i1 - i0 + 1;
@@ -949,6 +958,15 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
                 --l;
                 c *= 2.0;
             }
+            // the lane's reach: its distance to the nearest side of the covered cells (axes not
+            // covered whole), less two key quanta for the rounding of particle keys
+            double reach = 1e300;
+            for (int a = 0; a < 3; ++a)
+                if (!whole[a]) {
+                    const double b0 = it.lo[a] + (double)a0[a] * c, b1 = it.lo[a] + (double)(a0[a] + na[a]) * c;
+                    reach = fmin(reach, fmin(q[a] - b0, b1 - q[a]));
+                }
+            reach -= 2.0 * quantum;
             const int64_t ncl = 1ll << l;
             const int ncells = (int)(na[0] * na[1] * na[2]);
             int count = 0;
@@ -983,7 +1001,7 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
             if (lane == 0) S.rp[count] = carry;
             wave_sync();
             const int total = carry;
-            if (total > 2048) {
+            if (total > VT_SAMPLE_DENSE) {
                 // a dense region: every lane searches on its own, through finer cells
                 if (valid) bj = nearest_particle<PT4>(A, it, q, invL, bg);
                 break;
@@ -1022,8 +1040,7 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
                 }
                 wave_sync();
             }
-            const double reach = r - 2.0 * quantum;
-            const bool done = whole || (bj >= 0 && reach > 0.0 && best < reach * reach);
+            const bool done = (whole[0] && whole[1] && whole[2]) || (bj >= 0 && reach > 0.0 && best < reach * reach);
             if (__ballot(valid && !done) == 0ull) break;
         }
         if (valid) {
