@@ -383,6 +383,33 @@ class Context:
         return nv, np_, nt
 
 
+def task_grid(n_task, scheme="a", axis=0):
+    """Tasks per axis for the paper's two decomposition schemes (section 2).
+
+    Scheme "a" cuts the box in halves, along x, then y, then z, and round again, until there are
+    n_task equal regions (n_task a power of two; 32 gives 4 x 4 x 2).  Scheme "b" cuts it
+    n_task times along one axis (elongated volumes).
+    """
+    n_task = int(n_task)
+    if n_task < 1:
+        raise ValueError("n_task must be positive")
+    nt = [1, 1, 1]
+    if scheme == "a":
+        if n_task & (n_task - 1):
+            raise ValueError("scheme a needs a power-of-two task count, got %d" % n_task)
+        a = 0
+        while nt[0] * nt[1] * nt[2] < n_task:
+            nt[a] *= 2
+            a = (a + 1) % 3
+    elif scheme == "b":
+        if axis not in (0, 1, 2):
+            raise ValueError("axis must be 0, 1 or 2")
+        nt[axis] = n_task
+    else:
+        raise ValueError("scheme must be 'a' or 'b'")
+    return tuple(nt)
+
+
 def autoborder_thresholds(n, box_lo, box_hi, border_factor=1.5, growth=1.1, steps=48):
     """Buffer thicknesses tried by AUTOBORDER: border_factor times the mean inter-particle
     distance (V / n)^(1/3), grown by the factor ``growth`` per step."""
@@ -413,7 +440,8 @@ def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, ste
                      ctx=None, **build_opts):
     """Tessellate a periodic box as nt[0] x nt[1] x nt[2] tasks with AUTOBORDER buffers, all
     tasks in one batched build; cells still incomplete are built again, owned alone, with their
-    tasks' buffers widened ``widen`` times (up to ``reruns`` passes).
+    tasks' buffers widened ``widen`` times (up to ``reruns`` passes).  An integer nt is a task
+    count split by scheme (a) (``task_grid``).
 
     Returns a dict with per-particle ``volume`` (numpy), ``status`` (numpy uint8: the last pass
     that computed the cell), the neighbour CSR ``nbr_off``/``nbr_ids`` in particle order (numpy),
@@ -423,6 +451,9 @@ def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, ste
     import torch
 
     n = pos.shape[0]
+    if np.ndim(nt) == 0:
+        nt = task_grid(nt, "a")
+    nt = tuple(int(x) for x in nt)
     ctx = ctx or Context()
     thr = autoborder_thresholds(n, box_lo, box_hi, border_factor, growth, steps)
     thick, n_own, n_gh = ctx.vt_decompose(pos, box_lo, box_hi, nt, thr)

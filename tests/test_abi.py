@@ -69,3 +69,21 @@ def test_autotune_selection_logic():
     b = autotune.signature("MI355X", "torch.float32", 3_000_000, 1, 0)
     d = autotune.signature("MI355X", "torch.float32", 4_500_000, 1, 0)
     assert a == b and a != d
+
+
+def test_task_grid_schemes():
+    from paper_1601_06429_amd import task_grid
+
+    # the paper's example of scheme (a) (section 2): 32 tasks are 4 x 4 x 2
+    assert task_grid(32) == (4, 4, 2)
+    for k in range(11):
+        nt = task_grid(2 ** k)
+        assert nt[0] * nt[1] * nt[2] == 2 ** k
+        assert nt[0] >= nt[1] >= nt[2] and nt[0] <= 2 * nt[2]   # cuts balanced over the axes
+    assert task_grid(1) == (1, 1, 1) and task_grid(64) == (4, 4, 4)
+    # scheme (b): slabs along one axis
+    assert task_grid(12, "b") == (12, 1, 1) and task_grid(5, "b", axis=2) == (1, 1, 5)
+    with pytest.raises(ValueError):
+        task_grid(12)              # scheme (a) needs a power of two
+    with pytest.raises(ValueError):
+        task_grid(4, "c")

@@ -66,7 +66,7 @@ def test_decompose_pack_writes_owned_and_buffer_images(vt, torch_cuda, oracle, c
         assert got == want
 
 
-@pytest.mark.parametrize("nt", [(4, 4, 4), (2, 1, 1)])
+@pytest.mark.parametrize("nt", [(4, 4, 4), (2, 1, 1), 8])   # 8: scheme (a), 2 x 2 x 2
 def test_decomposed_build_equals_whole_box(vt, torch_cuda, oracle, clustered262k, nt):
     p = clustered262k.pos
     res = vt.decomposed_build(torch_cuda.from_numpy(p).cuda(), 0.0, 1.0, nt, border_factor=1.5)
