@@ -16,6 +16,7 @@ vertices) and the brute-force FP64 oracle timed on a bounded sample of the same
 workload on the host cores.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -376,6 +377,33 @@ def main():
             samp["sub%d" % sub] = {"ms": ms_s, "points_per_s": float(np.prod(grid_dims)) * sub ** 3 / (ms_s * 1e-3),
                                    "mean_abs_diff_vs_exact_over_mean": float((gs - grid).abs().mean() / grid.mean())}
         out["grid_sample"] = dict(samp, grid=list(grid_dims), exact_deposit_ms=stage_ms[4])
+
+        # the full structure output (vertices and faces as loops): one library call with the
+        # output arrays in place (count pass, scans, totals read back, write pass)
+        st = ctx.vt_structure()
+        sizes = (ctypes.c_int64 * 3)()
+        nv_, nf_, nl_ = st.verts.shape[0], st.face_nbr.numel(), st.loop_vert.numel()
+
+        def structure_call():
+            rc = vt.lib().vt_structure(ctx._ctx, vt._ptr(st.vert_off), vt._ptr(st.verts), nv_, vt._ptr(st.face_off),
+                                       vt._ptr(st.face_nbr), nf_, vt._ptr(st.loop_off), vt._ptr(st.loop_vert), nl_,
+                                       sizes, vt._stream())
+            assert rc == vt.VT_OK, rc
+
+        structure_call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            structure_call()
+        e1.record()
+        e1.synchronize()
+        ms_st = e0.elapsed_time(e1) / 3
+        nbytes = 16 * (N + 1) + 24 * nv_ + 4 * nf_ + 8 * (nf_ + 1) + 4 * nl_
+        out["structure"] = {"ms": ms_st, "cells_per_s": N / (ms_st * 1e-3), "bytes_per_particle": nbytes / N,
+                            "written_GB_per_s": nbytes / (ms_st * 1e-3) / 1e9,
+                            "vertices_per_cell": nv_ / N, "faces_per_cell": nf_ / N}
+        del st
 
     if not args.no_variants:
         # forward-only comparison of the two precisions at the same accuracy bar

@@ -187,6 +187,41 @@ vt_status vt_grid_sample(vt_ctx *ctx, const double *value, int32_t nx, int32_t n
                          double *grid, int32_t *nearest_id, void *stream);
 
 /*
+ * vt_structure -- the full tessellation structure of the owned cells (the
+ * paper's optional full structure output: section 3, memory consumption;
+ * section 4): every cell's vertices and its faces as vertex loops, CSR in
+ * output-row order.
+ *   vert_off   device, n_owned_total + 1 int64: cell i's vertices are rows
+ *              vert_off[i] .. vert_off[i+1]-1 of verts.
+ *   verts      device, vert_cap x 3 doubles: absolute coordinates, the seed
+ *              plus the vertex's offset (a cell of a periodic box is kept
+ *              whole, so its vertices may lie outside the box).
+ *   face_off   device, n_owned_total + 1 int64: cell i's faces.
+ *   face_nbr   device, face_cap int32: the global id across each face, or
+ *              -1 .. -6 for the walls -x, +x, -y, +y, -z, +z of a bounded
+ *              item.  A cell's faces ascend by it.  Faces of area <=
+ *              area_eps V^(2/3) are left out, so the nonnegative entries of a
+ *              row are its neighbour list (vt_cells); a cell that loses such a
+ *              face keeps a hole of at most that area (its loops then hold
+ *              fewer than three entries per vertex).
+ *   loop_off   device, face_cap + 1 int64: face f's loop is
+ *              loop_vert[loop_off[f] .. loop_off[f+1]-1].
+ *   loop_vert  device, loop_cap int32: vertex indices local to the cell
+ *              (0 .. vertices - 1), counter-clockwise seen from outside the
+ *              cell, starting at the face's smallest index.
+ *   sizes      host, 3 int64 (out): total vertices, faces and loop entries.
+ * The offsets are always written.  If a total exceeds its capacity, or an
+ * output pointer is NULL, nothing else is written and VT_ERR_CAPACITY is
+ * returned with sizes filled: call again with arrays of those sizes.  Needs a
+ * build with want_faces (else VT_ERR_STATE).  Synchronizes the stream (it
+ * reads the totals).  A cell whose face loops do not close is left empty and
+ * vt_query reports VT_ERR_TOPOLOGY.
+ */
+vt_status vt_structure(vt_ctx *ctx, int64_t *vert_off, double *verts, int64_t vert_cap, int64_t *face_off,
+                       int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert, int64_t loop_cap,
+                       int64_t sizes[3], void *stream);
+
+/*
  * vt_backward -- volume adjoint: given g = dL/dV (device, n_owned_total
  * doubles, output rows; ghost cells carry no volume), writes
  *   dL/dx_k = sum_{j in N(k)} (g_k - g_j) A_kj (c_kj - x_k) / |x_j - x_k|

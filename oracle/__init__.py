@@ -83,6 +83,9 @@ def _load():
             lib.ora_grid.argtypes = [i64, p, p, p, ctypes.c_int, i64, p, p, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
             lib.ora_grid.restype = ctypes.c_int
+            lib.ora_structure.argtypes = [i64, p, p, p, p, ctypes.c_int, i64, ctypes.c_double, ctypes.c_double,
+                                          i64, i64, i64, p, p, p, p, p, p]
+            lib.ora_structure.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -146,6 +149,32 @@ def cells(pos, box_lo, box_hi, periodic=True, query=None, gid=None, tol=1e-12, a
     if np.any(flags & FLAG_CAPACITY):
         raise RuntimeError("ora_cells: a cell has more than %d facets; raise stride" % stride)
     return Cells(q, vol, rmax, flags, nnb, topo, nbr, farea, fcen, fdist)
+
+
+def structure(pos, box_lo, box_hi, i, periodic=True, gid=None, tol=1e-12, area_eps=1e-12, cap=4096):
+    """Full structure of cell i (section 3, memory consumption; section 4): its vertices
+    (absolute, k x 3, every vertex on a face) and its faces of positive area as a list of
+    (id across the face, loop of vertex numbers counter-clockwise seen from outside), ascending
+    by id; the id is the neighbour's global id, or -1 .. -6 for the walls -x, +x, -y, +y, -z, +z."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, np.float64), 3))
+    hi = np.ascontiguousarray(np.broadcast_to(np.asarray(box_hi, np.float64), 3))
+    g = None if gid is None else np.ascontiguousarray(gid, dtype=np.int64)
+    verts = np.zeros((cap, 3))
+    fid = np.zeros(cap, np.int64)
+    floff = np.zeros(cap + 1, np.int64)
+    lverts = np.zeros(4 * cap, np.int32)
+    nv = np.zeros(1, np.int64)
+    nf = np.zeros(1, np.int64)
+    rc = lib.ora_structure(pos.shape[0], _ptr(pos), _ptr(g), _ptr(lo), _ptr(hi), int(bool(periodic)), int(i), tol,
+                           area_eps, cap, cap, 4 * cap, _ptr(verts), _ptr(nv), _ptr(fid), _ptr(floff), _ptr(nf),
+                           _ptr(lverts))
+    if rc != 0:
+        raise RuntimeError("ora_structure failed with code %d" % rc)
+    k, m = int(nv[0]), int(nf[0])
+    faces = [(int(fid[a]), lverts[floff[a]:floff[a + 1]].copy()) for a in range(m)]
+    return verts[:k].copy(), faces
 
 
 def density(mass, volume):

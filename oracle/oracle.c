@@ -898,3 +898,94 @@ int ora_grid(int64_t n, const double *pos, const double *lo, const double *hi, i
     }
     return err;
 }
+
+/*
+ * ora_structure: the full structure of cell i (the optional full structure
+ * output: section 3, memory consumption; section 4): its vertices and its
+ * faces as vertex loops.
+ *   verts[3k..3k+2]   vertex k, absolute (seed + offset), k < *nv: every
+ *                     vertex that lies on a face, in the polytope's order
+ *   fid[f]            the id across face f: the neighbour's global id (gid,
+ *                     else index), or -1 .. -6 for the walls -x, +x, -y, +y,
+ *                     -z, +z; faces of area <= area_eps V^(2/3) are left out
+ *                     and the rest are listed in ascending order of fid
+ *   floff[f..f+1]     face f's loop in lverts (floff[0] = 0), vertex numbers
+ *                     as in verts, counter-clockwise seen from outside
+ *   *nv, *nf          vertex and face counts
+ * Capacities vcap, fcap (floff holds fcap + 1) and lcap; ORA_ERR_CAPACITY if
+ * one is too small.
+ */
+int ora_structure(int64_t n, const double *pos, const int64_t *gid, const double *lo, const double *hi, int periodic,
+                  int64_t i, double tol, double area_eps, int64_t vcap, int64_t fcap, int64_t lcap, double *verts,
+                  int64_t *nv, int64_t *fid, int64_t *floff, int64_t *nf, int32_t *lverts) {
+    world Wd;
+    int rc = set_world(&Wd, n, pos, gid, lo, hi, periodic);
+    if (rc) return rc;
+    if (i < 0 || i >= n || !verts || !nv || !fid || !floff || !nf || !lverts) return ORA_ERR_ARG;
+    work W;
+    memset(&W, 0, sizeof(W));
+    poly *P = NULL;
+    double r2;
+    int64_t np;
+    rc = build_cell(&Wd, i, &W, &P, tol, &r2, &np);
+    face_geom *fg = NULL;
+    int *num = NULL, *ord = NULL;
+    if (!rc) {
+        fg = (face_geom *)malloc(sizeof(face_geom) * (size_t)(P->nf > 0 ? P->nf : 1));
+        num = (int *)malloc(sizeof(int) * (size_t)(P->nv > 0 ? P->nv : 1));
+        ord = (int *)malloc(sizeof(int) * (size_t)(P->nf > 0 ? P->nf : 1));
+        if (!fg || !num || !ord) rc = ORA_ERR_NOMEM;
+    }
+    if (!rc) {
+        double V = poly_measure(P, fg);
+        double amin = area_eps * pow(fabs(V), 2.0 / 3.0);
+        /* vertices on some face, numbered in the polytope's order */
+        for (int k = 0; k < P->nv; ++k) num[k] = -1;
+        for (int f = 0; f < P->nf; ++f)
+            for (int k = 0; k < P->flen[f]; ++k) num[P->fv[P->fofs[f] + k]] = 0;
+        int64_t cntv = 0;
+        for (int k = 0; k < P->nv; ++k)
+            if (num[k] == 0) num[k] = (int)cntv++;
+        /* kept faces, ascending by the id across them */
+        int cnt = 0;
+        for (int f = 0; f < P->nf; ++f)
+            if (fg[f].area > amin) ord[cnt++] = f;
+        for (int a = 1; a < cnt; ++a) {
+            int f = ord[a];
+            int64_t g = P->ftag[f] >= 0 && gid ? gid[P->ftag[f]] : P->ftag[f];
+            int b = a - 1;
+            while (b >= 0) {
+                int64_t gb = P->ftag[ord[b]] >= 0 && gid ? gid[P->ftag[ord[b]]] : P->ftag[ord[b]];
+                if (gb <= g) break;
+                ord[b + 1] = ord[b];
+                --b;
+            }
+            ord[b + 1] = f;
+        }
+        int64_t cntl = 0;
+        for (int a = 0; a < cnt; ++a) cntl += P->flen[ord[a]];
+        if (cntv > vcap || cnt > fcap || cntl > lcap) {
+            rc = ORA_ERR_CAPACITY;
+        } else {
+            for (int k = 0; k < P->nv; ++k)
+                if (num[k] >= 0)
+                    for (int c = 0; c < 3; ++c) verts[3 * num[k] + c] = pos[3 * i + c] + P->v[3 * k + c];
+            *nv = cntv;
+            *nf = cnt;
+            int64_t o = 0;
+            floff[0] = 0;
+            for (int a = 0; a < cnt; ++a) {
+                int f = ord[a];
+                int64_t t = P->ftag[f];
+                fid[a] = t >= 0 && gid ? gid[t] : t;
+                for (int k = 0; k < P->flen[f]; ++k) lverts[o++] = num[P->fv[P->fofs[f] + k]];
+                floff[a + 1] = o;
+            }
+        }
+    }
+    free(fg);
+    free(num);
+    free(ord);
+    work_free(&W);
+    return rc;
+}

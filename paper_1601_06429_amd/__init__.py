@@ -91,13 +91,14 @@ def lib():
             L.vt_decompose_pack.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, ctypes.POINTER(I32), D3, P,
                                             ctypes.POINTER(I32), I32, P, P, I64, ctypes.POINTER(vt_item),
                                             ctypes.POINTER(I64), P]
+            L.vt_structure.argtypes = [P, P, P, I64, P, P, I64, P, P, I64, ctypes.POINTER(I64), P]
             L.vt_destroy.argtypes = [P]
             L.vt_destroy.restype = None
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
                       "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack",
-                      "vt_grid_sample"):
+                      "vt_grid_sample", "vt_structure"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -195,6 +196,27 @@ class Cells:
     status: object     # torch uint8 [n_owned]
 
 
+@dataclass
+class Structure:
+    """Cell structure (``Context.vt_structure``): CSR arrays on the device."""
+    vert_off: "object"    # n + 1 int64
+    verts: "object"       # V x 3 float64, absolute coordinates
+    face_off: "object"    # n + 1 int64
+    face_nbr: "object"    # F int32: global id across the face, -1 .. -6 for walls
+    loop_off: "object"    # F + 1 int64
+    loop_vert: "object"   # int32 vertex indices local to the cell
+
+    def cell(self, i):
+        """Vertices (numpy, k x 3) and faces [(id, loop indices)] of row i, read back to the host."""
+        v0, v1 = int(self.vert_off[i]), int(self.vert_off[i + 1])
+        f0, f1 = int(self.face_off[i]), int(self.face_off[i + 1])
+        lo = self.loop_off[f0:f1 + 1].cpu().numpy()
+        lv = self.loop_vert[int(lo[0]):int(lo[-1])].cpu().numpy() if f1 > f0 else np.zeros(0, np.int32)
+        ids = self.face_nbr[f0:f1].cpu().numpy()
+        faces = [(int(ids[k]), lv[lo[k] - lo[0]:lo[k + 1] - lo[0]]) for k in range(f1 - f0)]
+        return self.verts[v0:v1].cpu().numpy(), faces
+
+
 class Context:
     """Owns a vt_ctx; methods map one to one onto the C ABI."""
 
@@ -271,6 +293,34 @@ class Context:
         _check(lib().vt_cells(self._ctx, _ptr(vol), _ptr(off), _ptr(ids), int(nbr_cap), _ptr(st), _stream(stream)),
                "vt_cells")
         return Cells(vol, off, ids[: int(nbr_cap)], st)
+
+    def vt_structure(self, stream=None):
+        """The full structure of the owned cells (needs a build with want_faces): a
+        ``Structure`` of device tensors -- vertices (absolute, V x 3) with per-cell offsets,
+        faces (the id across each face: a neighbour's global id, or -1 .. -6 for the walls of a
+        bounded item) with per-cell offsets, and each face's vertex loop (indices local to the
+        cell, counter-clockwise seen from outside) with per-face offsets."""
+        import torch
+
+        dev = self.device
+        n = self.n_owned
+        voff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        foff = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        sizes = (ctypes.c_int64 * 3)()
+        code = lib().vt_structure(self._ctx, _ptr(voff), None, 0, _ptr(foff), None, 0, None, None, 0, sizes,
+                                  _stream(stream))
+        if code != VT_ERR_CAPACITY:
+            _check(code, "vt_structure")
+        nv, nf, nl = int(sizes[0]), int(sizes[1]), int(sizes[2])
+        verts = torch.empty((max(nv, 1), 3), dtype=torch.float64, device=dev)
+        fnbr = torch.empty(max(nf, 1), dtype=torch.int32, device=dev)
+        loff = torch.empty(nf + 1, dtype=torch.int64, device=dev)
+        lv = torch.empty(max(nl, 1), dtype=torch.int32, device=dev)
+        _check(lib().vt_structure(self._ctx, _ptr(voff), _ptr(verts), nv, _ptr(foff), _ptr(fnbr), nf, _ptr(loff),
+                                  _ptr(lv), nl, sizes, _stream(stream)), "vt_structure")
+        if nf == 0:
+            loff.zero_()
+        return Structure(voff, verts[:nv], foff, fnbr[:nf], loff, lv[:nl])
 
     def vt_cells_into(self, vol, off, ids, status=None, stream=None):
         _check(lib().vt_cells(self._ctx, _ptr(vol), _ptr(off), _ptr(ids), int(ids.numel()), _ptr(status),

@@ -21,7 +21,7 @@
 // The grid lines are evaluated at X_i + 1e-12 h (likewise in y and z): a
 // vertex or face exactly on a grid line (lattice inputs) then has no tie; the
 // overlap volumes move by at most 1e-12 of a voxel.
-#include "poly.h"
+#include "rebuild.h"
 
 template <int VPL>
 struct GridMem {
@@ -65,21 +65,6 @@ struct GridArgs {
     double *grid;
     int nx, ny, nz;
 };
-
-// a double held by lane l (l the same in every lane)
-__device__ __forceinline__ double readlane_d(double x, int l) {
-    const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint64_t lo = readlane_u32((uint32_t)u, l), hi = readlane_u32((uint32_t)(u >> 32), l);
-    return __longlong_as_double((long long)((hi << 32) | lo));
-}
-
-template <typename PT4>
-__device__ __forceinline__ void gpos(const void *spos, int32_t j, double &x, double &y, double &z) {
-    PT4 p = ((const PT4 *)spos)[j];
-    x = (double)p.x;
-    y = (double)p.y;
-    z = (double)p.z;
-}
 
 __device__ __forceinline__ int64_t wrapi(int64_t i, int n) {
     int64_t r = i % n;
@@ -360,135 +345,10 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
             }
             Poly<double, VPL> P;
-            bool bad = false, over = false, have = false;
-            // ---- the clip kernel's topology record, if the cell has a well-formed one: every face
-            // plane comes from its tag, every vertex is the intersection of its three planes (in the
-            // triple's order, as the clip kernel computes it), and the face masks follow from the
-            // triples.  Any index out of range sends the cell to the rebuild below.
-            if constexpr (!RETRY && VPL == 1) {
-                const int nf = A.cnf[c], nv = A.cnv[c];
-                if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64) {
-                    const int64_t tb = (int64_t)c * VT_TOPO_STRIDE;
-                    bool ok = true;
-                    if (lane < nf) {
-                        const int32_t tag = A.ctopo[tb + lane];
-                        P4<double> p;
-                        if (tag >= 0 && (int64_t)tag < A.npos) {
-                            double qx, qy, qz;
-                            gpos<PT4>(A.spos, tag, qx, qy, qz);
-                            qx -= sx;
-                            qy -= sy;
-                            qz -= sz;
-                            if (it.periodic) {
-                                qx -= it.L[0] * rint(qx * (1.0 / it.L[0]));
-                                qy -= it.L[1] * rint(qy * (1.0 / it.L[1]));
-                                qz -= it.L[2] * rint(qz * (1.0 / it.L[2]));
-                            }
-                            p.x = qx;
-                            p.y = qy;
-                            p.z = qz;
-                            p.d = 0.5 * (qx * qx + qy * qy + qz * qz);
-                        } else if (tag < 0 && tag >= -6) {
-                            // wall -1 .. -6: -x, +x, -y, +y, -z, +z of the seed-relative box
-                            const int b = -1 - tag, a = b >> 1;
-                            const bool pos = b & 1;
-                            p.x = (a == 0) ? (pos ? 1.0 : -1.0) : 0.0;
-                            p.y = (a == 1) ? (pos ? 1.0 : -1.0) : 0.0;
-                            p.z = (a == 2) ? (pos ? 1.0 : -1.0) : 0.0;
-                            p.d = pos ? bhi[a] : -blo[a];
-                        } else {
-                            ok = false;
-                            p.x = p.y = p.z = p.d = 0.0;
-                        }
-                        S.P.pl64[lane] = p;
-                        S.P.fm[lane][0] = 0ull;
-                    }
-                    uint32_t t = 0, k0 = 0, k1 = 0, k2 = 0;
-                    if (lane < nv) {
-                        t = (uint32_t)A.ctopo[tb + VT_TOPO_FACES + lane];
-                        k0 = t & 0xFFu;
-                        k1 = (t >> 8) & 0xFFu;
-                        k2 = (t >> 16) & 0xFFu;
-                        if ((t >> 24) || k0 >= (uint32_t)nf || k1 >= (uint32_t)nf || k2 >= (uint32_t)nf || k0 == k1 ||
-                            k1 == k2 || k0 == k2)
-                            ok = false;
-                    }
-                    if (__ballot(!ok) == 0ull) {
-                        wave_sync();
-                        double x = 0.0, y = 0.0, z = 0.0;
-                        if (lane < nv) {
-                            intersect3<double>(S.P.pl64[k0], S.P.pl64[k1], S.P.pl64[k2], x, y, z);
-                            atomicOr((unsigned long long *)&S.P.fm[k0][0], (unsigned long long)mybit);
-                            atomicOr((unsigned long long *)&S.P.fm[k1][0], (unsigned long long)mybit);
-                            atomicOr((unsigned long long *)&S.P.fm[k2][0], (unsigned long long)mybit);
-                        }
-                        const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
-                        if (__ballot(!fin) == 0ull) {
-                            P.vx[0] = x;
-                            P.vy[0] = y;
-                            P.vz[0] = z;
-                            P.vt[0] = t;
-                            P.alive[0] = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
-                            P.fa[0] = (1ull << nf) - 1ull;
-                            have = true;
-                        }
-                        wave_sync();
-                    }
-                }
-            }
-            // ---- otherwise rebuild the cell from its facets.  The planes are loaded lane-parallel;
-            // the normal kernel applies them nearest first (the cell then stays close to its final
-            // size, 64 vertices suffice), the large kernel in stored order.  A cell that still
-            // outgrows the normal kernel goes to the large one.
-            if (!have) P.init_box(S.P, blo, bhi);
-            const int64_t row = A.crow[c];
-            const int32_t cnt = have ? 0 : A.ccnt[c];
-            for (int32_t t0 = 0; t0 < cnt && !bad && !over; t0 += 64) {
-                const int32_t t = t0 + lane;
-                double qx = 0.0, qy = 0.0, qz = 0.0;
-                int32_t qj = -1;
-                uint64_t key = ~0ull;
-                if (t < cnt) {
-                    qj = A.stage_ids[row + t];
-                    gpos<PT4>(A.spos, qj, qx, qy, qz);
-                    qx -= sx;
-                    qy -= sy;
-                    qz -= sz;
-                    if (it.periodic) {
-                        qx -= it.L[0] * rint(qx / it.L[0]);
-                        qy -= it.L[1] * rint(qy / it.L[1]);
-                        qz -= it.L[2] * rint(qz / it.L[2]);
-                    }
-                    const float d2f = (float)(qx * qx + qy * qy + qz * qz);
-                    key = RETRY ? (uint64_t)lane : (((uint64_t)__float_as_uint(d2f) << 32) | (uint64_t)lane);
-                }
-                if (!RETRY) {
-                    uint64_t kk[1] = {key};
-                    bitonic_u64<1>(kk);
-                    key = kk[0];
-                }
-                const int nin = min(64, cnt - t0);
-                for (int i = 0; i < nin; ++i) {
-                    const int src = (int)(readlane_u32((uint32_t)(key & 0xFFFFFFFFull), i) & 63u);
-                    P4<double> p;
-                    p.x = __shfl(qx, src);
-                    p.y = __shfl(qy, src);
-                    p.z = __shfl(qz, src);
-                    p.d = 0.5 * (p.x * p.x + p.y * p.y + p.z * p.z);
-                    const int32_t j = __shfl(qj, src);
-                    const int rc = P.clip(S.P, p, j);
-                    if (rc == CLIP_OVERFLOW && !RETRY) {
-                        over = true;
-                        break;
-                    }
-                    if (rc < 0) {
-                        if (lane == 0) atomicOr(&A.counters[CTR_DEBUG], 1u << (-rc));
-                        bad = true;
-                        break;
-                    }
-                }
-            }
-            if (over) {
+            const CellSrc src{A.spos, A.ctopo, A.cnf, A.cnv, A.npos, A.crow, A.ccnt, A.stage_ids, A.counters};
+            const int rb = rebuild_cell<PT4, VPL, RETRY>(src, it, S.P, P, c, sx, sy, sz, blo, bhi);
+            if (rb == REBUILD_OVERFLOW) {
+                // the cell outgrows the normal kernel: the large one takes it
                 if (lane == 0) {
                     const uint32_t qi = atomicAdd(&A.counters[CTR_GRID_Q], 1u);
                     if ((int64_t)qi < A.gqueue_cap) A.gqueue[qi] = c;
@@ -496,7 +356,7 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
                 continue;
             }
-            if (bad) {
+            if (rb == REBUILD_FAILED) {
                 if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
                 continue;
             }

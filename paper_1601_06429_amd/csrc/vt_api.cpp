@@ -295,6 +295,20 @@ vt_status vt_grid_sample(vt_ctx *c, const double *value, int32_t nx, int32_t ny,
     return VT_OK;
 }
 
+vt_status vt_structure(vt_ctx *c, int64_t *vert_off, double *verts, int64_t vert_cap, int64_t *face_off,
+                       int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert, int64_t loop_cap,
+                       int64_t sizes[3], void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!c->faces_valid) return VT_ERR_STATE;
+    if (!vert_off || !face_off || !sizes || vert_cap < 0 || face_cap < 0 || loop_cap < 0) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    clear_stale_error();
+    bool fits = false;
+    TRY(vt_launch_structure(c, vert_off, verts, vert_cap, face_off, face_nbr, face_cap, loop_off, loop_vert, loop_cap,
+                            sizes, &fits));
+    return fits ? VT_OK : VT_ERR_CAPACITY;
+}
+
 vt_status vt_backward(vt_ctx *c, const double *dL_dV, double *dL_dx, void *stream) {
     if (!c || !c->built) return VT_ERR_STATE;
     if (!c->faces_valid) return VT_ERR_STATE;
@@ -350,6 +364,7 @@ void vt_destroy(vt_ctx *c) {
     hipDeviceSynchronize();
     free_all(c);
     vt_dec_free(c);
+    vt_struct_free(c);
     if (c->samp_fine) hipFree(c->samp_fine);
     for (int k = 0; k < 4; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);

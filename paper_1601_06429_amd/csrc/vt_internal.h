@@ -34,6 +34,7 @@
 #define CTR_GRID_RETRY 8
 #define CTR_DEBUG 9        // bit k set: a clip in the grid kernel returned -k (diagnostics)
 #define CTR_GRID_Q 10      // grid deposit: cells handed from the normal to the large kernel
+#define CTR_STRUCT_Q 11    // structure output: cells handed from the normal to the large kernel
 #define CTR_COUNT 12
 
 // per-item description on the device
@@ -115,6 +116,13 @@ struct vt_ctx {
     // nearest-particle sampling: per sample point, the nearest particle (sorted index)
     int32_t *samp_fine = nullptr;
     int64_t cap_samp = 0;
+    // structure output (structure.hip): per-row counts (vertices, faces, loop entries), loop
+    // offsets per row, per-cell large-kernel marks, overflow queue
+    int64_t *st_cnt = nullptr;
+    int64_t *st_lbase = nullptr;
+    uint8_t *smark = nullptr;
+    int32_t *squeue = nullptr;
+    int64_t cap_struct = 0;
     // optional stage timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
@@ -138,6 +146,10 @@ hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 
 int64_t vt_scan_tmp_elems(int64_t n);
 void vt_dec_free(vt_ctx *c);
+hipError_t vt_launch_structure(vt_ctx *c, int64_t *vert_off, double *verts, int64_t vert_cap, int64_t *face_off,
+                               int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert,
+                               int64_t loop_cap, int64_t sizes[3], bool *fits);
+void vt_struct_free(vt_ctx *c);
 
 // ---------------------------------------------------------------- device helpers
 #ifdef __HIP_DEVICE_COMPILE__

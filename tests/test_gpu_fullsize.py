@@ -10,6 +10,9 @@
   1e-12;
 * clustered 2M sampled at 256^3 (nearest-particle grid variant): the nearest ids of 200k
   random voxel centres against scipy's periodic k-d tree;
+* clustered 2M full structure: every cell's face ids against its neighbour list, its volume
+  by the divergence theorem over its face loops, Euler's formula; 32 sampled cells (the eight
+  largest among them) against the oracle's structure;
 * diff262k: the adjoint gradient of a density-matching loss at full size against central
   finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
   perturbed loss is evaluated exactly on a small bounded world around the moved particle
@@ -118,6 +121,56 @@ def test_clustered2m_grid_sample_against_kdtree(vt, torch_cuda):
     assert np.array_equal(g.cpu().numpy().reshape(-1)[v], near[v].astype(np.float64))
     del ctx, t, g
     torch_cuda.cuda.empty_cache()
+
+
+def test_clustered2m_structure(vt, torch_cuda, oracle):
+    """Full structure of every cell: face ids against the neighbour lists, divergence volumes
+    against the cell volumes and Euler's formula (on the device), and sampled cells, the
+    largest ones included, against the oracle's structure."""
+    T = torch_cuda
+    w = wl.clustered2m()
+    ctx = vt.Context().vt_build(T.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi), want_faces=True)
+    cells = ctx.vt_cells()
+    st = ctx.vt_structure()
+    assert ctx.vt_query()[0] == 0
+    n = w.n
+    voff, foff, loff = st.vert_off, st.face_off, st.loop_off
+    nf = st.face_nbr.numel()
+    keep = st.face_nbr >= 0
+    assert T.equal(st.face_nbr[keep], cells.nbr_ids)
+    cell_of_face = T.repeat_interleave(T.arange(n, device="cuda"), foff.diff())
+    assert T.equal(T.bincount(cell_of_face[keep], minlength=n), cells.nbr_off.diff())
+    face_of_loop = T.repeat_interleave(T.arange(nf, device="cuda"), loff.diff())
+    c = cell_of_face[face_of_loop]
+    seeds = T.from_numpy(w.pos.astype(np.float64)).cuda()
+    v = st.verts[voff[c] + st.loop_vert.long()] - seeds[c]
+    nxt = T.arange(v.shape[0], device="cuda") + 1
+    nxt[loff[1:] - 1] = loff[:-1]
+    N = T.zeros((nf, 3), dtype=T.float64, device="cuda").index_add_(0, face_of_loop, T.cross(v, v[nxt], dim=1))
+    del nxt
+    vol = T.zeros(n, dtype=T.float64, device="cuda").index_add_(0, cell_of_face, (N * v[loff[:-1]]).sum(1) / 6.0)
+    assert ((vol - cells.volume).abs() / cells.volume).max().item() <= 1e-11
+    V, F = voff.diff(), foff.diff()
+    Lc = T.bincount(c, minlength=n)
+    closed = Lc == 3 * V
+    assert T.all((V - Lc // 2 + F)[closed] == 2)
+    assert closed.double().mean().item() >= 0.999
+    del v, N, c, face_of_loop, cell_of_face
+    # sampled cells against the oracle, the largest (cells of the large kernels) among them
+    nv = V.cpu().numpy()
+    rows = np.concatenate([np.argsort(nv)[-8:], np.random.default_rng(7007).choice(n, 24, replace=False)])
+    assert nv[rows].max() > 64
+    p64 = w.pos.astype(np.float64)
+    for r in rows:
+        vg, fg = st.cell(int(r))
+        vo, fo = oracle.structure(p64, w.box_lo, w.box_hi, int(r))
+        assert len(vg) == len(vo) and [j for j, _ in fg] == [j for j, _ in fo], r
+        for (_, lg), (_, lo_) in zip(fg, fo):
+            A, B = vg[lg], vo[lo_]
+            k = int(np.argmin(((A - B[0]) ** 2).sum(1)))
+            assert len(lg) == len(lo_) and np.max(np.abs(np.roll(A, -k, axis=0) - B)) <= 1e-10, r
+    del ctx, st, cells
+    T.cuda.empty_cache()
 
 
 def _target(torch, x, lam, phi, amp, mean):

@@ -1,0 +1,213 @@
+"""Full cell structure (vt_structure) on the GPU:
+
+* sampled cells against the oracle's structure: the same vertex count, the same faces (ids
+  across them, in ascending order), every face loop equal to the oracle's up to where it starts
+  (same orientation), vertices within 1e-12;
+* over every cell: the nonnegative face ids are the neighbour lists of vt_cells exactly, the
+  volume by the divergence theorem over the face loops equals the cell volume, and Euler's
+  formula holds for every cell that lost no face to the facet area rule;
+* the clustered set (cells of the large kernels included), the mixed-precision build, bounded
+  batched worlds with walls, the capacity protocol, and a .vtu file written from the output.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1601_06429_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(st):
+    return {k: getattr(st, k).cpu().numpy() for k in ("vert_off", "verts", "face_off", "face_nbr", "loop_off",
+                                                      "loop_vert")}
+
+
+def _cell(h, i):
+    v = h["verts"][h["vert_off"][i]:h["vert_off"][i + 1]]
+    f0, f1 = h["face_off"][i], h["face_off"][i + 1]
+    lo = h["loop_off"]
+    return v, [(int(h["face_nbr"][f]), h["loop_vert"][lo[f]:lo[f + 1]]) for f in range(f0, f1)]
+
+
+def _same_loop(vg, lg, vo, lo_, tol):
+    if len(lg) != len(lo_):
+        return False
+    A, B = vg[lg], vo[lo_]
+    k = int(np.argmin(((A - B[0]) ** 2).sum(1)))
+    return np.max(np.abs(np.roll(A, -k, axis=0) - B)) <= tol
+
+
+def _against_oracle(oracle, h, rows, p, lo, hi, periodic=True, gid=None, local=None, tol=1e-12):
+    for r in rows:
+        i = r if local is None else local(r)
+        vg, fg = _cell(h, r)
+        vo, fo = oracle.structure(p, lo, hi, i, periodic=periodic, gid=gid)
+        assert len(vg) == len(vo), r
+        assert [j for j, _ in fg] == [j for j, _ in fo], r
+        for (_, lg), (_, lo_) in zip(fg, fo):
+            assert _same_loop(vg, lg, vo, lo_, tol), r
+
+
+def _whole_cell_checks(h, seeds, cells):
+    """Every row: face ids against the neighbour lists, divergence volume, Euler's formula."""
+    n = len(seeds)
+    voff, foff, loff, lv = h["vert_off"], h["face_off"], h["loop_off"], h["loop_vert"].astype(np.int64)
+    nbr_off, nbr_ids = cells.nbr_off.cpu().numpy(), cells.nbr_ids.cpu().numpy()
+    ids = h["face_nbr"]
+    keep = ids >= 0
+    cell_of_face = np.repeat(np.arange(n), np.diff(foff))
+    assert np.array_equal(ids[keep], nbr_ids)
+    assert np.array_equal(np.bincount(cell_of_face[keep], minlength=n), np.diff(nbr_off))
+    nf = len(ids)
+    flen = np.diff(loff)
+    face_of_loop = np.repeat(np.arange(nf), flen)
+    c = cell_of_face[face_of_loop]
+    g = voff[c] + lv
+    nxt = np.arange(len(lv)) + 1
+    last = loff[1:] - 1
+    nxt[last] = loff[:-1]
+    v = h["verts"][g] - seeds[c]
+    w = v[nxt]
+    N = np.zeros((nf, 3))
+    np.add.at(N, face_of_loop, np.cross(v, w))
+    vol = np.zeros(n)
+    np.add.at(vol, cell_of_face, (N * v[loff[:-1]]).sum(1) / 6.0)
+    ref = cells.volume.cpu().numpy()
+    assert np.max(np.abs(vol - ref) / ref) <= 1e-11
+    # Euler's formula for every closed cell: one whose loops hold each vertex three times (a cell
+    # that lost a face of area <= area_eps V^(2/3) to the facet rule has fewer entries)
+    V = np.diff(voff)
+    Lc = np.bincount(c, minlength=n)
+    F = np.diff(foff)
+    closed = Lc == 3 * V
+    assert np.all(V[closed] - Lc[closed] // 2 + F[closed] == 2)
+    assert closed.mean() >= 0.999, closed.mean()
+
+
+def test_structure_uniform_matches_oracle(vt, torch_cuda, oracle):
+    w = wl.uniform4096()
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi),
+                                want_faces=True)
+    cells = ctx.vt_cells()
+    h = _host(ctx.vt_structure())
+    assert ctx.vt_query()[0] == 0
+    _whole_cell_checks(h, w.pos.astype(np.float64), cells)
+    rows = np.random.default_rng(31).choice(w.n, 64, replace=False)
+    _against_oracle(oracle, h, rows, w.pos, w.box_lo, w.box_hi)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_structure_clustered_with_large_cells(vt, torch_cuda, oracle, precision):
+    w = wl.diff262k()
+    prec = vt.PREC_FP64 if precision == "fp64" else vt.PREC_MIXED
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(w.pos).cuda(), vt.whole_box(w.n, 0.0, 1.0),
+                                want_faces=True, precision=prec)
+    cells = ctx.vt_cells()
+    h = _host(ctx.vt_structure())
+    assert ctx.vt_query()[0] == 0
+    p64 = w.pos.astype(np.float64)
+    _whole_cell_checks(h, p64, cells)
+    nv = np.diff(h["vert_off"])
+    big = np.argsort(nv)[-8:]
+    rows = np.concatenate([big, np.random.default_rng(32).choice(w.n, 24, replace=False)])
+    _against_oracle(oracle, h, rows, p64, 0.0, 1.0)
+
+
+def test_structure_large_cell_matches_oracle(vt, torch_cuda, oracle):
+    # a seed inside a shell of 60 particles: its cell has about 116 vertices, more than the
+    # normal kernels hold, and its shell neighbours have large cells too
+    rng = np.random.default_rng(34)
+    bg = rng.random((4096, 3))
+    bg = bg[np.linalg.norm(bg - 0.5, axis=1) > 0.08]
+    d = rng.standard_normal((60, 3))
+    shell = 0.5 + 0.05 * d / np.linalg.norm(d, axis=1, keepdims=True)
+    p = np.concatenate([[[0.5, 0.5, 0.5]], shell, bg])
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(p).cuda(), vt.whole_box(len(p), 0.0, 1.0), want_faces=True)
+    cells = ctx.vt_cells()
+    h = _host(ctx.vt_structure())
+    assert ctx.vt_query()[0] == 0
+    assert np.diff(h["vert_off"])[0] > 64
+    assert cells.status.cpu().numpy()[0] & vt.CELL_RETRIED
+    _whole_cell_checks(h, p, cells)
+    _against_oracle(oracle, h, range(0, 61), p, 0.0, 1.0)
+
+
+def test_structure_bounded_worlds_with_walls(vt, torch_cuda, oracle):
+    rng = np.random.default_rng(33)
+    worlds = []
+    for k in range(3):
+        lo = np.array([0.0, 0.0, 0.0]) + k
+        owned = lo + 0.1 + 0.8 * rng.random((3000, 3))
+        ghosts = lo + rng.random((1500, 3))
+        ghosts = ghosts[np.any((ghosts < lo + 0.1) | (ghosts > lo + 0.9), axis=1)]
+        worlds.append((owned, ghosts, lo, lo + 1.0))
+    pos, items, gid = vt.pack_worlds(worlds)
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(pos).cuda(), items,
+                                global_id=torch_cuda.from_numpy(gid).cuda(), want_faces=True)
+    h = _host(ctx.vt_structure())
+    assert ctx.vt_query()[0] == 0
+    row = 0
+    for it in items:
+        o, no, ng = it["offset"], it["n_owned"], it["n_ghost"]
+        wp = pos[o:o + no + ng]
+        rows = row + np.array([0, 1, 2, no // 2, no - 1])
+        _against_oracle(oracle, h, rows, wp, it["lo"], it["hi"], periodic=False,
+                        gid=np.arange(o, o + no + ng), local=lambda r, row=row: r - row)
+        # walls: ids -1 .. -6 and their vertices on the wall planes
+        for r in range(row, row + no):
+            v, faces = _cell(h, r)
+            for j, lp in faces:
+                if j < 0:
+                    b = -1 - j
+                    at = it["hi"][b >> 1] if b & 1 else it["lo"][b >> 1]
+                    assert np.all(np.abs(v[lp, b >> 1] - at) <= 1e-12)
+        row += no
+
+
+def test_structure_capacity_protocol(vt, torch_cuda):
+    w = wl.uniform4096()
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi),
+                                want_faces=True)
+    T = torch_cuda
+    voff = T.empty(w.n + 1, dtype=T.int64, device="cuda")
+    foff = T.empty(w.n + 1, dtype=T.int64, device="cuda")
+    sizes = (ctypes.c_int64 * 3)()
+    s = vt._stream()
+    code = vt.lib().vt_structure(ctx._ctx, vt._ptr(voff), None, 0, vt._ptr(foff), None, 0, None, None, 0, sizes, s)
+    assert code == vt.VT_ERR_CAPACITY
+    nv, nf, nl = sizes[0], sizes[1], sizes[2]
+    assert voff[-1].item() == nv and foff[-1].item() == nf and nl == 2 * (nv + nf - 2 * w.n)  # Euler, all closed
+    verts = T.empty((nv, 3), dtype=T.float64, device="cuda")
+    fnbr = T.empty(nf, dtype=T.int32, device="cuda")
+    loff = T.empty(nf + 1, dtype=T.int64, device="cuda")
+    lv = T.empty(nl, dtype=T.int32, device="cuda")
+    code = vt.lib().vt_structure(ctx._ctx, vt._ptr(voff), vt._ptr(verts), nv, vt._ptr(foff), vt._ptr(fnbr), nf - 1,
+                                 vt._ptr(loff), vt._ptr(lv), nl, sizes, s)
+    assert code == vt.VT_ERR_CAPACITY      # one face short
+    code = vt.lib().vt_structure(ctx._ctx, vt._ptr(voff), vt._ptr(verts), nv, vt._ptr(foff), vt._ptr(fnbr), nf,
+                                 vt._ptr(loff), vt._ptr(lv), nl, sizes, s)
+    assert code == vt.VT_OK and loff[-1].item() == nl
+    # a build without facet lists cannot give the structure
+    bare = vt.Context().vt_build(torch_cuda.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi))
+    with pytest.raises(vt.VTError):
+        bare.vt_structure()
+
+
+def test_structure_vtu_file(vt, torch_cuda, tmp_path):
+    from paper_1601_06429_amd import vtk
+
+    w = wl.uniform4096()
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi),
+                                want_faces=True)
+    cells = ctx.vt_cells()
+    st = ctx.vt_structure()
+    path = str(tmp_path / "uniform.vtu")
+    vtk.write_vtu(path, st, cell_data={"volume": cells.volume})
+    r = vtk.read_vtu(path)
+    assert r["Points"].shape == (st.verts.shape[0], 3) and len(r["types"]) == w.n
+    np.testing.assert_array_equal(r["volume"], cells.volume.cpu().numpy())
+    fs, fo = r["faces"], r["faceoffsets"]
+    starts = np.concatenate([[0], fo[:-1]])
+    assert np.array_equal(fs[starts], np.diff(st.face_off.cpu().numpy()))

@@ -563,3 +563,96 @@ def test_grid_sample_converges_to_exact_overlaps(oracle):
     errs = [np.abs(oracle.grid_sample(p, 0.0, 1.0, val, (4, 4, 4), sub=s)[0] - exact).mean() for s in (1, 4, 16)]
     assert errs[2] < errs[1] < errs[0]
     assert errs[2] < 0.05 * errs[0]
+
+
+# ---------------------------------------------------------------- full structure
+def _loop_normal(v, loop):
+    """Newell's vector of a polygon (twice its vector area)."""
+    P = v[loop]
+    Q = np.roll(P, -1, axis=0)
+    return np.cross(P, Q).sum(0)
+
+
+def test_structure_sc_lattice_cubes(oracle):
+    p = wl.lattice("sc", 4)
+    a = 0.25
+    for i in (0, 5, 63):
+        v, faces = oracle.structure(p, 0.0, 1.0, i)
+        corners = p[i] + a / 2 * np.array(list(itertools.product([-1, 1], repeat=3)))
+        assert len(v) == 8 and len(faces) == 6
+        assert sorted(map(tuple, np.round(v, 12))) == sorted(map(tuple, np.round(corners, 12)))
+        for j, loop in faces:
+            assert len(loop) == 4
+            D = p[j] - p[i]
+            D -= np.rint(D)
+            assert np.isclose(np.linalg.norm(D), a)
+            # the face lies on the bisector, and its loop turns counter-clockwise seen from outside
+            np.testing.assert_allclose((v[loop] - p[i]) @ D, a * a / 2, atol=1e-15)
+            nrm = _loop_normal(v - p[i], loop)
+            assert np.isclose(nrm @ D / a, 2 * a * a)
+
+
+def test_structure_bcc_truncated_octahedron(oracle):
+    p = wl.lattice("bcc", 4)
+    v, faces = oracle.structure(p, 0.0, 1.0, 17)
+    sizes = sorted(len(lp) for _, lp in faces)
+    assert len(v) == 24 and sizes == [4] * 6 + [6] * 8
+    E = sum(sizes) // 2
+    assert len(v) - E + len(faces) == 2
+
+
+@pytest.fixture(scope="module")
+def random_structures(oracle):
+    rng = np.random.default_rng(2024)
+    p = rng.random((400, 3))
+    q = [0, 17, 123, 399]
+    return p, q, [oracle.structure(p, 0.0, 1.0, i) for i in q], oracle.cells(p, 0.0, 1.0, query=q)
+
+
+def test_structure_vertices_are_voronoi_vertices(random_structures):
+    # empty sphere: no particle (any periodic image) is closer to a vertex than the seed, and
+    # the particles of the vertex's faces are exactly as close
+    p, q, st, _ = random_structures
+    for i, (v, faces) in zip(q, st):
+        d = v[:, None, :] - p[None, :, :]
+        d -= np.rint(d)
+        dist = np.sqrt((d * d).sum(-1))
+        r = dist[:, i]
+        assert np.all(dist >= r[:, None] * (1 - 1e-12))
+        for j, loop in faces:
+            np.testing.assert_allclose(dist[loop, j], r[loop], rtol=1e-12)
+
+
+def test_structure_topology_orientation_and_volume(random_structures):
+    p, q, st, cells = random_structures
+    for k, (i, (v, faces)) in enumerate(zip(q, st)):
+        ids = [j for j, _ in faces]
+        assert ids == list(cells.neighbours(k))
+        inc = np.zeros(len(v), int)
+        edges = set()
+        vol = 0.0
+        for j, loop in faces:
+            inc[loop] += 1
+            edges.update(tuple(sorted(e)) for e in zip(loop, np.roll(loop, -1)))
+            D = p[j] - p[i]
+            D -= np.rint(D)
+            assert _loop_normal(v - p[i], loop) @ D > 0          # counter-clockwise from outside
+            # divergence theorem with F = x / 3 about the seed
+            vol += _loop_normal(v - p[i], loop) @ (v[loop[0]] - p[i]) / 6
+        assert np.all(inc >= 3)
+        assert len(v) - len(edges) + len(faces) == 2
+        assert abs(vol - cells.volume[k]) <= 1e-13 * cells.volume[k]
+
+
+def test_structure_bounded_walls(oracle):
+    rng = np.random.default_rng(8)
+    p = rng.random((200, 3))
+    corner = int(np.argmin(p.sum(1)))
+    v, faces = oracle.structure(p, 0.0, 1.0, corner, periodic=False)
+    walls = [(j, lp) for j, lp in faces if j < 0]
+    assert walls and all(-6 <= j <= -1 for j, _ in walls)
+    assert [j for j, _ in faces] == sorted(j for j, _ in faces)
+    for j, lp in walls:
+        b = -1 - j
+        axis, at = b >> 1, float(b & 1)
+        np.testing.assert_allclose(v[lp, axis], at, atol=1e-15)
