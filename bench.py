@@ -378,6 +378,24 @@ def main():
                                    "mean_abs_diff_vs_exact_over_mean": float((gs - grid).abs().mean() / grid.mean())}
         out["grid_sample"] = dict(samp, grid=list(grid_dims), exact_deposit_ms=stage_ms[4])
 
+        # grid tensors of the deposit (tidal tensor; the Hessian takes the same passes)
+        tt = ctx.vt_grid_tensor(grid, vt.TENSOR_TIDAL)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            ctx.vt_grid_tensor(grid, vt.TENSOR_TIDAL, out=tt)
+        e1.record()
+        e1.synchronize()
+        ms_t = e0.elapsed_time(e1) / 3
+        npts = float(np.prod(grid_dims))
+        # HBM bytes per grid point: real->complex 24, forward FFT 3 x 32, per component pair the
+        # multiply 32, the inverse FFT 3 x 32 and the unpack 32
+        tbytes = npts * (24 + 3 * 32 + 3 * (32 + 3 * 32 + 32))
+        out["grid_tensor"] = {"ms": ms_t, "grid": list(grid_dims), "points_per_s": npts / (ms_t * 1e-3),
+                              "algorithmic_GB_per_s": tbytes / (ms_t * 1e-3) / 1e9}
+        del tt
+
         # the full structure output (vertices and faces as loops): one library call with the
         # output arrays in place (count pass, scans, totals read back, write pass)
         st = ctx.vt_structure()

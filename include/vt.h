@@ -186,6 +186,32 @@ vt_status vt_grid_deposit(vt_ctx *ctx, const double *value, int32_t nx, int32_t 
 vt_status vt_grid_sample(vt_ctx *ctx, const double *value, int32_t nx, int32_t ny, int32_t nz, int32_t sub,
                          double *grid, int32_t *nearest_id, void *stream);
 
+/* kinds of grid tensor (vt_grid_tensor) */
+#define VT_TENSOR_TIDAL 0     /* d_i d_j phi, laplacian(phi) = f / mean(f) - 1 */
+#define VT_TENSOR_HESSIAN 1   /* d_i d_j f */
+
+/*
+ * vt_grid_tensor -- second-derivative tensor of a grid field, for the tidal-
+ * tensor and Hessian analysis the paper lists among future grid outputs
+ * (section 4).  Spectral on the periodic grid of item 0's box, k_a = 2 pi m / L_a
+ * with m the signed frequency index:
+ *   VT_TENSOR_TIDAL    T_ij = d_i d_j phi with laplacian(phi) = delta,
+ *                      delta = f / mean(f) - 1, i.e. T_ij(k) = k_i k_j / |k|^2
+ *                      f(k) / mean(f) (0 at k = 0); trace T = delta.
+ *   VT_TENSOR_HESSIAN  H_ij = d_i d_j f, H_ij(k) = -k_i k_j f(k).
+ * A mixed component is zero on the Nyquist plane of either of its axes.
+ *   grid   device, nx*ny*nz doubles laid out like vt_grid_deposit's (e.g. its
+ *          output); for VT_TENSOR_TIDAL its mean must not be zero.
+ *   out    device, 6 x nx*ny*nz doubles: components xx, yy, zz, xy, xz, yz,
+ *          each laid out like grid; overwritten.
+ * nx, ny, nz are powers of two from 2 to 4096.  Periodic single-item contexts
+ * only.  Scratch: 32 bytes per grid point, kept by the context.
+ * Errors: VT_ERR_STATE, VT_ERR_ARG (sizes, kind, context), VT_ERR_OOM,
+ * VT_ERR_HIP.
+ */
+vt_status vt_grid_tensor(vt_ctx *ctx, const double *grid, int32_t nx, int32_t ny, int32_t nz, int32_t kind,
+                         double *out, void *stream);
+
 /*
  * vt_structure -- the full tessellation structure of the owned cells (the
  * paper's optional full structure output: section 3, memory consumption;

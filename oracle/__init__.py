@@ -177,6 +177,36 @@ def structure(pos, box_lo, box_hi, i, periodic=True, gid=None, tol=1e-12, area_e
     return verts[:k].copy(), faces
 
 
+def grid_tensor(field, box_len, kind="tidal"):
+    """Second-derivative tensors of a periodic grid field (section 4 lists tidal-tensor and
+    Hessian grid outputs among future work), by the discrete Fourier transform (numpy.fft):
+    tidal T_ij = d_i d_j phi with laplacian(phi) = f / mean(f) - 1, Hessian H_ij = d_i d_j f,
+    with k_a = 2 pi m / L_a for the signed frequency index m.  A mixed component is zero on the
+    Nyquist plane of either of its axes.  Returns 6 x field.shape: xx, yy, zz, xy, xz, yz."""
+    f = np.asarray(field, np.float64)
+    L = np.broadcast_to(np.asarray(box_len, np.float64), 3)
+    F = np.fft.fftn(f)
+    ks, nyq = [], []
+    for a, n in enumerate(f.shape):
+        shape = [1, 1, 1]
+        shape[a] = n
+        m = np.rint(np.fft.fftfreq(n) * n)
+        ks.append((2.0 * np.pi * m / L[a]).reshape(shape))
+        nyq.append((np.arange(n) * 2 == n).reshape(shape))
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    out = []
+    for i, j in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
+        kk = ks[i] * ks[j]
+        if kind == "tidal":
+            M = np.where(k2 > 0, kk / np.where(k2 > 0, k2, 1.0), 0.0) / f.mean()
+        else:
+            M = -kk * np.ones_like(k2)
+        if i != j:
+            M = np.where(nyq[i] | nyq[j], 0.0, M)
+        out.append(np.fft.ifftn(M * F).real)
+    return np.stack(out)
+
+
 def density(mass, volume):
     """rho_i = m_i / V_i (section 2)."""
     return np.asarray(mass, np.float64) / np.asarray(volume, np.float64)

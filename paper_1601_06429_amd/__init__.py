@@ -33,6 +33,8 @@ STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out 
                 7: "invalid call order", 8: "inconsistent clipping topology"}
 VT_F32, VT_F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+TENSOR_TIDAL, TENSOR_HESSIAN = 0, 1
+TENSOR_COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
 CELL_INCOMPLETE, CELL_RETRIED, CELL_FAILED = 1, 2, 4
 
 
@@ -92,13 +94,14 @@ def lib():
                                             ctypes.POINTER(I32), I32, P, P, I64, ctypes.POINTER(vt_item),
                                             ctypes.POINTER(I64), P]
             L.vt_structure.argtypes = [P, P, P, I64, P, P, I64, P, P, I64, ctypes.POINTER(I64), P]
+            L.vt_grid_tensor.argtypes = [P, P, I32, I32, I32, I32, P, P]
             L.vt_destroy.argtypes = [P]
             L.vt_destroy.restype = None
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
                       "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack",
-                      "vt_grid_sample", "vt_structure"):
+                      "vt_grid_sample", "vt_structure", "vt_grid_tensor"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -367,6 +370,20 @@ class Context:
         _check(lib().vt_grid_sample(self._ctx, _ptr(value), nx, ny, nz, int(sub), _ptr(g), _ptr(nid),
                                     _stream(stream)), "vt_grid_sample")
         return (g, nid) if nearest else g
+
+    def vt_grid_tensor(self, grid, kind=TENSOR_TIDAL, out=None, stream=None):
+        """Tidal tensor (kind TENSOR_TIDAL) or Hessian (TENSOR_HESSIAN) of a grid field on the
+        context's periodic box: a 6 x nx x ny x nz tensor, components TENSOR_COMPONENTS."""
+        import torch
+
+        _require_cuda(grid, "grid")
+        if grid.dim() != 3 or grid.dtype != torch.float64:
+            raise ValueError("grid must be an nx x ny x nz float64 tensor")
+        nx, ny, nz = grid.shape
+        o = out if out is not None else torch.empty((6, nx, ny, nz), dtype=torch.float64, device=self.device)
+        _check(lib().vt_grid_tensor(self._ctx, _ptr(grid), nx, ny, nz, int(kind), _ptr(o), _stream(stream)),
+               "vt_grid_tensor")
+        return o
 
     def vt_backward(self, dL_dV, out=None, stream=None):
         import torch

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvt.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["sort.hip", "clip.hip", "post.hip", "grid.hip", "decomp.hip", "structure.hip", "vt_api.cpp"]
+SOURCES = ["sort.hip", "clip.hip", "post.hip", "grid.hip", "decomp.hip", "structure.hip", "spectral.hip", "vt_api.cpp"]
 HEADERS = ["vt_internal.h", "poly.h", "rebuild.h"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

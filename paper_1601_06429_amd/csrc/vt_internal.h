@@ -123,6 +123,9 @@ struct vt_ctx {
     uint8_t *smark = nullptr;
     int32_t *squeue = nullptr;
     int64_t cap_struct = 0;
+    // grid tensors (spectral.hip): two complex work arrays of the grid's size
+    void *spec_buf = nullptr;
+    int64_t cap_spec = 0;
     // optional stage timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
@@ -150,6 +153,8 @@ hipError_t vt_launch_structure(vt_ctx *c, int64_t *vert_off, double *verts, int6
                                int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert,
                                int64_t loop_cap, int64_t sizes[3], bool *fits);
 void vt_struct_free(vt_ctx *c);
+hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind, double *out);
+void vt_spec_free(vt_ctx *c);
 
 // ---------------------------------------------------------------- device helpers
 #ifdef __HIP_DEVICE_COMPILE__

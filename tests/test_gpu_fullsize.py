@@ -10,6 +10,8 @@
   1e-12;
 * clustered 2M sampled at 256^3 (nearest-particle grid variant): the nearest ids of 200k
   random voxel centres against scipy's periodic k-d tree;
+* clustered 2M deposit at 256^3: its tidal tensor against the oracle's discrete-Fourier
+  reference, its trace against the density contrast;
 * clustered 2M full structure: every cell's face ids against its neighbour list, its volume
   by the divergence theorem over its face loops, Euler's formula; 32 sampled cells (the eight
   largest among them) against the oracle's structure;
@@ -170,6 +172,26 @@ def test_clustered2m_structure(vt, torch_cuda, oracle):
             k = int(np.argmin(((A - B[0]) ** 2).sum(1)))
             assert len(lg) == len(lo_) and np.max(np.abs(np.roll(A, -k, axis=0) - B)) <= 1e-10, r
     del ctx, st, cells
+    T.cuda.empty_cache()
+
+
+def test_clustered2m_tidal_tensor_of_the_deposit(vt, torch_cuda, oracle):
+    """The benchmark's 256^3 deposit of the clustered set: its tidal tensor against the oracle's
+    discrete-Fourier reference, and its trace against the density contrast."""
+    T = torch_cuda
+    w = wl.clustered2m()
+    ctx = vt.Context().vt_build(T.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi), want_faces=True)
+    rho = ctx.vt_density(T.from_numpy(w.mass).cuda())
+    g = ctx.vt_grid_deposit(rho, (256, 256, 256))
+    tt = ctx.vt_grid_tensor(g, vt.TENSOR_TIDAL)
+    assert ctx.vt_query()[0] == 0
+    gn = g.cpu().numpy()
+    d = gn / gn.mean() - 1
+    tr = (tt[0] + tt[1] + tt[2]).cpu().numpy()
+    assert np.max(np.abs(tr - d)) <= 1e-12 * np.abs(d).max()
+    ref = oracle.grid_tensor(gn, w.box_len, "tidal")
+    assert np.max(np.abs(tt.cpu().numpy() - ref)) <= 1e-12 * np.abs(ref).max()
+    del ctx, tt, g, ref
     T.cuda.empty_cache()
 
 

@@ -656,3 +656,57 @@ def test_structure_bounded_walls(oracle):
         b = -1 - j
         axis, at = b >> 1, float(b & 1)
         np.testing.assert_allclose(v[lp, axis], at, atol=1e-15)
+
+
+# ---------------------------------------------------------------- grid tensors
+def _mode_grid(shape, L, m, amp, mean, phase):
+    x = [np.arange(n) * (L[a] / n) for a, n in enumerate(shape)]
+    X = np.meshgrid(*x, indexing="ij")
+    k = [2 * np.pi * m[a] / L[a] for a in range(3)]
+    arg = k[0] * X[0] + k[1] * X[1] + k[2] * X[2] + phase
+    return mean + amp * np.cos(arg), k, arg
+
+
+PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+
+
+def test_grid_tensor_single_mode_closed_forms(oracle):
+    # f = mean + A cos(k.x + p): T_ij = k_i k_j / |k|^2 (A / mean) cos(.), H_ij = -k_i k_j A cos(.)
+    shape, L = (16, 8, 32), (1.0, 1.0, 1.0)
+    f, k, arg = _mode_grid(shape, L, (3, -2, 5), 0.5, 2.0, 0.7)
+    T = oracle.grid_tensor(f, L, "tidal")
+    H = oracle.grid_tensor(f, L, "hessian")
+    k2 = sum(x * x for x in k)
+    for c, (i, j) in enumerate(PAIRS):
+        np.testing.assert_allclose(T[c], k[i] * k[j] / k2 * 0.25 * np.cos(arg), atol=1e-13)
+        np.testing.assert_allclose(H[c], -k[i] * k[j] * 0.5 * np.cos(arg), atol=1e-10)
+
+
+def test_grid_tensor_constant_field_and_trace(oracle):
+    shape, L = (8, 16, 8), 2.0
+    assert np.abs(oracle.grid_tensor(np.full(shape, 3.0), L, "tidal")).max() == 0.0
+    assert np.abs(oracle.grid_tensor(np.full(shape, 3.0), L, "hessian")).max() == 0.0
+    # trace T = delta for a field with no Nyquist content
+    rng = np.random.default_rng(41)
+    F = np.fft.fftn(rng.standard_normal(shape))
+    for a, n in enumerate(shape):
+        sl = [slice(None)] * 3
+        sl[a] = n // 2
+        F[tuple(sl)] = 0.0
+    f = 3.0 + np.fft.ifftn(F).real
+    T = oracle.grid_tensor(f, L, "tidal")
+    np.testing.assert_allclose(T[0] + T[1] + T[2], f / f.mean() - 1.0, atol=1e-13)
+    # and the Hessian's trace is the Laplacian: the second difference limit, checked on a mode
+    g, k, arg = _mode_grid(shape, (L, L, L), (1, 2, 3), 1.0, 0.0, 0.3)
+    H = oracle.grid_tensor(g, L, "hessian")
+    np.testing.assert_allclose(H[0] + H[1] + H[2], -sum(x * x for x in k) * np.cos(arg), atol=1e-10)
+
+
+def test_grid_tensor_nyquist_convention(oracle):
+    # a mode on the x Nyquist plane: mixed components with x vanish, the xx component does not
+    shape, L = (8, 8, 8), (1.0, 1.0, 1.0)
+    f, k, arg = _mode_grid(shape, L, (4, 1, 0), 1.0, 0.0, 0.0)
+    H = oracle.grid_tensor(f, L, "hessian")
+    assert np.abs(H[3]).max() <= 1e-10 and np.abs(H[4]).max() <= 1e-10   # rounding only (|H_xx| ~ 600)
+    np.testing.assert_allclose(H[0], -k[0] ** 2 * np.cos(arg), atol=1e-10)
+    np.testing.assert_allclose(H[1], -k[1] ** 2 * np.cos(arg), atol=1e-10)
