@@ -225,11 +225,13 @@ vt_status vt_grid_tensor(vt_ctx *ctx, const double *grid, int32_t nx, int32_t ny
  *   face_off   device, n_owned_total + 1 int64: cell i's faces.
  *   face_nbr   device, face_cap int32: the global id across each face, or
  *              -1 .. -6 for the walls -x, +x, -y, +y, -z, +z of a bounded
- *              item.  A cell's faces ascend by it.  Faces of area <=
- *              area_eps V^(2/3) are left out, so the nonnegative entries of a
- *              row are its neighbour list (vt_cells); a cell that loses such a
- *              face keeps a hole of at most that area (its loops then hold
- *              fewer than three entries per vertex).
+ *              item.  A cell's faces ascend by it.  A particle's face is
+ *              listed if the particle is in the cell's neighbour list (faces
+ *              of area > area_eps V^(2/3); vt_cells), so the nonnegative
+ *              entries of a row are exactly that list; a wall if its area
+ *              exceeds the same bound.  A cell that loses a face this way
+ *              keeps a hole of at most that area (its loops then hold fewer
+ *              than three entries per vertex).
  *   loop_off   device, face_cap + 1 int64: face f's loop is
  *              loop_vert[loop_off[f] .. loop_off[f+1]-1].
  *   loop_vert  device, loop_cap int32: vertex indices local to the cell

@@ -4,12 +4,15 @@
 //   vertices  vert_off[row] .. vert_off[row + 1], absolute coordinates (seed + offset);
 //   faces     face_off[row] .. face_off[row + 1], ascending by the id across the face: the
 //             neighbour's global id, or -1 .. -6 for the walls -x, +x, -y, +y, -z, +z of a
-//             bounded item; only faces of positive area (area > area_eps V^(2/3)), the facets
-//             of the neighbour lists, plus surviving walls;
+//             bounded item; a particle's face is kept if the particle is in the cell's facet
+//             list (the faces of area > area_eps V^(2/3), the neighbour list), a wall if its
+//             area is above that threshold;
 //   loops     loop_off[f] .. loop_off[f + 1], vertex indices local to the cell, counter-clockwise
 //             seen from outside, starting at the face's smallest index.
 // Two passes over the cells: the first counts (vertices, faces, loop entries) per row, the host
-// scans the counts, and the second writes.  Each pass is one wavefront per cell: the cell is
+// scans the counts, and the second writes, after checking that it finds the counted sizes.  A
+// cell of a periodic box with a topology record whose faces are all facets is counted from the
+// record alone (its vertices, its faces, three loop entries per vertex).  Each pass is one wavefront per cell: the cell is
 // rebuilt from its topology record (or its facets), its face loops are walked lane-parallel, one
 // face per lane, and sorted by neighbour id with a wave bitonic sort.  Cells with more than 64
 // vertices go to a large kernel with four vertex slots per lane.
@@ -22,6 +25,7 @@ struct StructMem {
     int32_t vidx[64 * VPL];  // local vertex index: rank among the cell's vertices
     int32_t flen[64 * VPL];  // loop length of each kept face slot, 0 otherwise
     int32_t frev[64 * VPL];  // 1: the walk runs clockwise seen from outside and is written reversed
+    int32_t fl[64 * VPL];    // the cell's facet list (sorted indices of its neighbours)
     PolyMem<double, VPL> P;
 };
 
@@ -106,6 +110,17 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
             continue;
         }
         const DevItem &it = A.items[item_of(A.items, A.n_items, j0)];
+        if (!RETRY && !A.write && it.periodic) {
+            const int nf = A.src.cnf[c], nv = A.src.cnv[c];
+            if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64 && A.src.ccnt[c] == nf) {
+                if (lane == 0) {
+                    A.nvert[row] = nv;
+                    A.nface[row] = nf;
+                    A.nloop[row] = 3 * nv;
+                }
+                continue;
+            }
+        }
         double xs[3];
         gpos<PT4>(A.src.spos, j0, xs[0], xs[1], xs[2]);
         double blo[3], bhi[3];
@@ -121,11 +136,17 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
         Poly<double, VPL> P;
         const int rb = rebuild_cell<PT4, VPL, RETRY>(A.src, it, S.P, P, c, xs[0], xs[1], xs[2], blo, bhi);
         if (rb == REBUILD_OVERFLOW) {
-            if (!A.write && lane == 0) {
-                A.smark[c] = 1;
-                const uint32_t qi = atomicAdd(&A.counters[CTR_STRUCT_Q], 1u);
-                if ((int64_t)qi < A.squeue_cap) A.squeue[qi] = c;
-                else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+            if (lane == 0) {
+                if (!A.write) {
+                    A.smark[c] = 1;
+                    const uint32_t qi = atomicAdd(&A.counters[CTR_STRUCT_Q], 1u);
+                    if ((int64_t)qi < A.squeue_cap) A.squeue[qi] = c;
+                    else atomicOr(&A.counters[CTR_STATUS], VT_DEV_CAPACITY);
+                } else {
+                    // counted from its record, but rebuilt from its facets here: no room was
+                    // counted for what this pass would write
+                    atomicOr(&A.counters[CTR_STATUS], VT_DEV_TOPOLOGY);
+                }
             }
             continue;
         }
@@ -146,9 +167,14 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
             nv += __popcll(am);
         }
         wave_sync();
+        // ---- the cell's facet list in LDS
+        const int32_t fcnt = min(A.src.ccnt[c], 64 * VPL);
+        const int64_t frow = A.src.crow[c];
+        for (int t = lane; t < fcnt; t += 64) S.fl[t] = A.src.stage_ids[frow + t];
+        wave_sync();
         // ---- faces: walk each loop once (one face slot per lane) for its length, area and
-        // orientation; a face is kept if its area is above the facet threshold
-        // the facet threshold as the clip kernel takes it
+        // orientation; a particle's face is kept if the particle is in the facet list, a wall
+        // if its area is above the facet threshold (as the clip kernel takes it)
         const double amin = (double)(A.area_eps * exp2f(log2f((float)fabs(A.cvol[c])) * (2.0f / 3.0f)));
         uint64_t key[VPL];
         bool open_loop = false;
@@ -186,10 +212,16 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
                 // clockwise seen from outside
                 const P4<double> &pl = S.P.pl64[f];
                 const double sa = 0.5 * (nx * pl.x + ny * pl.y + nz * pl.z) / sqrt(pl.x * pl.x + pl.y * pl.y + pl.z * pl.z);
-                if (m >= 3 && fabs(sa) > amin) {
+                const int32_t tag = S.P.ptag[f];
+                bool keep = false;
+                if (tag >= 0) {
+                    for (int t = 0; t < fcnt; ++t) keep = keep || S.fl[t] == tag;
+                } else {
+                    keep = fabs(sa) > amin;
+                }
+                if (m >= 3 && keep) {
                     rev = sa < 0.0 ? 1 : 0;
                     keep_len = m;
-                    const int32_t tag = S.P.ptag[f];
                     const int64_t g = tag >= 0 ? (int64_t)A.sgid[tag] : (int64_t)tag;
                     key[r] = ((uint64_t)(g + 16) << 32) | (uint64_t)f;
                 }
@@ -223,8 +255,12 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
             }
             continue;
         }
-        // ---- write pass: vertices, then faces and their loops
+        // ---- write pass: only into the room the count pass made for this row
         const int64_t vb = A.vert_off[row], fb = A.face_off[row], lb = A.loop_base[row];
+        if (A.vert_off[row + 1] - vb != nv || A.face_off[row + 1] - fb != nkept || A.loop_base[row + 1] - lb != nloop) {
+            if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_TOPOLOGY);
+            continue;
+        }
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             const int u = s * 64 + lane;
