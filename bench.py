@@ -398,13 +398,13 @@ def main():
 
         # the full structure output (vertices and faces as loops): one library call with the
         # output arrays in place (count pass, scans, totals read back, write pass)
-        st = ctx.vt_structure()
+        so = ctx.vt_structure()
         sizes = (ctypes.c_int64 * 3)()
-        nv_, nf_, nl_ = st.verts.shape[0], st.face_nbr.numel(), st.loop_vert.numel()
+        nv_, nf_, nl_ = so.verts.shape[0], so.face_nbr.numel(), so.loop_vert.numel()
 
         def structure_call():
-            rc = vt.lib().vt_structure(ctx._ctx, vt._ptr(st.vert_off), vt._ptr(st.verts), nv_, vt._ptr(st.face_off),
-                                       vt._ptr(st.face_nbr), nf_, vt._ptr(st.loop_off), vt._ptr(st.loop_vert), nl_,
+            rc = vt.lib().vt_structure(ctx._ctx, vt._ptr(so.vert_off), vt._ptr(so.verts), nv_, vt._ptr(so.face_off),
+                                       vt._ptr(so.face_nbr), nf_, vt._ptr(so.loop_off), vt._ptr(so.loop_vert), nl_,
                                        sizes, vt._stream())
             assert rc == vt.VT_OK, rc
 
@@ -421,7 +421,7 @@ def main():
         out["structure"] = {"ms": ms_st, "cells_per_s": N / (ms_st * 1e-3), "bytes_per_particle": nbytes / N,
                             "written_GB_per_s": nbytes / (ms_st * 1e-3) / 1e9,
                             "vertices_per_cell": nv_ / N, "faces_per_cell": nf_ / N}
-        del st
+        del so
 
     if not args.no_variants:
         # forward-only comparison of the two precisions at the same accuracy bar
