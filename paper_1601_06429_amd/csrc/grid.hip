@@ -27,6 +27,7 @@ template <int VPL>
 struct GridMem {
     static constexpr int FMAX = 64 * VPL;      // face slots
     static constexpr int LOOP = 3 * 64 * VPL;  // vertex-face incidences (3 per vertex)
+    static constexpr int ACC = 256 * VPL;      // voxels of a cell's box summed in LDS
     double vp[64 * VPL][3];  // vertex positions, grid frame (box origin at 0)
     uint32_t vt[64 * VPL];   // vertex triples
     double lp[LOOP][3];      // face vertex loops (seed-relative x, y, z), counter-clockwise in (y, z)
@@ -37,6 +38,7 @@ struct GridMem {
     int32_t ipre[FMAX + 1];  // prefix of work items per face
     int32_t fid[FMAX];       // compacted face slots
     uint64_t iq[128];        // work items queued for integration (face, plane, rectangle offsets)
+    double acc[ACC];         // the cell's contributions per voxel of its box
     PolyMem<double, VPL> P;
 };
 
@@ -390,6 +392,11 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
                 continue;
             }
+            // the cell's voxel box: contributions are summed in LDS when it fits, and each voxel
+            // then takes one global atomic
+            const int64_t bx = i1[0] - i0[0] + 1, by = i1[1] - i0[1] + 1, bz = i1[2] - i0[2] + 1;
+            const int nacc = bx * by * bz <= M::ACC ? (int)(bx * by * bz) : 0;
+            for (int t = lane; t < nacc; t += 64) S.acc[t] = 0.0;
             // ---- faces: compact the alive ones
             int nf = 0;
 #pragma unroll
@@ -528,6 +535,11 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
             // ---- work items
             auto emit = [&](int64_t i, int64_t j, int64_t k, double v) {
                 if (v == 0.0) return;
+                const int64_t li = i - i0[0], lj = j - i0[1], lk = k - i0[2];
+                if (nacc > 0 && li >= 0 && li < bx && lj >= 0 && lj < by && lk >= 0 && lk < bz) {
+                    unsafeAtomicAdd(&S.acc[(li * by + lj) * bz + lk], v);
+                    return;
+                }
                 int64_t g = (wrap1(i, dims[0]) * dims[1] + wrap1(j, dims[1])) * dims[2] + wrap1(k, dims[2]);
                 unsafeAtomicAdd(&A.grid[g], v * vscale);
             };
@@ -616,6 +628,15 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
             }
             wave_sync();
+            for (int t = lane; t < nacc; t += 64) {
+                const double v = S.acc[t];
+                if (v != 0.0) {
+                    const int64_t lk = t % bz, lj = (t / bz) % by, li = t / (by * bz);
+                    const int64_t g = (wrap1(i0[0] + li, dims[0]) * dims[1] + wrap1(i0[1] + lj, dims[1])) * dims[2] +
+                                      wrap1(i0[2] + lk, dims[2]);
+                    unsafeAtomicAdd(&A.grid[g], v * vscale);
+                }
+            }
         }
     }
 }
