@@ -228,6 +228,7 @@ class Context:
         self._keep = []
         self.n_owned = 0
         self.n_total = 0
+        self._pack_cap = 0     # largest batch vt_decompose_pack has written for this context
 
     def __del__(self):
         try:
@@ -429,13 +430,25 @@ class Context:
         tptr = None if tl is None else tl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         args = (ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, ntc, _dptr(th), _ptr(own_mask), tptr,
                 n_list)
-        code = lib().vt_decompose_pack(*args, None, None, 0, arr, ctypes.byref(n_out), _stream(stream))
-        if code not in (VT_OK, VT_ERR_CAPACITY):
-            _check(code, "vt_decompose_pack")
-        out = torch.empty((max(n_out.value, 1), 3), dtype=torch.float64, device=pos.device)
-        gid = torch.empty(max(n_out.value, 1), dtype=torch.int32, device=pos.device)
-        _check(lib().vt_decompose_pack(*args, _ptr(out), _ptr(gid), out.shape[0], arr, ctypes.byref(n_out),
-                                       _stream(stream)), "vt_decompose_pack")
+        # outputs sized by the largest batch this context has packed; a larger one is sized by
+        # the call that finds it too small, then packed again
+        cap = self._pack_cap
+        out = gid = None
+        code = VT_ERR_CAPACITY
+        if cap > 0:
+            out = torch.empty((cap, 3), dtype=torch.float64, device=pos.device)
+            gid = torch.empty(cap, dtype=torch.int32, device=pos.device)
+            code = lib().vt_decompose_pack(*args, _ptr(out), _ptr(gid), cap, arr, ctypes.byref(n_out),
+                                           _stream(stream))
+        else:
+            code = lib().vt_decompose_pack(*args, None, None, 0, arr, ctypes.byref(n_out), _stream(stream))
+        if code == VT_ERR_CAPACITY:
+            self._pack_cap = max(cap, n_out.value, 1)
+            out = torch.empty((self._pack_cap, 3), dtype=torch.float64, device=pos.device)
+            gid = torch.empty(self._pack_cap, dtype=torch.int32, device=pos.device)
+            code = lib().vt_decompose_pack(*args, _ptr(out), _ptr(gid), self._pack_cap, arr, ctypes.byref(n_out),
+                                           _stream(stream))
+        _check(code, "vt_decompose_pack")
         items = [dict(offset=arr[k].offset, n_owned=arr[k].n_owned, n_ghost=arr[k].n_ghost, periodic=False,
                       lo=np.array(arr[k].lo[:]), hi=np.array(arr[k].hi[:])) for k in range(n_list)]
         return out[:n_out.value], gid[:n_out.value], items

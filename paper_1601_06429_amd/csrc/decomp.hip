@@ -136,35 +136,80 @@ __device__ __forceinline__ void dec_members(const T *pos, int64_t p, const DecGe
                         }
 }
 
+// The per-task counters are few and every particle adds to one or more of them, so a global atomic
+// per membership serializes on a few addresses across the whole chip.  Each block therefore counts
+// in LDS (nc = 2 per listed task: owned, buffer) and adds its totals once; the scatter reserves one
+// range per block and counter, then places its particles within it with LDS atomics.
+#define DEC_TPB 256
+#define DEC_LDS_COUNTERS 4096   // above this, the kernels count with global atomics directly
+
 template <typename T>
-__global__ void k_dec_count(const T *pos, int64_t n, DecGeo g, const double *thick, double T0, double T1,
-                            double T2, const uint8_t *own_mask, const int32_t *tpos, unsigned long long *cnt) {
+__global__ void __launch_bounds__(DEC_TPB) k_dec_count(const T *pos, int64_t n, DecGeo g, const double *thick,
+                                                       double T0, double T1, double T2, const uint8_t *own_mask,
+                                                       const int32_t *tpos, int nc, unsigned long long *cnt) {
+    extern __shared__ uint32_t lc[];
+    const bool lds = nc <= DEC_LDS_COUNTERS;
+    if (lds) {
+        for (int i = threadIdx.x; i < nc; i += DEC_TPB) lc[i] = 0;
+        __syncthreads();
+    }
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
     const double Tm[3] = {T0, T1, T2};
-    dec_members(pos, p, g, thick, Tm, own_mask, tpos, [&](int b, const int *, bool ghost) {
-        const int l = tpos ? tpos[b] : b;
-        atomicAdd(&cnt[2 * (int64_t)l + (ghost ? 1 : 0)], 1ull);
-    });
+    if (p < n)
+        dec_members(pos, p, g, thick, Tm, own_mask, tpos, [&](int b, const int *, bool ghost) {
+            const int k = 2 * (tpos ? tpos[b] : b) + (ghost ? 1 : 0);
+            if (lds) atomicAdd(&lc[k], 1u);
+            else atomicAdd(&cnt[k], 1ull);
+        });
+    if (lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc; i += DEC_TPB)
+            if (lc[i]) atomicAdd(&cnt[i], (unsigned long long)lc[i]);
+    }
 }
 
 template <typename T>
-__global__ void k_dec_scatter(const T *pos, int64_t n, DecGeo g, const double *thick, double T0, double T1,
-                              double T2, const uint8_t *own_mask, const int32_t *tpos, const int64_t *base,
-                              unsigned long long *cur, int64_t cap, double *out_pos, int32_t *out_gid) {
+__global__ void __launch_bounds__(DEC_TPB) k_dec_scatter(const T *pos, int64_t n, DecGeo g, const double *thick,
+                                                         double T0, double T1, double T2, const uint8_t *own_mask,
+                                                         const int32_t *tpos, int nc, const int64_t *base,
+                                                         unsigned long long *cur, int64_t cap, double *out_pos,
+                                                         int32_t *out_gid) {
+    extern __shared__ uint32_t lc[];
+    unsigned long long *lb = (unsigned long long *)(lc + ((nc + 1) & ~1));  // block's reserved range starts
+    const bool lds = nc <= DEC_LDS_COUNTERS;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
     const double Tm[3] = {T0, T1, T2};
-    double x[3];
-    dec_pos(pos, p, x);
-    dec_members(pos, p, g, thick, Tm, own_mask, tpos, [&](int b, const int *s, bool ghost) {
-        const int l = tpos ? tpos[b] : b;
-        const int64_t slot = (int64_t)atomicAdd(&cur[2 * (int64_t)l + (ghost ? 1 : 0)], 1ull);
-        const int64_t o = base[2 * (int64_t)l + (ghost ? 1 : 0)] + slot;
-        if (o >= cap) return;  // the count pass sized the output; never write past it
-        for (int a = 0; a < 3; ++a) out_pos[3 * o + a] = x[a] + (double)s[a] * g.L[a];
-        out_gid[o] = (int32_t)p;
-    });
+    double x[3] = {0.0, 0.0, 0.0};
+    if (p < n) dec_pos(pos, p, x);
+    if (lds) {
+        for (int i = threadIdx.x; i < nc; i += DEC_TPB) lc[i] = 0;
+        __syncthreads();
+        if (p < n)
+            dec_members(pos, p, g, thick, Tm, own_mask, tpos, [&](int b, const int *, bool ghost) {
+                atomicAdd(&lc[2 * (tpos ? tpos[b] : b) + (ghost ? 1 : 0)], 1u);
+            });
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc; i += DEC_TPB) {
+            lb[i] = lc[i] ? atomicAdd(&cur[i], (unsigned long long)lc[i]) : 0ull;
+            lc[i] = 0;
+        }
+        __syncthreads();
+    }
+    if (p < n)
+        dec_members(pos, p, g, thick, Tm, own_mask, tpos, [&](int b, const int *s, bool ghost) {
+            const int k = 2 * (tpos ? tpos[b] : b) + (ghost ? 1 : 0);
+            const int64_t slot = lds ? (int64_t)lb[k] + (int64_t)atomicAdd(&lc[k], 1u) : (int64_t)atomicAdd(&cur[k], 1ull);
+            const int64_t o = base[k] + slot;
+            if (o >= cap) return;  // the count pass sized the output; never write past it
+            for (int a = 0; a < 3; ++a) out_pos[3 * o + a] = x[a] + (double)s[a] * g.L[a];
+            out_gid[o] = (int32_t)p;
+        });
+}
+
+static size_t dec_lds_bytes(int nc, bool scatter) {
+    if (nc > DEC_LDS_COUNTERS) return 0;
+    const size_t c32 = sizeof(uint32_t) * (size_t)((nc + 1) & ~1);
+    return scatter ? c32 + sizeof(unsigned long long) * (size_t)nc : c32;
 }
 
 template <typename T>
@@ -244,9 +289,9 @@ vt_status dec_count(vt_ctx *c, const T *pos, int64_t n, const DecGeo &g, const d
     if (e != hipSuccess) return dec_err(e);
     e = vt_launch_zero_u32((uint32_t *)c->dec_cnt, 4 * n_list, s);
     if (e != hipSuccess) return dec_err(e);
-    const int tpb = 256;
-    k_dec_count<T><<<(n + tpb - 1) / tpb, tpb, 0, s>>>(pos, n, g, c->dec_thick, Tm[0], Tm[1], Tm[2], own_mask, d_tpos,
-                                                       (unsigned long long *)c->dec_cnt);
+    const int nc = (int)(2 * n_list);
+    k_dec_count<T><<<(n + DEC_TPB - 1) / DEC_TPB, DEC_TPB, dec_lds_bytes(nc, false), s>>>(
+        pos, n, g, c->dec_thick, Tm[0], Tm[1], Tm[2], own_mask, d_tpos, nc, (unsigned long long *)c->dec_cnt);
     e = hipGetLastError();
     if (e != hipSuccess) return dec_err(e);
     cnt.assign(2 * n_list, 0);
@@ -350,10 +395,10 @@ vt_status decompose_pack(vt_ctx *c, const T *pos, int64_t n, const DecGeo &g, co
     double Tm[3] = {0.0, 0.0, 0.0};
     for (int64_t b = 0; b < n_tasks; ++b)
         for (int a = 0; a < 3; ++a) Tm[a] = std::max(Tm[a], std::max(thick[6 * b + 2 * a], thick[6 * b + 2 * a + 1]));
-    const int tpb = 256;
-    k_dec_scatter<T><<<(n + tpb - 1) / tpb, tpb, 0, s>>>(pos, n, g, c->dec_thick, Tm[0], Tm[1], Tm[2], own_mask,
-                                                         c->dec_tpos, c->dec_base, (unsigned long long *)c->dec_cnt,
-                                                         off, out_pos, out_gid);
+    const int nc = 2 * n_list;
+    k_dec_scatter<T><<<(n + DEC_TPB - 1) / DEC_TPB, DEC_TPB, dec_lds_bytes(nc, true), s>>>(
+        pos, n, g, c->dec_thick, Tm[0], Tm[1], Tm[2], own_mask, c->dec_tpos, nc, c->dec_base,
+        (unsigned long long *)c->dec_cnt, off, out_pos, out_gid);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? VT_OK : dec_err(e);
