@@ -8,11 +8,12 @@
 // every multiplier even in k, so every component is real.
 //
 // The 3D FFT is three passes of 1D transforms, one per axis.  A block takes B whole lines of
-// length N (B N <= 4096 complex values, 64 KB of LDS) chosen so that its loads and stores are
-// coalesced: lines along the contiguous axis are taken consecutively, lines along the other
-// axes side by side.  Each line is transformed in LDS by an in-place radix-2 decimation in time
-// (loaded in bit-reversed order), twiddles from sincospi in FP64.  Two real components go
-// through one inverse transform as the real and imaginary parts of one complex field.
+// length N (B N <= 4096 complex values, 64 KB of LDS, plus N / 2 twiddles) chosen so that its
+// loads and stores are coalesced: lines along the contiguous axis are taken consecutively, lines
+// along the other axes side by side.  Each line is transformed in LDS by an in-place radix-2
+// decimation in time (loaded in bit-reversed order); the twiddles are computed once per block
+// with sincospi in FP64.  Two real components go through one inverse transform as the real and
+// imaginary parts of one complex field.
 #include "vt_internal.h"
 
 #define FFT_TPB 256
@@ -31,6 +32,14 @@ __global__ void __launch_bounds__(FFT_TPB) k_fft(double2 *data, int n0, int n1, 
     const int N = 1 << logn;
     const int64_t l0 = (int64_t)blockIdx.x * B;
     const int total = B * N;
+    // twiddles exp(sign 2 pi i m / N), m < N / 2; stage s takes m = k N / 2^s, the same argument
+    // k / 2^(s-1) as evaluating it in the stage
+    double2 *tw = sl + total;
+    for (int m = threadIdx.x; m < N / 2; m += FFT_TPB) {
+        double sn, cs;
+        sincospi(sign * 2.0 * (double)m / (double)N, &sn, &cs);
+        tw[m] = make_double2(cs, sn);
+    }
     // load in bit-reversed order within each line; consecutive threads take consecutive
     // addresses (along the line for the contiguous axis, across lines otherwise)
     for (int t = threadIdx.x; t < total; t += FFT_TPB) {
@@ -54,8 +63,8 @@ __global__ void __launch_bounds__(FFT_TPB) k_fft(double2 *data, int n0, int n1, 
             const int k = j & (half - 1);
             const int i0 = l * N + ((j >> (s - 1)) << s) + k;
             const int i1 = i0 + half;
-            double sn, cs;
-            sincospi(sign * (double)k / (double)half, &sn, &cs);
+            const double2 t = tw[k << (logn - s)];
+            const double cs = t.x, sn = t.y;
             const double2 u = sl[i0], v = sl[i1];
             const double2 w = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
             sl[i0] = make_double2(u.x + w.x, u.y + w.y);
@@ -139,7 +148,7 @@ static hipError_t fft3(double2 *d, const int n[3], double sign, hipStream_t s) {
         const int64_t nlines = ((int64_t)n[0] * n[1] * n[2]) / N;
         int B = FFT_LDS / N;
         if (B > nlines) B = (int)nlines;
-        const size_t lds = sizeof(double2) * (size_t)B * N;
+        const size_t lds = sizeof(double2) * ((size_t)B * N + N / 2);
         hipError_t e = hipFuncSetAttribute((const void *)k_fft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         k_fft<<<dim3((unsigned)(nlines / B)), dim3(FFT_TPB), lds, s>>>(d, n[0], n[1], n[2], axis, logn, B, sign);
