@@ -8,16 +8,17 @@
 // every multiplier even in k, so every component is real.
 //
 // The 3D FFT is three passes of 1D transforms, one per axis.  A block takes B whole lines of
-// length N (B N <= 4096 complex values, 64 KB of LDS, plus N / 2 twiddles) chosen so that its
-// loads and stores are coalesced: lines along the contiguous axis are taken consecutively, lines
-// along the other axes side by side.  Each line is transformed in LDS by an in-place radix-2
+// length N (B N up to 2048 complex values, 32 KB of LDS, plus N / 2 twiddles; a line of 4096 is
+// a block of its own) chosen so that its loads and stores are coalesced: lines along the
+// contiguous axis are taken consecutively, lines along the other axes side by side.  Blocks of
+// 32 KB leave room for four per CU; blocks of 64 KB, two, and took 27% longer at 256^3.  Each line is transformed in LDS by an in-place radix-2
 // decimation in time (loaded in bit-reversed order); the twiddles are computed once per block
 // with sincospi in FP64.  Two real components go through one inverse transform as the real and
 // imaginary parts of one complex field.
 #include "vt_internal.h"
 
 #define FFT_TPB 256
-#define FFT_LDS 4096   // complex values per block
+#define FFT_LDS 2048   // complex values per block (lines of up to 4096 take one block each)
 
 // element i of line l of the transform along `axis` of an n0 x n1 x n2 array (n2 contiguous)
 __device__ __forceinline__ int64_t line_elem(int axis, int64_t l, int64_t i, int n1, int n2) {
@@ -146,7 +147,7 @@ static hipError_t fft3(double2 *d, const int n[3], double sign, hipStream_t s) {
         int logn = 0;
         while ((1 << logn) < N) ++logn;
         const int64_t nlines = ((int64_t)n[0] * n[1] * n[2]) / N;
-        int B = FFT_LDS / N;
+        int B = N >= FFT_LDS ? 1 : FFT_LDS / N;
         if (B > nlines) B = (int)nlines;
         const size_t lds = sizeof(double2) * ((size_t)B * N + N / 2);
         hipError_t e = hipFuncSetAttribute((const void *)k_fft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
