@@ -1,6 +1,7 @@
 """Grid tensors (vt_grid_tensor) on the GPU against the oracle's discrete-Fourier reference:
-random fields on grids of unequal power-of-two sides, a deposited density grid, both kinds,
-within 1e-12 of the largest component; bad sizes are refused."""
+random fields on grids of unequal power-of-two sides (the longest lines, 4096, along a strided
+and along the contiguous axis), a deposited density grid, both kinds, within 1e-12 of the
+largest component; bad sizes are refused."""
 import numpy as np
 import pytest
 
@@ -15,7 +16,7 @@ def _ctx(vt, torch_cuda):
 
 
 @pytest.mark.parametrize("kind", ["tidal", "hessian"])
-@pytest.mark.parametrize("shape", [(32, 16, 64), (8, 128, 4), (2, 2, 2)])
+@pytest.mark.parametrize("shape", [(32, 16, 64), (8, 128, 4), (2, 2, 2), (4096, 2, 4), (2, 4, 4096)])
 def test_grid_tensor_random_field(vt, torch_cuda, oracle, kind, shape):
     w, ctx = _ctx(vt, torch_cuda)
     f = 2.0 + np.random.default_rng(51).random(shape)
