@@ -211,3 +211,22 @@ def test_structure_vtu_file(vt, torch_cuda, tmp_path):
     fs, fo = r["faces"], r["faceoffsets"]
     starts = np.concatenate([[0], fo[:-1]])
     assert np.array_equal(fs[starts], np.diff(st.face_off.cpu().numpy()))
+
+
+@pytest.mark.parametrize("kind,n_faces,n_points", [("sc", 6, 8), ("bcc", 14, 24), ("fcc", 12, 14)])
+def test_structure_lattices(vt, torch_cuda, kind, n_faces, n_points):
+    # degenerate inputs: contacts of zero area are not faces, and where four faces meet (the
+    # rhombic dodecahedron) the vertices of the kernel's simple polytope coincide; the distinct
+    # points are the polyhedron's corners and every face lies on its bisector
+    p = wl.lattice(kind, 4)
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(p).cuda(), vt.whole_box(len(p), 0.0, 1.0), want_faces=True)
+    h = _host(ctx.vt_structure())
+    assert ctx.vt_query()[0] == 0
+    for r in range(0, len(p), 7):
+        v, faces = _cell(h, r)
+        assert len(faces) == n_faces
+        assert len(np.unique(np.round(v, 12), axis=0)) == n_points
+        for j, loop in faces:
+            D = p[j] - p[r]
+            D -= np.rint(D)
+            np.testing.assert_allclose((v[loop] - p[r]) @ D, D @ D / 2, atol=1e-14)
