@@ -33,6 +33,16 @@ Readings where the paper is silent (documented with the design notes):
     smaller index (pinned by lattice points at voxel centres, a two-particle
     bisector, an exact tie, and convergence to the exact overlaps under finer
     sub-sampling);
+  * full structure (section 3, memory consumption; section 4): a cell's vertices
+    and its faces of area above the facet threshold as loops, counter-clockwise
+    seen from outside, ascending by the id across them (pinned by the cube and
+    truncated octahedron of lattices, the empty-sphere property of every vertex,
+    faces on their bisectors, Euler's formula, the divergence volume and walls);
+  * grid tensors (section 4, future grid outputs): tidal tensor d_i d_j phi with
+    laplacian(phi) = f / mean(f) - 1, and Hessian d_i d_j f, by numpy.fft on the
+    periodic grid, mixed components zero on Nyquist planes (pinned by single-mode
+    closed forms, a constant field, trace = density contrast and the Nyquist
+    convention);
   * adjoint: dV_i/dx_j = A_ij (x_j - c_ij) / d_ij and
     dV_i/dx_i = sum_j A_ij (c_ij - x_i) / d_ij (derived from the motion of the
     bisector plane; pinned by central finite differences of the oracle's own
