@@ -56,6 +56,10 @@ def test_argument_errors_are_synchronous():
     assert L.vt_build(ctypes.byref(ctx), None, vt.VT_F32, None, items, 1, None, None) == 1
     # calls on a context that was never built
     assert L.vt_cells(None, None, None, None, 0, None, None) == 7
+    sizes = (ctypes.c_int64 * 3)()
+    assert L.vt_structure(None, None, None, 0, None, None, 0, None, None, 0, sizes, None) == 7
+    assert L.vt_grid_tensor(None, None, 16, 16, 16, 0, None, None) == 7
+    assert L.vt_grid_sample(None, None, 8, 8, 8, 1, None, None, None) == 7
 
 
 def test_autotune_selection_logic():
