@@ -643,20 +643,29 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
 
 // ---------------------------------------------------------------- nearest-particle sampling
 // A cheaper grid (the paper lists grid variants as future work): every sample point takes the
-// value of the particle nearest to it (periodic minimum image, FP64 squared distances; ties to
-// the smaller global id), i.e. of the Voronoi cell that contains it.  A voxel averages the sub^3
-// points at its sub-cell centres.  One wavefront takes a 4 x 4 x 4 tile of sample points (a
-// lane each) and scans one candidate list for the whole tile: the particles of the Morton cells
-// that cover the tile widened by r, staged through LDS 64 at a time.  A lane is done when its
-// best distance is below its distance to the sides of the covered cells less two key quanta
-// (every particle outside them is farther); otherwise the wave doubles r and scans again.  A
-// tile whose region holds more than VT_SAMPLE_DENSE particles (inside a dense halo) lets every
-// lane search on its own through finer cells.
-// The minimum-image shift uses rint(e / L) with 1 / L precomputed; it can round differently
-// from the quotient only near |e| = L / 2, where no nearest particle lies.
-#ifndef VT_SAMPLE_DENSE
-#define VT_SAMPLE_DENSE 4096   // candidates above which a tile's lanes search on their own
-#endif
+// value of the particle nearest to it (periodic minimum image, FP64 squared distances
+// ex*ex + ey*ey + ez*ez; ties to the smaller global id), i.e. of the Voronoi cell that contains
+// it.  A voxel averages the sub^3 points at its sub-cell centres.
+//
+// The tessellation is already built, so each cell claims its points: a wavefront per cell walks
+// the sample points within R of its seed (R its largest vertex distance) and claims a point
+// when the seed is nearer than every facet neighbour (or as near, with the smaller global id).
+// In exact arithmetic the cell is the intersection of its facet half-spaces, so the one cell
+// holding a point claims it; the comparisons are the reference's own squared distances, and
+// the claims go through a 64-bit atomic minimum on (global id, sorted index).  A point no cell
+// claims (rounding at a boundary, or a cell with more candidate points or facets than a wave takes)
+// is found by its own exact search.  With several points per voxel a cell's sphere holds
+// sub^3 times as many candidates, and tiles of points do better: one wavefront takes a 4 x 4 x 4
+// tile (a lane each) and scans one candidate list for the tile, the particles of the Morton
+// cells covering the tile widened by r, staged through LDS 64 at a time; a lane is done when its
+// best distance is below its distance to the sides of the covered cells less two key quanta,
+// otherwise r doubles, and a tile whose region holds more than VT_SAMPLE_DENSE particles lets
+// every lane search on its own through finer cells.  The minimum-image shift uses rint(e / L)
+// with 1 / L precomputed; it can round differently from the quotient only near |e| = L / 2,
+// where no nearest particle lies.
+#define VT_CLAIM_MAX 65536  // candidate points above which a cell leaves its points to the search
+#define VT_SAMPLE_DENSE 4096  // tiles: candidates above which a tile's lanes search on their own
+#define VT_CLAIM_NBR 160    // facet neighbours staged per cell (the large clip kernel keeps at most 136)
 
 struct SampleArgs {
     const void *spos;
@@ -665,13 +674,37 @@ struct SampleArgs {
     const int32_t *sgid;
     const int32_t *srow;
     const DevItem *items;
+    const int32_t *cells;       // cell slot -> sorted index of its seed
+    const uint8_t *cstat;
+    const double *crad;         // largest vertex distance per cell
+    const int64_t *crow;        // facet list: stage_ids[crow .. crow + ccnt)
+    const int32_t *ccnt;
+    const int32_t *stage_ids;
+    int64_t ncells;
     const double *value;
     double *grid;
-    int32_t *nearest;   // sub = 1: global id per voxel
-    int32_t *fine;      // sub > 1: sorted index of the nearest particle per sample point
+    int32_t *nearest;           // global id per voxel (of its last point), or null
+    unsigned long long *slot;   // per sample point: (global id << 32) | sorted index, ~0 unclaimed
     int nx, ny, nz, sub;
-    double r0;          // first widening (the mean inter-particle distance)
+    double r0;                  // tiles: first widening (the mean inter-particle distance)
 };
+
+// sample point (fine index f along axis a): voxel f / sub, sub-cell f % sub, at the sub-cell centre
+__device__ __forceinline__ double sample_coord(const DevItem &it, int a, int dim, int sub, int64_t f) {
+    const double h = it.L[a] / dim;
+    return it.lo[a] + ((double)(f / sub) + ((double)(f % sub) + 0.5) / (double)sub) * h;
+}
+
+// the same for f < 2^22 (the quotient by the float reciprocal, corrected)
+__device__ __forceinline__ double sample_coord32(const DevItem &it, int a, int dim, int sub, int f) {
+    const double h = it.L[a] / dim;
+    int rem;
+    const int vox = divmod_small(f, sub, rem);
+    return it.lo[a] + ((double)vox + ((double)rem + 0.5) / (double)sub) * h;
+}
+
+// i in [-n, 2n) to [0, n)
+__device__ __forceinline__ int wrap_once(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 struct SampleMem {
     int32_t rb[512];    // covering cells: range starts
@@ -777,6 +810,124 @@ __device__ int32_t nearest_particle(const SampleArgs &A, const DevItem &it, cons
         if (2 * k + 1 >= ncl) break;  // the block covers the whole box
     }
     return bj;
+}
+
+// One wavefront per cell: the facet neighbours are staged in LDS once (nearest first when
+// there are at most 64), and the lanes take the cell's candidate points 64 at a time.
+struct ClaimMem {
+    double px[VT_CLAIM_NBR], py[VT_CLAIM_NBR], pz[VT_CLAIM_NBR];
+    int32_t pg[VT_CLAIM_NBR];
+};
+
+template <typename PT4>
+__global__ void __launch_bounds__(256) k_sample_claim(SampleArgs A) {
+    __shared__ ClaimMem Ms[4];
+    ClaimMem &M = Ms[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const DevItem &it = A.items[0];
+    const int sub = A.sub;
+    const int dims[3] = {A.nx, A.ny, A.nz};
+    const int64_t F[3] = {(int64_t)A.nx * sub, (int64_t)A.ny * sub, (int64_t)A.nz * sub};
+    const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < A.ncells; c += nwaves) {
+        if (A.cstat[c] & VT_CELL_FAILED) continue;
+        const int32_t cnt = A.ccnt[c];
+        if (cnt > VT_CLAIM_NBR) continue;   // left to the search
+        const int32_t j0 = A.cells[c];
+        const int32_t gi = A.sgid[j0];
+        double x[3];
+        gpos<PT4>(A.spos, j0, x[0], x[1], x[2]);
+        const double R = A.crad[c] * (1.0 + 1e-9) + 1e-12 * it.S;
+        const double R2 = R * R;
+        if (!(R2 < 1e300)) continue;   // not a finite radius: the points go to the search
+        int64_t f0[3], nf[3];
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            const double hf = it.L[a] / (double)F[a];
+            f0[a] = (int64_t)floor((x[a] - R - it.lo[a]) / hf - 0.5) - 1;
+            nf[a] = (int64_t)floor((x[a] + R - it.lo[a]) / hf - 0.5) + 2 - f0[a];
+            if (nf[a] > F[a]) {   // the cell spans the period along a: every point once
+                f0[a] = 0;
+                nf[a] = F[a];
+            }
+            ok = ok && nf[a] >= 1;
+        }
+        const int64_t ncand = nf[0] * nf[1] * nf[2];
+        if (!ok || ncand > VT_CLAIM_MAX) continue;
+        // one correction brings every candidate index into [0, F)
+        for (int a = 0; a < 3; ++a) ok = ok && F[a] < (1 << 29) && f0[a] >= -F[a] && f0[a] + nf[a] <= 2 * F[a];
+        if (!ok) continue;
+        const int64_t row = A.crow[c];
+        if (cnt <= 64) {
+            // nearest neighbours first: a point outside the cell fails on one of them early
+            double px = 0.0, py = 0.0, pz = 0.0;
+            int32_t pg = 0;
+            uint64_t key[1] = {~0ull};
+            if (lane < cnt) {
+                const int32_t j = A.stage_ids[row + lane];
+                gpos<PT4>(A.spos, j, px, py, pz);
+                pg = A.sgid[j];
+                double ex = px - x[0], ey = py - x[1], ez = pz - x[2];
+                ex -= it.L[0] * rint(ex * invL[0]);
+                ey -= it.L[1] * rint(ey * invL[1]);
+                ez -= it.L[2] * rint(ez * invL[2]);
+                key[0] = ((uint64_t)__float_as_uint((float)(ex * ex + ey * ey + ez * ez)) << 32) | (uint64_t)lane;
+            }
+            bitonic_u64<1>(key);
+            const int src = (int)(key[0] & 63ull);
+            const double sx_ = __shfl(px, src), sy_ = __shfl(py, src), sz_ = __shfl(pz, src);
+            const int32_t sg_ = __shfl(pg, src);
+            if (lane < cnt) {
+                M.px[lane] = sx_;
+                M.py[lane] = sy_;
+                M.pz[lane] = sz_;
+                M.pg[lane] = sg_;
+            }
+        } else {
+            for (int k = lane; k < cnt; k += 64) {
+                const int32_t j = A.stage_ids[row + k];
+                gpos<PT4>(A.spos, j, M.px[k], M.py[k], M.pz[k]);
+                M.pg[k] = A.sgid[j];
+            }
+        }
+        wave_sync();
+        const unsigned long long mine = ((unsigned long long)(uint32_t)gi << 32) | (uint32_t)j0;
+        for (int64_t base = 0; base < ncand; base += 64) {
+            const int64_t m = base + lane;
+            if (m < ncand) {
+                // 32-bit index arithmetic: the candidate's offsets, then one period's correction
+                // (a periodic cell is less than a quarter period across)
+                int t, v;
+                const int r = divmod_small((int)m, (int)nf[2], t);
+                const int u = divmod_small(r, (int)nf[1], v);
+                const int w0 = wrap_once((int)f0[0] + u, (int)F[0]);
+                const int w1 = wrap_once((int)f0[1] + v, (int)F[1]);
+                const int w2 = wrap_once((int)f0[2] + t, (int)F[2]);
+                const double q0 = sample_coord32(it, 0, dims[0], sub, w0);
+                const double q1 = sample_coord32(it, 1, dims[1], sub, w1);
+                const double q2 = sample_coord32(it, 2, dims[2], sub, w2);
+                double e0 = x[0] - q0, e1 = x[1] - q1, e2 = x[2] - q2;
+                e0 -= it.L[0] * rint(e0 * invL[0]);
+                e1 -= it.L[1] * rint(e1 * invL[1]);
+                e2 -= it.L[2] * rint(e2 * invL[2]);
+                const double d2 = e0 * e0 + e1 * e1 + e2 * e2;
+                if (d2 <= R2) {
+                    bool win = true;
+                    for (int32_t k = 0; k < cnt && win; ++k) {
+                        double ex = M.px[k] - q0, ey = M.py[k] - q1, ez = M.pz[k] - q2;
+                        ex -= it.L[0] * rint(ex * invL[0]);
+                        ey -= it.L[1] * rint(ey * invL[1]);
+                        ez -= it.L[2] * rint(ez * invL[2]);
+                        const double dj = ex * ex + ey * ey + ez * ez;
+                        win = !(dj < d2 || (dj == d2 && M.pg[k] < gi));
+                    }
+                    if (win) atomicMin(&A.slot[((int64_t)w0 * F[1] + w1) * F[2] + w2], mine);
+                }
+            }
+        }
+        wave_sync();
+    }
 }
 
 template <typename PT4>
@@ -924,16 +1075,41 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
             const bool done = (whole[0] && whole[1] && whole[2]) || (bj >= 0 && reach > 0.0 && best < reach * reach);
             if (__ballot(valid && !done) == 0ull) break;
         }
-        if (valid) {
-            if (sub == 1) {
-                const int64_t v = (f[0] * A.ny + f[1]) * A.nz + f[2];
-                A.grid[v] = A.value[A.srow[bj]];
-                if (A.nearest) A.nearest[v] = bg;
-            } else {
-                A.fine[(f[0] * fd[1] + f[1]) * fd[2] + f[2]] = bj;
-            }
-        }
+        if (valid) A.slot[(f[0] * fd[1] + f[1]) * fd[2] + f[2]] = ((unsigned long long)(uint32_t)bg << 32) | (uint32_t)bj;
     }
+}
+
+// Points no cell claimed get their own exact search; with one point per voxel the voxel's
+// value is written here too.
+template <typename PT4>
+__global__ void k_sample_fixup(SampleArgs A) {
+    const int sub = A.sub;
+    const int64_t F[3] = {(int64_t)A.nx * sub, (int64_t)A.ny * sub, (int64_t)A.nz * sub};
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= F[0] * F[1] * F[2]) return;
+    unsigned long long s = A.slot[p];
+    if (s == ~0ull) {
+        const DevItem &it = A.items[0];
+        const int dims[3] = {A.nx, A.ny, A.nz};
+        const int64_t f[3] = {p / (F[1] * F[2]), (p / F[2]) % F[1], p % F[2]};
+        double q[3];
+        for (int a = 0; a < 3; ++a) q[a] = sample_coord(it, a, dims[a], sub, f[a]);
+        const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
+        int32_t bg;
+        const int32_t bj = nearest_particle<PT4>(A, it, q, invL, bg);
+        s = ((unsigned long long)(uint32_t)bg << 32) | (uint32_t)bj;
+        A.slot[p] = s;
+    }
+    if (sub == 1) {
+        const int32_t bj = (int32_t)(s & 0xFFFFFFFFull);
+        A.grid[p] = A.value[A.srow[bj]];
+        if (A.nearest) A.nearest[p] = (int32_t)(s >> 32);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // sub > 1: each voxel averages its sub^3 points in the reference's order
@@ -945,16 +1121,15 @@ __global__ void k_sample_average(SampleArgs A) {
     const int64_t iz = v % A.nz, iy = (v / A.nz) % A.ny, ix = v / ((int64_t)A.ny * A.nz);
     const int64_t fy = (int64_t)A.ny * sub, fz = (int64_t)A.nz * sub;
     double acc = 0.0;
-    int32_t last = 0;
+    unsigned long long last = 0;
     for (int s0 = 0; s0 < sub; ++s0)
         for (int s1 = 0; s1 < sub; ++s1)
             for (int s2 = 0; s2 < sub; ++s2) {
-                const int32_t j = A.fine[((ix * sub + s0) * fy + (iy * sub + s1)) * fz + (iz * sub + s2)];
-                acc += A.value[A.srow[j]];
-                last = j;
+                last = A.slot[((ix * sub + s0) * fy + (iy * sub + s1)) * fz + (iz * sub + s2)];
+                acc += A.value[A.srow[(int32_t)(last & 0xFFFFFFFFull)]];
             }
     A.grid[v] = acc / (double)(sub * sub * sub);
-    if (A.nearest) A.nearest[v] = A.sgid[last];
+    if (A.nearest) A.nearest[v] = (int32_t)(last >> 32);
 }
 
 hipError_t vt_launch_grid_sample(vt_ctx *c, const double *value, int nx, int ny, int nz, int sub, double *grid,
@@ -966,43 +1141,67 @@ hipError_t vt_launch_grid_sample(vt_ctx *c, const double *value, int nx, int ny,
     a.sgid = c->sgid;
     a.srow = c->srow;
     a.items = c->items;
+    a.cells = c->cells;
+    a.cstat = c->cstat;
+    a.crad = c->crad;
+    a.crow = c->crow;
+    a.ccnt = c->ccnt;
+    a.stage_ids = c->stage_ids;
+    a.ncells = c->n_owned;
     a.value = value;
     a.grid = grid;
     a.nearest = nearest;
-    a.fine = nullptr;
     a.nx = nx;
     a.ny = ny;
     a.nz = nz;
     a.sub = sub;
-    const DevItem &it = c->h_items[0];
-    a.r0 = cbrt(it.L[0] * it.L[1] * it.L[2] / (double)c->n_total);
+    // one 64-bit slot per sample point, kept by the context (samp_fine counts int32 words)
     const int64_t nfine = (int64_t)nx * ny * nz * sub * sub * sub;
-    if (sub > 1) {
-        if (nfine > c->cap_samp) {
-            if (c->samp_fine) hipFree(c->samp_fine);
-            c->samp_fine = nullptr;
-            c->cap_samp = 0;
-            hipError_t e = hipMalloc((void **)&c->samp_fine, sizeof(int32_t) * (size_t)nfine);
-            if (e != hipSuccess) return e;
-            c->cap_samp = nfine;
-        }
-        a.fine = c->samp_fine;
+    if (2 * nfine > c->cap_samp) {
+        if (c->samp_fine) (void)hipFree(c->samp_fine);
+        c->samp_fine = nullptr;
+        c->cap_samp = 0;
+        hipError_t e = hipMalloc((void **)&c->samp_fine, sizeof(unsigned long long) * (size_t)nfine);
+        if (e != hipSuccess) return e;
+        c->cap_samp = 2 * nfine;
     }
-    const size_t lds = sizeof(SampleMem) * 4;
+    a.slot = (unsigned long long *)c->samp_fine;
+    const DevItem &it0 = c->h_items[0];
+    a.r0 = cbrt(it0.L[0] * it0.L[1] * it0.L[2] / (double)c->n_total);
+    const int tpb = 256;
     int ncu = 0;
+    if (sub > 1) {
+        // several points per voxel: tiles of points sharing one candidate list
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+        if (ncu <= 0) ncu = 256;
+        const size_t lds = sizeof(SampleMem) * 4;
+        const int64_t tiles = ((int64_t)nx * sub + 3) / 4 * (((int64_t)ny * sub + 3) / 4) * (((int64_t)nz * sub + 3) / 4);
+        int64_t blocks = (tiles + 3) / 4;
+        if (blocks > (int64_t)ncu * 64) blocks = (int64_t)ncu * 64;
+        if (c->dtype == VT_F32)
+            k_sample_tiles<float4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
+        else
+            k_sample_tiles<double4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t nv = (int64_t)nx * ny * nz;
+        k_sample_average<<<(nv + tpb - 1) / tpb, tpb, 0, c->stream>>>(a);
+        return hipGetLastError();
+    }
+    // one point per voxel: the cells claim their points
+    k_fill_u64<<<(nfine + tpb - 1) / tpb, tpb, 0, c->stream>>>(a.slot, nfine, ~0ull);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
     if (ncu <= 0) ncu = 256;
-    const int64_t tiles = ((int64_t)nx * sub + 3) / 4 * (((int64_t)ny * sub + 3) / 4) * (((int64_t)nz * sub + 3) / 4);
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > (int64_t)ncu * 64) blocks = (int64_t)ncu * 64;
-    if (c->dtype == VT_F32)
-        k_sample_tiles<float4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
-    else
-        k_sample_tiles<double4><<<(unsigned)blocks, 256, lds, c->stream>>>(a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || sub == 1) return e;
-    const int64_t nv = (int64_t)nx * ny * nz;
-    k_sample_average<<<(nv + 255) / 256, 256, 0, c->stream>>>(a);
+    int64_t cblocks = (a.ncells + 3) / 4;
+    if (cblocks > (int64_t)ncu * 32) cblocks = (int64_t)ncu * 32;
+    if (cblocks < 1) cblocks = 1;
+    if (c->dtype == VT_F32) {
+        k_sample_claim<float4><<<(unsigned)cblocks, tpb, 0, c->stream>>>(a);
+        k_sample_fixup<float4><<<(nfine + tpb - 1) / tpb, tpb, 0, c->stream>>>(a);
+    } else {
+        k_sample_claim<double4><<<(unsigned)cblocks, tpb, 0, c->stream>>>(a);
+        k_sample_fixup<double4><<<(nfine + tpb - 1) / tpb, tpb, 0, c->stream>>>(a);
+    }
     return hipGetLastError();
 }
 
