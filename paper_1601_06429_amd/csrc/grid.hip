@@ -66,6 +66,8 @@ struct GridArgs {
     uint32_t *counters;
     double *grid;
     int nx, ny, nz;
+    int seg;                  // large kernel: which queue (see grid_body)
+    int n_large;              // fused launch: leading blocks that run the large kernel
 };
 
 __device__ __forceinline__ int64_t wrapi(int64_t i, int n) {
@@ -268,11 +270,13 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
     return D;
 }
 
+// The deposit of one wavefront (wid its index in the block's LDS).  The large kernel
+// (RETRY) takes queued cells: seg 0 both queues, seg 1 the clip's retry queue only (counter
+// CTR_GRID_RETRY), seg 2 only the cells the normal kernel handed over (counter CTR_GRID, zeroed
+// after the normal kernel has run).
 template <typename PT4, int VPL, bool RETRY>
-__global__ void __launch_bounds__(256) k_grid(GridArgs A) {
+__device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid) {
     using M = GridMem<VPL>;
-    extern __shared__ char smem[];
-    const int wid = threadIdx.x >> 6;
     M &S = *reinterpret_cast<M *>(smem + (size_t)wid * sizeof(M));
     const int lane = lane_id();
     const uint64_t mybit = 1ull << lane;
@@ -284,8 +288,14 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
     const double hv = h[0] * h[1] * h[2];
     const int dims[3] = {A.nx, A.ny, A.nz};
     const int64_t nq = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : 0;
-    const int64_t ntodo =
-        RETRY ? nq + (int64_t)min((uint64_t)A.counters[CTR_GRID_Q], (uint64_t)A.gqueue_cap) : A.ncells;
+    int64_t w_lo = 0, ntodo = RETRY ? nq + (int64_t)min((uint64_t)A.counters[CTR_GRID_Q], (uint64_t)A.gqueue_cap)
+                                    : A.ncells;
+    int ctr = RETRY ? CTR_GRID_RETRY : CTR_GRID;
+    if (RETRY && A.seg == 1) ntodo = nq;
+    if (RETRY && A.seg == 2) {
+        w_lo = nq;
+        ctr = CTR_GRID;
+    }
 
     // Cells are taken GB at a time: lane l loads the scalars of the batch's cell l (the latency
     // of those dependent loads is paid once per batch), a cell inside one voxel (its ball of
@@ -294,8 +304,8 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
     constexpr int GB = 16;
     for (;;) {
         int64_t wb = 0;
-        if (lane == 0) wb = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_GRID_RETRY : CTR_GRID], (uint32_t)GB);
-        wb = (int64_t)uni_i((int)__shfl((long long)wb, 0));
+        if (lane == 0) wb = (int64_t)atomicAdd(&A.counters[ctr], (uint32_t)GB);
+        wb = (int64_t)uni_i((int)__shfl((long long)wb, 0)) + w_lo;
         if (wb >= ntodo) break;
         const int64_t wl = wb + lane;
         int32_t cl = 0;
@@ -638,6 +648,25 @@ __global__ void __launch_bounds__(256) k_grid(GridArgs A) {
                 }
             }
         }
+    }
+}
+
+template <typename PT4, int VPL, bool RETRY>
+__global__ void __launch_bounds__(256) k_grid(GridArgs A) {
+    extern __shared__ char smem[];
+    grid_body<PT4, VPL, RETRY>(A, smem, (int)(threadIdx.x >> 6));
+}
+
+// The normal deposit and, in the first n_large blocks (one wavefront each), the large kernel
+// over the clip's retry queue, so that the few slow cells next to halos overlap the bulk.
+template <typename PT4>
+__global__ void __launch_bounds__(256) k_grid_fused(GridArgs A) {
+    extern __shared__ char smem[];
+    if ((int)blockIdx.x < A.n_large) {
+        if ((threadIdx.x >> 6) != 0) return;
+        grid_body<PT4, 4, true>(A, smem, 0);
+    } else {
+        grid_body<PT4, 1, false>(A, smem, (int)(threadIdx.x >> 6));
     }
 }
 
@@ -1224,6 +1253,35 @@ static hipError_t launch_grid_one(vt_ctx *c, GridArgs &a, int wpb) {
     return hipGetLastError();
 }
 
+template <typename PT4>
+static hipError_t launch_grid_fused(vt_ctx *c, GridArgs &a) {
+    const size_t l1 = sizeof(GridMem<1>) * 4, l4 = sizeof(GridMem<4>);
+    const size_t lds = l1 > l4 ? l1 : l4;
+    auto kern = k_grid_fused<PT4>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int ncu = 0;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (ncu <= 0) ncu = 256;
+    a.n_large = ncu;
+    a.seg = 1;
+    const int64_t blocks = (int64_t)ncu + (int64_t)ncu * 16 / 4;
+    kern<<<dim3((unsigned)blocks), dim3(256), lds, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+// The normal kernel with the large one over the clip's retry queue in one launch, then the large
+// kernel over the cells the normal one handed over.
+template <typename PT4>
+static hipError_t launch_grid_all(vt_ctx *c, GridArgs &a) {
+    hipError_t e = launch_grid_fused<PT4>(c, a);
+    if (e == hipSuccess) e = vt_launch_zero_u32(c->counters + CTR_GRID, 1, c->stream);
+    if (e != hipSuccess) return e;
+    a.seg = 2;
+    a.n_large = 0;
+    return launch_grid_one<PT4, 4, true>(c, a, 1);
+}
+
 hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz, double *grid) {
     const int64_t ng = (int64_t)nx * ny * nz;
     k_zero_f64<<<(ng + 255) / 256, 256, 0, c->stream>>>(grid, ng);
@@ -1255,13 +1313,7 @@ hipError_t vt_launch_grid(vt_ctx *c, const double *value, int nx, int ny, int nz
     a.nx = nx;
     a.ny = ny;
     a.nz = nz;
-    hipError_t e;
-    if (c->dtype == VT_F32) {
-        e = launch_grid_one<float4, 1, false>(c, a, 4);
-        if (e == hipSuccess) e = launch_grid_one<float4, 4, true>(c, a, 1);
-    } else {
-        e = launch_grid_one<double4, 1, false>(c, a, 4);
-        if (e == hipSuccess) e = launch_grid_one<double4, 4, true>(c, a, 1);
-    }
-    return e;
+    a.seg = 0;
+    a.n_large = 0;
+    return c->dtype == VT_F32 ? launch_grid_all<float4>(c, a) : launch_grid_all<double4>(c, a);
 }
