@@ -11,9 +11,10 @@
 // length N (B N up to 2048 complex values, 32 KB of LDS, plus N / 2 twiddles; a line of 4096 is
 // a block of its own) chosen so that its loads and stores are coalesced: lines along the
 // contiguous axis are taken consecutively, lines along the other axes side by side.  Blocks of
-// 32 KB leave room for four per CU; blocks of 64 KB, two, and took 27% longer at 256^3.  Each line is transformed in LDS by an in-place radix-2
-// decimation in time (loaded in bit-reversed order); the twiddles are computed once per block
-// with sincospi in FP64.  Two real components go through one inverse transform as the real and
+// 32 KB leave room for four per CU; blocks of 64 KB, two, and took 27% longer at 256^3.  Each
+// line is transformed in LDS by an in-place radix-2 decimation in time (loaded in bit-reversed
+// order), two stages per pass over the LDS; the twiddles are computed once per block with
+// sincospi in FP64.  Two real components go through one inverse transform as the real and
 // imaginary parts of one complex field.
 #include "vt_internal.h"
 
@@ -25,6 +26,11 @@ __device__ __forceinline__ int64_t line_elem(int axis, int64_t l, int64_t i, int
     if (axis == 2) return l * n2 + i;
     if (axis == 1) return (l / n2) * ((int64_t)n1 * n2) + (l % n2) + i * n2;
     return l + i * ((int64_t)n1 * n2);
+}
+
+// v times the twiddle t = (cos, sin)
+__device__ __forceinline__ double2 bmul(double2 v, double2 t) {
+    return make_double2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
 }
 
 __global__ void __launch_bounds__(FFT_TPB) k_fft(double2 *data, int n0, int n1, int n2, int axis, int logn, int B,
@@ -56,7 +62,32 @@ __global__ void __launch_bounds__(FFT_TPB) k_fft(double2 *data, int n0, int n1, 
         sl[l * N + r] = data[line_elem(axis, l0 + l, i, n1, n2)];
     }
     __syncthreads();
-    for (int s = 1; s <= logn; ++s) {
+    // stages s and s + 1 together: a thread takes the four points k, k + h, k + 2h, k + 3h of a
+    // block of 4h (h = 2^(s-1)) through both radix-2 stages in registers, each point through
+    // the same butterflies as stage by stage
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);
+        for (int b = threadIdx.x; b < total / 4; b += FFT_TPB) {
+            const int l = b >> (logn - 2);
+            const int j = b & (N / 4 - 1);
+            const int k = j & (h - 1);
+            const int i0 = l * N + ((j >> (s - 1)) << (s + 1)) + k;
+            const double2 a = sl[i0], bb = sl[i0 + h], c = sl[i0 + 2 * h], d = sl[i0 + 3 * h];
+            const double2 t1 = tw[k << (logn - s)];
+            const double2 t2 = tw[k << (logn - s - 1)], t3 = tw[(k + h) << (logn - s - 1)];
+            const double2 wb = bmul(bb, t1), wd = bmul(d, t1);
+            const double2 a1 = make_double2(a.x + wb.x, a.y + wb.y), b1 = make_double2(a.x - wb.x, a.y - wb.y);
+            const double2 c1 = make_double2(c.x + wd.x, c.y + wd.y), d1 = make_double2(c.x - wd.x, c.y - wd.y);
+            const double2 wc = bmul(c1, t2), wd1 = bmul(d1, t3);
+            sl[i0] = make_double2(a1.x + wc.x, a1.y + wc.y);
+            sl[i0 + 2 * h] = make_double2(a1.x - wc.x, a1.y - wc.y);
+            sl[i0 + h] = make_double2(b1.x + wd1.x, b1.y + wd1.y);
+            sl[i0 + 3 * h] = make_double2(b1.x - wd1.x, b1.y - wd1.y);
+        }
+        __syncthreads();
+    }
+    if (s == logn) {   // an odd number of stages: the last one alone
         const int half = 1 << (s - 1);
         for (int b = threadIdx.x; b < total / 2; b += FFT_TPB) {
             const int l = b >> (logn - 1);
@@ -64,10 +95,8 @@ __global__ void __launch_bounds__(FFT_TPB) k_fft(double2 *data, int n0, int n1, 
             const int k = j & (half - 1);
             const int i0 = l * N + ((j >> (s - 1)) << s) + k;
             const int i1 = i0 + half;
-            const double2 t = tw[k << (logn - s)];
-            const double cs = t.x, sn = t.y;
-            const double2 u = sl[i0], v = sl[i1];
-            const double2 w = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+            const double2 u = sl[i0];
+            const double2 w = bmul(sl[i1], tw[k << (logn - s)]);
             sl[i0] = make_double2(u.x + w.x, u.y + w.y);
             sl[i1] = make_double2(u.x - w.x, u.y - w.y);
         }
