@@ -73,9 +73,14 @@ typedef enum {
  *   periodic = 1: the box [lo, hi) is periodic; it must be a cube, every
  *                 particle must lie in it, and n_ghost must be 0.
  *   periodic = 0: the box [lo, hi] bounds the world; its walls are the initial
- *                 cell (the buffer zone of section 2: cells that the walls still
- *                 touch, or whose security ball leaves the box, are flagged
- *                 VT_CELL_INCOMPLETE).
+ *                 cell.  A wall is either a cut through a larger volume (the
+ *                 outer side of the buffer zone of section 2) or a true boundary
+ *                 of the tessellated world (a survey volume's edge), as `walls`
+ *                 says.  A cell that a cut wall still touches, or whose security
+ *                 ball crosses a cut wall, is flagged VT_CELL_INCOMPLETE; true
+ *                 walls clip cells but never make them incomplete.
+ *   walls    (bounded items only) bit f set: box face f (-x, +x, -y, +y, -z, +z
+ *            for f = 0 .. 5) is a true boundary.  0 = every wall is a cut.
  * Owned outputs are dense over items: the owned particle k of item b is output
  * row sum_{b' < b} n_owned(b') + k.
  */
@@ -84,7 +89,7 @@ typedef struct {
     int64_t n_owned;
     int64_t n_ghost;
     int32_t periodic;
-    int32_t reserved;
+    int32_t walls;
     double lo[3];
     double hi[3];
 } vt_item;
@@ -287,45 +292,83 @@ vt_status vt_timings(vt_ctx *ctx, float ms[3]);
 /*
  * Domain decomposition with AUTOBORDER (section 2: the volume is split into
  * sub-volumes, each with a buffer zone of boundary particles; the buffer
- * starts at BORDERFACTOR times the mean inter-particle distance and, where the
- * particle density in it is below the mean, grows until it holds the number of
- * particles the mean density puts in the initial zone).  On one GPU the tasks
- * become the items of one batched vt_build.
+ * starts at BORDERFACTOR times the mean inter-particle distance, computed from
+ * the whole input, and, where the particle density in it is below the mean,
+ * grows until it holds the number of particles the mean density puts in the
+ * initial zone; cells whose buffer still did not suffice are reported).  On one
+ * GPU the tasks become the items of one batched vt_build.
  *
- * The periodic box [lo, hi)^3 is split into nt[0] x nt[1] x nt[2] equal tasks;
- * task b = (ix * nt[1] + iy) * nt[2] + iz owns the particles whose cell index
- * floor((x - lo) / w) (clamped to the grid) is (ix, iy, iz), w = (hi - lo) / nt.
- * The buffer zone of a face is the slab beyond it over the face's extent.
- * Reading of the growth rule: the thickness is thresholds[k] for the smallest k
- * whose slab holds at least nbar * A_face * thresholds[0] particles (nbar = n
- * over the box volume, A_face the face's area; a particle counts if its
- * distance beyond the face is below thresholds[k]); thresholds[n_thr - 1] if
- * no k does.  Thicknesses are capped below (L - w) / 2 per axis (L / 2 when
- * nt = 1 there) so that a buffered task spans less than one period.
+ * The world [lo, hi] is split into nt[0] x nt[1] x nt[2] equal tasks: the
+ * paper's scheme (a) is a power-of-two split into near-cubes, scheme (b) a
+ * split along one axis into slabs for elongated volumes (survey slices and
+ * cones).  Task b = (ix * nt[1] + iy) * nt[2] + iz owns the particles whose
+ * cell index floor((x - lo) / w) (clamped to the grid) is (ix, iy, iz),
+ * w = (hi - lo) / nt.  The world is either a periodic box [lo, hi) or a bounded
+ * volume [lo, hi] (every particle inside; its faces are true walls, see
+ * vt_item.walls).  The buffer zone of a task face is the slab beyond it over
+ * the face's extent.
+ *
+ * Reading of the growth rule: with s = (V / n)^(1/3) the mean inter-particle
+ * distance (V the world's volume), the thicknesses tried are
+ * t_k = border_factor * s * growth^k, k = 0 .. n_steps - 1, and a face takes
+ * the smallest t_k whose slab holds at least n / V * A_face * t_0 particles (a
+ * particle counts if its distance beyond the face is below t_k), t_{n_steps-1}
+ * if none does; then it is capped.  Periodic worlds: a buffered task spans
+ * less than one period, so the cap is (L - w) / 2 per axis (L / 2 with one task
+ * there).  Bounded worlds: the cap is the face's distance to the world's wall
+ * (0 on the world's own faces), so a buffered task never leaves the world.
  */
+typedef struct {
+    double border_factor;  /* BORDERFACTOR, default 1.5 (the paper's example value) */
+    double growth;         /* ratio of consecutive thicknesses, default 1.1 */
+    int32_t n_steps;       /* thicknesses tried, 1 .. 64, default 48 */
+    int32_t max_reruns;    /* vt_decomposed_build: passes after the first, default 3 */
+    double widen;          /* vt_decomposed_build: buffer factor per re-run, default 2 */
+} vt_border;
+
+/*
+ * vt_task_grid -- tasks per axis for the paper's two layouts (section 2), host
+ * only.  scheme 0 (a): the box is halved along x, then y, then z, and round
+ * again, until there are n_task equal regions (n_task a power of two; 32 gives
+ * 4 x 4 x 2).  scheme 1 (b): n_task slabs along `axis` (elongated volumes).
+ * nt: host out, 3 int32.  Errors: VT_ERR_ARG.
+ */
+vt_status vt_task_grid(int32_t n_task, int32_t scheme, int32_t axis, int32_t nt[3]);
+
+/*
+ * vt_border_thresholds -- the thicknesses t_k above for n particles in the
+ * world [lo, hi] (host only; no device is touched).  Zero fields of `border`
+ * (nullable) take their defaults.  out: host, n_steps doubles.
+ * Errors: VT_ERR_ARG.
+ */
+vt_status vt_border_thresholds(int64_t n, const double lo[3], const double hi[3], const vt_border *border,
+                               double *out);
 
 /*
  * vt_decompose -- the AUTOBORDER thicknesses and the task sizes.
  *   ctx          in/out as for vt_build (the decomposition keeps its own
  *                scratch in the context).
- *   pos          device, n x 3 positions (dtype), every particle in [lo, hi).
+ *   pos          device, n x 3 positions (dtype), every particle in the world.
+ *   periodic     1: periodic box [lo, hi); 0: bounded world [lo, hi].
  *   nt           host, tasks per axis, each >= 1.
- *   thresholds   host, n_thr (1..64) increasing positive thicknesses.
+ *   border       host, nullable (defaults).
  *   thick        host out, 6 per task: faces -x, +x, -y, +y, -z, +z.
- *   n_owned      host out, per task: owned particles.
- *   n_ghost      host out, per task: buffer particles (particle images inside
- *                the buffered box that the task does not own).
+ *   n_owned      host out (nullable), per task: owned particles.
+ *   n_ghost      host out (nullable), per task: buffer particles (particle
+ *                images inside the buffered box that the task does not own).
  * Synchronises the stream.  Errors: VT_ERR_ARG, VT_ERR_OOM, VT_ERR_HIP.
  */
 vt_status vt_decompose(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n, const double lo[3],
-                       const double hi[3], const int32_t nt[3], const double *thresholds, int32_t n_thr,
+                       const double hi[3], int32_t periodic, const int32_t nt[3], const vt_border *border,
                        double *thick, int64_t *n_owned, int64_t *n_ghost, void *stream);
 
 /*
  * vt_decompose_pack -- the batch for vt_build: for each listed task (in list
- * order), its owned particles and then its buffer particles, shifted by whole
- * periods next to the task, as FP64 (exact: the shifts are multiples of L).
- *   thick        host, 6 per task (as from vt_decompose, or widened).
+ * order), its owned particles and then its buffer particles (periodic worlds:
+ * shifted by whole periods next to the task), as FP64 (exact: the shifts are
+ * multiples of L).
+ *   thick        host, 6 per task (as from vt_decompose, or widened; at most
+ *                the caps above).
  *   own_mask     device, n bytes or NULL: if given, a task owns only its
  *                particles with a nonzero byte, and its other particles are
  *                buffer particles (to re-run the incomplete cells of a first
@@ -333,16 +376,44 @@ vt_status vt_decompose(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n,
  *   tasks        host, n_list task indices, or NULL for every task in order.
  *   out_pos      device, cap x 3 doubles; out_gid device, cap int32 (the
  *                particle's index in pos).
- *   items        host out, n_list bounded items (box = the buffered box).
+ *   items        host out, n_list bounded items (box = the buffered box; in a
+ *                bounded world the faces that lie on the world's faces are
+ *                marked true walls).
  *   n_out        host out, particles written (or needed, if above cap).
  * A listed task must own at least one particle.  Synchronises the stream.
  * Errors: VT_ERR_ARG, VT_ERR_CAPACITY (cap too small; *n_out is the size
  * needed and nothing was written), VT_ERR_OOM, VT_ERR_HIP.
  */
 vt_status vt_decompose_pack(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n, const double lo[3],
-                            const double hi[3], const int32_t nt[3], const double *thick, const uint8_t *own_mask,
-                            const int32_t *tasks, int32_t n_list, double *out_pos, int32_t *out_gid, int64_t cap,
-                            vt_item *items, int64_t *n_out, void *stream);
+                            const double hi[3], int32_t periodic, const int32_t nt[3], const double *thick,
+                            const uint8_t *own_mask, const int32_t *tasks, int32_t n_list, double *out_pos,
+                            int32_t *out_gid, int64_t cap, vt_item *items, int64_t *n_out, void *stream);
+
+/*
+ * vt_decomposed_build -- the whole AUTOBORDER procedure on one device:
+ * thicknesses (vt_decompose), all tasks packed and built as one batch, then up
+ * to border->max_reruns more passes in which the cells still INCOMPLETE are
+ * built again, owned alone by their tasks, whose buffers are widened by
+ * border->widen (up to the caps).  Each particle's result is taken from the
+ * last pass that computed its cell.  Afterwards the context answers vt_cells,
+ * vt_density and vt_query in PARTICLE order (row i = particle i of pos, ids =
+ * indices in pos), with VT_CELL_INCOMPLETE left on cells that the last pass
+ * still could not complete; vt_query's n_retried and n_incomplete are those of
+ * the last pass.  Other calls on the context return VT_ERR_STATE until it is
+ * built again.
+ *   opts         host, nullable: options of the builds (want_faces ignored).
+ *   thick        host out (nullable), 6 per task: the first pass's thicknesses.
+ *   pass_stats   host out (nullable), 4 int64 per pass, (max_reruns + 1) rows:
+ *                tasks built, particles packed, cells built, cells left
+ *                incomplete.
+ *   n_passes     host out (nullable): passes run.
+ * Synchronises the stream.  Errors: as vt_decompose and vt_build; a device
+ * error of a pass's build (vt_query) is returned as is.
+ */
+vt_status vt_decomposed_build(vt_ctx **ctx, const void *pos, vt_dtype dtype, int64_t n, const double lo[3],
+                              const double hi[3], int32_t periodic, const int32_t nt[3], const vt_border *border,
+                              const vt_opts *opts, double *thick, int64_t *pass_stats, int32_t *n_passes,
+                              void *stream);
 
 /* n_owned_total and n_total of the last build (host, no sync). */
 vt_status vt_sizes(vt_ctx *ctx, int64_t *n_owned_total, int64_t *n_total);

@@ -161,6 +161,98 @@ def cells(pos, box_lo, box_hi, periodic=True, query=None, gid=None, tol=1e-12, a
     return Cells(q, vol, rmax, flags, nnb, topo, nbr, farea, fcen, fdist)
 
 
+def local_cells(pos, box_lo, box_hi, query, periodic=True, moved=None, k0=24, tree=None, workers=16,
+                tol=1e-12, area_eps=1e-12, stride=256) -> Cells:
+    """The same cells as ``cells`` for the particles in ``query``, each computed in a small
+    bounded world around it, so that large inputs take seconds.
+
+    The world of particle i holds every particle (periodic: its minimum image) within a ball of
+    radius r around x_i, and its box is the cube of half-side r.  The cell computed there equals
+    the cell in the whole input once no box wall remains a face and 2 R < r, R the largest vertex
+    distance: every particle that could cut the cell lies within 2 R of x_i (section 2 of the
+    paper's security-radius argument for buffer particles), and all of those are in the world.
+    Otherwise r is doubled and the cell computed again.  r starts at 3 times the distance to
+    the k0-th nearest particle.  ``moved`` ({index: position}) replaces particle positions, for
+    finite differences; the moved particles must stay within r of where they were by a margin,
+    which the 2 R < 0.999 r test leaves.  Particle selection uses scipy's k-d tree (a library
+    search structure, not part of the cell's arithmetic)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from scipy.spatial import cKDTree
+
+    x = np.ascontiguousarray(pos, np.float64)
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    hi = np.broadcast_to(np.asarray(box_hi, np.float64), 3)
+    L = hi - lo
+    q = np.asarray(query, np.int64)
+    if tree is None:
+        tree = cKDTree(x - lo, boxsize=L if periodic else None)
+    moved = moved or {}
+    mv_idx = np.array(sorted(moved), np.int64)
+    d0, _ = tree.query(x[q] - lo, k=min(k0 + 1, len(x)))
+    r0 = 3.0 * d0[:, -1]
+
+    def one(t):
+        i = int(q[t])
+        xi = moved.get(i, x[i])
+        r = float(r0[t])
+        for _ in range(40):
+            r_q = min(r, 0.499 * float(L.min())) if periodic else r
+            idx = np.asarray(tree.query_ball_point(xi - lo, r_q), np.int64)
+            idx = np.union1d(idx, mv_idx[np.linalg.norm(_shift(np.array([moved[k] for k in mv_idx]), xi, L,
+                                                                  periodic), axis=1) < r_q]
+                             if len(mv_idx) else np.zeros(0, np.int64))
+            if i not in idx:
+                idx = np.union1d(idx, [i])
+            p = x[idx].copy()
+            for k, v in moved.items():
+                hit = np.nonzero(idx == k)[0]
+                if len(hit):
+                    p[hit[0]] = v
+            p = xi + _shift(p, xi, L, periodic)
+            if not periodic:
+                keep = np.all((p >= lo) & (p <= hi), axis=1)
+                p, idx = p[keep], idx[keep]
+            wlo = xi - r_q
+            whi = xi + r_q
+            if not periodic:
+                # the cube, cut by the world's own walls (those are faces of the true cell too)
+                wlo = np.maximum(wlo, lo)
+                whi = np.minimum(whi, hi)
+            me = int(np.nonzero(idx == i)[0][0])
+            c = cells(p, wlo, whi, periodic=False, query=[me], gid=idx, tol=tol, area_eps=area_eps, stride=stride,
+                      nthreads=1)
+            # every particle within 2 R is in the world (the ball of radius r_q), and a cell within
+            # R < r_q / 2 of its seed touches no wall of the cube (the world's own walls of a bounded
+            # input are faces of the true cell as well)
+            if 2.0 * c.rmax[0] < 0.999 * r_q:
+                return c
+            if periodic and r_q >= 0.499 * float(L.min()):
+                raise RuntimeError("local_cells: cell %d reaches half the box" % i)
+            r *= 2.0
+        raise RuntimeError("local_cells: no world proves cell %d" % i)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(one, range(len(q))))
+    nq = len(q)
+    vol = np.array([c.volume[0] for c in res])
+    rmax = np.array([c.rmax[0] for c in res])
+    flags = np.array([c.flags[0] for c in res], np.int32)
+    nnb = np.array([c.nnb[0] for c in res], np.int32)
+    topo = np.stack([c.topo[0] for c in res]) if nq else np.zeros((0, 5), np.int64)
+    nbr = np.stack([c._nbr[0] for c in res]) if nq else np.zeros((0, stride), np.int64)
+    farea = np.stack([c._farea[0] for c in res]) if nq else np.zeros((0, stride))
+    fcen = np.stack([c._fcen[0] for c in res]) if nq else np.zeros((0, stride, 3))
+    fdist = np.stack([c._fdist[0] for c in res]) if nq else np.zeros((0, stride))
+    return Cells(q, vol, rmax, flags, nnb, topo, nbr, farea, fcen, fdist)
+
+
+def _shift(p, xi, L, periodic):
+    """Separations p - xi, minimum image in a periodic box."""
+    d = np.asarray(p, np.float64) - xi
+    return d - L * np.rint(d / L) if periodic else d
+
+
 def structure(pos, box_lo, box_hi, i, periodic=True, gid=None, tol=1e-12, area_eps=1e-12, cap=4096):
     """Full structure of cell i (section 3, memory consumption; section 4): its vertices
     (absolute, k x 3, every vertex on a face) and its faces of positive area as a list of
@@ -298,33 +390,57 @@ def task_index(pos, box_lo, box_hi, nt):
     return np.clip(np.floor((x - lo) / (L / nt)).astype(np.int64), 0, nt - 1)
 
 
-def thickness_cap(box_lo, box_hi, nt):
-    """Largest buffer thickness per axis: a buffered task must span less than one period."""
+def mean_spacing(n, box_lo, box_hi):
+    """Mean inter-particle distance computed from the whole input (section 2, buffer zones):
+    the side of the cube that holds one particle on average, (V / n)^(1/3)."""
     L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    nt = np.asarray(nt)
-    return np.where(nt >= 2, 0.5 * (L - L / nt), 0.5 * L) * (1.0 - 1e-12)
+    return float(np.cbrt(np.prod(L) / n))
 
 
-def autoborder(pos, box_lo, box_hi, nt, thresholds):
+def _task_bounds(lo, hi, nt, a, j):
+    """Lower and upper coordinate of task cell j along axis a (the last cell ends at hi)."""
+    w = (hi[a] - lo[a]) / nt[a]
+    return lo[a] + j * w, (hi[a] if j + 1 >= nt[a] else lo[a] + (j + 1) * w)
+
+
+def face_cap(box_lo, box_hi, nt, ii, f, periodic=True):
+    """Largest buffer thickness of face f (-x, +x, -y, +y, -z, +z) of the task with cell index ii:
+    periodic, a buffered task spans less than one period ((L - w) / 2, L / 2 for a single task along
+    the axis); bounded, the buffer stops at the world's face beyond it."""
+    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
+    hi = np.broadcast_to(np.asarray(box_hi, np.float64), 3)
+    a = f // 2
+    L = hi[a] - lo[a]
+    if periodic:
+        w = L / nt[a]
+        return (0.5 * (L - w) if nt[a] >= 2 else 0.5 * L) * (1.0 - 1e-12)
+    c0, c1 = _task_bounds(lo, hi, nt, a, ii[a])
+    return hi[a] - c1 if f % 2 else c0 - lo[a]
+
+
+def autoborder(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, steps=48, periodic=True):
     """AUTOBORDER thicknesses, n_tasks x 6 (faces -x, +x, -y, +y, -z, +z), section 2.
 
-    For the face of task (i0, i1, i2) normal to axis a on side +/-: the particles
-    in the face's column (same cell index on the two other axes) at periodic
-    distance d beyond the face, d = (x_a - F) mod L_a (+) or (F - x_a) mod L_a (-),
-    F the face's coordinate; the slab of thickness t holds those with
-    d < min(t, cap_a).  The thickness is the first threshold whose slab holds at
-    least n / V * A_face * thresholds[0] particles, the last threshold if none
-    does, and at most cap_a.
+    The initial zone is border_factor times the mean inter-particle distance s of the whole
+    input.  It grows, through border_factor * s * growth^k, until the slab beyond the face holds
+    as many particles as the mean density puts in the initial zone.  For the face of task
+    (i0, i1, i2) normal to axis a on side +/-, the particles counted are those in the face's column
+    (same cell index on the two other axes) at distance d beyond the face:
+    d = (x_a - F) or (F - x_a), taken mod L_a in a periodic box; in a bounded world only d >= 0
+    counts.  F is the face's coordinate.  A slab of thickness t holds those with d < min(t, cap).
+    The thickness is the first t_k whose slab holds at least n / V * A_face * t_0 particles, the
+    last one if none does, and at most the face's cap (``face_cap``).
     """
     x = np.asarray(pos, np.float64)
     n = len(x)
     lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    hi = np.broadcast_to(np.asarray(box_hi, np.float64), 3)
+    L = hi - lo
     nt = np.asarray(nt, np.int64)
     w = L / nt
-    thr = np.asarray(thresholds, np.float64)
-    cap = thickness_cap(box_lo, box_hi, nt)
-    idx = task_index(x, box_lo, box_hi, nt)
+    s = mean_spacing(n, lo, hi)
+    thr = border_factor * s * growth ** np.arange(steps, dtype=np.float64)
+    idx = task_index(x, lo, hi, nt)
     nbar = n / float(np.prod(L))
     out = np.zeros((int(np.prod(nt)), 6))
     for i0 in range(nt[0]):
@@ -336,43 +452,55 @@ def autoborder(pos, box_lo, box_hi, nt, thresholds):
                     c1, c2 = (a + 1) % 3, (a + 2) % 3
                     col = (idx[:, c1] == ii[c1]) & (idx[:, c2] == ii[c2])
                     expect = nbar * w[c1] * w[c2] * thr[0]
+                    f0, f1 = _task_bounds(lo, hi, nt, a, ii[a])
                     for side in (0, 1):
+                        cap = face_cap(lo, hi, nt, ii, 2 * a + side, periodic)
                         if side:
-                            F = lo[a] + (ii[a] + 1) * w[a]
-                            d = np.mod(x[col, a] - F, L[a])
+                            d = x[col, a] - f1
                         else:
-                            F = lo[a] + ii[a] * w[a]
-                            d = np.mod(F - x[col, a], L[a])
+                            d = f0 - x[col, a]
+                        if periodic:
+                            d = np.mod(d, L[a])
+                        else:
+                            d = d[d >= 0]
                         t = thr[-1]
                         for tk in thr:
-                            if np.count_nonzero(d < min(tk, cap[a])) >= expect:
+                            if np.count_nonzero(d < min(tk, cap)) >= expect:
                                 t = tk
                                 break
-                        out[b, 2 * a + side] = min(t, cap[a])
+                        out[b, 2 * a + side] = min(t, cap)
     return out
 
 
-def task_members(pos, box_lo, box_hi, nt, thick, task):
-    """Owned particles of a task and the particle images x + s L (s in {-1, 0, 1}^3) inside its
-    buffered box that it does not own: (owned indices, buffer indices, buffer shifts)."""
+def task_members(pos, box_lo, box_hi, nt, thick, task, periodic=True):
+    """Owned particles of a task and the particle images x + s L (s in {-1, 0, 1}^3 in a periodic
+    box, s = 0 in a bounded world) inside its buffered box that it does not own:
+    (owned indices, buffer indices, buffer shifts).  A bounded world is closed: its own upper
+    faces belong to it."""
     x = np.asarray(pos, np.float64)
     lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
+    hi = np.broadcast_to(np.asarray(box_hi, np.float64), 3)
+    L = hi - lo
     nt = np.asarray(nt, np.int64)
-    w = L / nt
-    idx = task_index(x, box_lo, box_hi, nt)
+    idx = task_index(x, lo, hi, nt)
     ii = np.array([task // (nt[1] * nt[2]), (task // nt[2]) % nt[1], task % nt[2]])
     t = np.asarray(thick, np.float64).reshape(-1, 6)[task]
-    blo = lo + ii * w - t[0::2]
-    bhi = lo + (ii + 1) * w + t[1::2]
+    cb = [_task_bounds(lo, hi, nt, a, ii[a]) for a in range(3)]
+    blo = np.array([cb[a][0] for a in range(3)]) - t[0::2]
+    bhi = np.array([cb[a][1] for a in range(3)]) + t[1::2]
+    if not periodic:
+        blo = np.maximum(blo, lo)
+        bhi = np.minimum(bhi, hi)
     owner = np.all(idx == ii, axis=1)
+    shifts = (-1, 0, 1) if periodic else (0,)
     buf_i, buf_s = [], []
-    for s0 in (-1, 0, 1):
-        for s1 in (-1, 0, 1):
-            for s2 in (-1, 0, 1):
+    for s0 in shifts:
+        for s1 in shifts:
+            for s2 in shifts:
                 sv = np.array([s0, s1, s2])
                 y = x + sv * L
-                inside = np.all((y >= blo) & (y < bhi), axis=1)
+                upper = (y < bhi) | ((bhi >= hi) & (y <= bhi)) if not periodic else (y < bhi)
+                inside = np.all((y >= blo) & upper, axis=1)
                 if s0 == 0 and s1 == 0 and s2 == 0:
                     inside &= ~owner
                 k = np.nonzero(inside)[0]

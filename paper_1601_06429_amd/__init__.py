@@ -46,14 +46,25 @@ class VTError(RuntimeError):
 
 class vt_item(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("n_owned", ctypes.c_int64), ("n_ghost", ctypes.c_int64),
-                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("walls", ctypes.c_int32),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class vt_border(ctypes.Structure):
+    _fields_ = [("border_factor", ctypes.c_double), ("growth", ctypes.c_double), ("n_steps", ctypes.c_int32),
+                ("max_reruns", ctypes.c_int32), ("widen", ctypes.c_double)]
 
 
 class vt_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_faces", ctypes.c_int32), ("radius_factor", ctypes.c_float),
                 ("area_eps", ctypes.c_float), ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
+
+
+def _load_cdll():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libvt.so not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    return ctypes.CDLL(LIB_PATH)
 
 
 def lib():
@@ -73,7 +84,7 @@ def lib():
 
             if torch.cuda.is_available():
                 torch.cuda.init()
-            L = ctypes.CDLL(LIB_PATH)
+            L = _load_cdll()
             P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
             L.vt_build.argtypes = [ctypes.POINTER(P), P, I32, P, ctypes.POINTER(vt_item), I32,
                                    ctypes.POINTER(vt_opts), P]
@@ -88,11 +99,17 @@ def lib():
             L.vt_sizes.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
             L.vt_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
             D3 = ctypes.POINTER(ctypes.c_double)
-            L.vt_decompose.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, ctypes.POINTER(I32), D3, I32, D3,
+            BP = ctypes.POINTER(vt_border)
+            L.vt_task_grid.argtypes = [I32, I32, I32, ctypes.POINTER(I32)]
+            L.vt_border_thresholds.argtypes = [I64, D3, D3, BP, D3]
+            L.vt_decompose.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, I32, ctypes.POINTER(I32), BP, D3,
                                        ctypes.POINTER(I64), ctypes.POINTER(I64), P]
-            L.vt_decompose_pack.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, ctypes.POINTER(I32), D3, P,
-                                            ctypes.POINTER(I32), I32, P, P, I64, ctypes.POINTER(vt_item),
+            L.vt_decompose_pack.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, I32, ctypes.POINTER(I32), D3,
+                                            P, ctypes.POINTER(I32), I32, P, P, I64, ctypes.POINTER(vt_item),
                                             ctypes.POINTER(I64), P]
+            L.vt_decomposed_build.argtypes = [ctypes.POINTER(P), P, I32, I64, D3, D3, I32, ctypes.POINTER(I32), BP,
+                                              ctypes.POINTER(vt_opts), D3, ctypes.POINTER(I64),
+                                              ctypes.POINTER(I32), P]
             L.vt_structure.argtypes = [P, P, P, I64, P, P, I64, P, P, I64, ctypes.POINTER(I64), P]
             L.vt_grid_tensor.argtypes = [P, P, I32, I32, I32, I32, P, P]
             L.vt_destroy.argtypes = [P]
@@ -101,7 +118,8 @@ def lib():
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
                       "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack",
-                      "vt_grid_sample", "vt_structure", "vt_grid_tensor"):
+                      "vt_grid_sample", "vt_structure", "vt_grid_tensor", "vt_task_grid", "vt_border_thresholds",
+                      "vt_decomposed_build"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
     return _lib
@@ -130,11 +148,13 @@ def _require_cuda(t, name):
         raise ValueError("%s must be contiguous" % name)
 
 
-def whole_box(n, box_lo, box_hi, periodic=True):
-    """Item list for a single world of n owned particles."""
+def whole_box(n, box_lo, box_hi, periodic=True, walls=0):
+    """Item list for a single world of n owned particles (``walls``: true-boundary faces of a
+    bounded world, vt_item.walls; 63 = a whole bounded world)."""
     lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
     hi = np.broadcast_to(np.asarray(box_hi, np.float64), 3)
-    return [dict(offset=0, n_owned=int(n), n_ghost=0, periodic=bool(periodic), lo=lo, hi=hi)]
+    return [dict(offset=0, n_owned=int(n), n_ghost=0, periodic=bool(periodic), lo=lo, hi=hi,
+                 walls=0 if periodic else int(walls))]
 
 
 def pack_worlds(worlds):
@@ -185,6 +205,7 @@ def _items(items):
         arr[k].n_owned = int(it["n_owned"])
         arr[k].n_ghost = int(it.get("n_ghost", 0))
         arr[k].periodic = 1 if it.get("periodic", False) else 0
+        arr[k].walls = int(it.get("walls", 0))
         for a in range(3):
             arr[k].lo[a] = float(np.broadcast_to(it["lo"], 3)[a])
             arr[k].hi[a] = float(np.broadcast_to(it["hi"], 3)[a])
@@ -394,23 +415,26 @@ class Context:
         _check(lib().vt_backward(self._ctx, _ptr(dL_dV), _ptr(g), _stream(stream)), "vt_backward")
         return g
 
-    def vt_decompose(self, pos, box_lo, box_hi, nt, thresholds, stream=None):
+    def vt_decompose(self, pos, box_lo, box_hi, nt, border_factor=1.5, periodic=True, growth=0.0, n_steps=0,
+                     stream=None):
         """AUTOBORDER thicknesses (n_tasks x 6: faces -x, +x, -y, +y, -z, +z) and the tasks'
         owned and buffer counts, as numpy arrays."""
         dt = _pos_dtype(pos)
         lo, hi, ntc = _box3(box_lo), _box3(box_hi), (ctypes.c_int32 * 3)(*[int(x) for x in nt])
-        thr = np.ascontiguousarray(thresholds, np.float64)
+        bp = _border(border_factor, growth, n_steps)
         n_tasks = int(np.prod(nt))
         thick = np.zeros(6 * n_tasks)
         n_own = np.zeros(n_tasks, np.int64)
         n_gh = np.zeros(n_tasks, np.int64)
-        _check(lib().vt_decompose(ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, ntc, _dptr(thr),
-                                  len(thr), _dptr(thick), n_own.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        _check(lib().vt_decompose(ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, int(bool(periodic)),
+                                  ntc, ctypes.byref(bp), _dptr(thick),
+                                  n_own.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   n_gh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(stream)),
                "vt_decompose")
         return thick.reshape(n_tasks, 6), n_own, n_gh
 
-    def vt_decompose_pack(self, pos, box_lo, box_hi, nt, thick, own_mask=None, tasks=None, stream=None):
+    def vt_decompose_pack(self, pos, box_lo, box_hi, nt, thick, own_mask=None, tasks=None, periodic=True,
+                          stream=None):
         """The batch of the listed tasks for vt_build: (positions float64 n x 3, int32 global ids,
         item list)."""
         import torch
@@ -428,8 +452,8 @@ class Context:
         arr = (vt_item * n_list)()
         n_out = ctypes.c_int64()
         tptr = None if tl is None else tl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        args = (ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, ntc, _dptr(th), _ptr(own_mask), tptr,
-                n_list)
+        args = (ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi, int(bool(periodic)), ntc, _dptr(th),
+                _ptr(own_mask), tptr, n_list)
         # outputs sized by the largest batch this context has packed; a larger one is sized by
         # the call that finds it too small, then packed again
         cap = self._pack_cap
@@ -450,8 +474,36 @@ class Context:
                                            _stream(stream))
         _check(code, "vt_decompose_pack")
         items = [dict(offset=arr[k].offset, n_owned=arr[k].n_owned, n_ghost=arr[k].n_ghost, periodic=False,
-                      lo=np.array(arr[k].lo[:]), hi=np.array(arr[k].hi[:])) for k in range(n_list)]
+                      walls=arr[k].walls, lo=np.array(arr[k].lo[:]), hi=np.array(arr[k].hi[:]))
+                 for k in range(n_list)]
         return out[:n_out.value], gid[:n_out.value], items
+
+    def vt_decomposed_build(self, pos, box_lo, box_hi, nt, border_factor=1.5, periodic=True, max_reruns=0,
+                            widen=0.0, growth=0.0, n_steps=0, precision=PREC_FP64, radius_factor=0.0,
+                            waves_per_cu=0, stream=None):
+        """The whole AUTOBORDER procedure in the library; afterwards vt_cells / vt_density /
+        vt_query answer in particle order.  Returns (first-pass thicknesses n_tasks x 6,
+        per-pass [tasks, particles packed, cells built, cells left incomplete])."""
+        dt = _pos_dtype(pos)
+        lo, hi, ntc = _box3(box_lo), _box3(box_hi), (ctypes.c_int32 * 3)(*[int(x) for x in nt])
+        bp = _border(border_factor, growth, n_steps, max_reruns, widen)
+        o = vt_opts()
+        o.precision = int(precision)
+        o.radius_factor = float(radius_factor)
+        o.waves_per_cu = int(waves_per_cu)
+        n_tasks = int(np.prod(nt))
+        thick = np.zeros(6 * n_tasks)
+        stats = np.zeros((16, 4), np.int64)
+        npass = ctypes.c_int32()
+        _check(lib().vt_decomposed_build(ctypes.byref(self._ctx), _ptr(pos), dt, pos.shape[0], lo, hi,
+                                         int(bool(periodic)), ntc, ctypes.byref(bp), ctypes.byref(o), _dptr(thick),
+                                         stats.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(npass),
+                                         _stream(stream)), "vt_decomposed_build")
+        no, nt_ = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().vt_sizes(self._ctx, ctypes.byref(no), ctypes.byref(nt_)), "vt_sizes")
+        self.n_owned, self.n_total = no.value, nt_.value
+        self.device = pos.device
+        return thick.reshape(n_tasks, 6), stats[:npass.value]
 
     def vt_stats(self, stream=None):
         import torch
@@ -463,138 +515,78 @@ class Context:
         return nv, np_, nt
 
 
+def _border(border_factor=1.5, growth=0.0, n_steps=0, max_reruns=0, widen=0.0):
+    bp = vt_border()
+    bp.border_factor = float(border_factor)
+    bp.growth = float(growth)
+    bp.n_steps = int(n_steps)
+    bp.max_reruns = int(max_reruns)
+    bp.widen = float(widen)
+    return bp
+
+
 def task_grid(n_task, scheme="a", axis=0):
-    """Tasks per axis for the paper's two decomposition schemes (section 2).
-
-    Scheme "a" cuts the box in halves, along x, then y, then z, and round again, until there are
-    n_task equal regions (n_task a power of two; 32 gives 4 x 4 x 2).  Scheme "b" cuts it
-    n_task times along one axis (elongated volumes).
-    """
-    n_task = int(n_task)
-    if n_task < 1:
-        raise ValueError("n_task must be positive")
-    nt = [1, 1, 1]
-    if scheme == "a":
-        if n_task & (n_task - 1):
-            raise ValueError("scheme a needs a power-of-two task count, got %d" % n_task)
-        a = 0
-        while nt[0] * nt[1] * nt[2] < n_task:
-            nt[a] *= 2
-            a = (a + 1) % 3
-    elif scheme == "b":
-        if axis not in (0, 1, 2):
-            raise ValueError("axis must be 0, 1 or 2")
-        nt[axis] = n_task
-    else:
+    """Tasks per axis for the paper's two decomposition schemes (section 2; vt_task_grid):
+    scheme "a" halves the box along x, y, z in turn until there are n_task regions, scheme "b"
+    makes n_task slabs along one axis."""
+    if scheme not in ("a", "b"):
         raise ValueError("scheme must be 'a' or 'b'")
-    return tuple(nt)
+    nt = (ctypes.c_int32 * 3)()
+    code = _host_lib().vt_task_grid(int(n_task), 0 if scheme == "a" else 1, int(axis), nt)
+    if code != VT_OK:
+        raise ValueError("no %s layout for %d tasks (axis %d)" % (scheme, n_task, axis))
+    return tuple(int(x) for x in nt)
 
 
-def autoborder_thresholds(n, box_lo, box_hi, border_factor=1.5, growth=1.1, steps=48):
-    """Buffer thicknesses tried by AUTOBORDER: border_factor times the mean inter-particle
-    distance (V / n)^(1/3), grown by the factor ``growth`` per step."""
-    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    s = (float(np.prod(L)) / n) ** (1.0 / 3.0)
-    return border_factor * s * growth ** np.arange(steps, dtype=np.float64)
+def border_thresholds(n, box_lo, box_hi, border_factor=1.5, growth=0.0, n_steps=0):
+    """The AUTOBORDER thicknesses the library tries (vt_border_thresholds; host only)."""
+    bp = _border(border_factor, growth, n_steps)
+    k = bp.n_steps or 48
+    out = np.zeros(k)
+    _check(_host_lib().vt_border_thresholds(int(n), _box3(box_lo), _box3(box_hi), ctypes.byref(bp), _dptr(out)),
+           "vt_border_thresholds")
+    return out
 
 
-def task_limits(box_lo, box_hi, nt):
-    """Largest buffer thickness per axis (a buffered task spans less than one period)."""
-    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    nt = np.asarray(nt)
-    w = L / nt
-    return np.where(nt >= 2, 0.5 * (L - w), 0.5 * L) * (1.0 - 1e-12)
+_hlib = None
 
 
-def owner_tasks(pos_np, box_lo, box_hi, nt):
-    """Owner task of every particle (the library's rule: cell index floor((x - lo) / w))."""
-    lo = np.broadcast_to(np.asarray(box_lo, np.float64), 3)
-    L = np.broadcast_to(np.asarray(box_hi, np.float64), 3) - lo
-    nt = np.asarray(nt)
-    w = L / nt
-    i = np.clip(np.floor((np.asarray(pos_np, np.float64) - lo) / w).astype(np.int64), 0, nt - 1)
-    return (i[:, 0] * nt[1] + i[:, 1]) * nt[2] + i[:, 2]
+def _host_lib():
+    """libvt for its host-only calls (vt_task_grid, vt_border_thresholds): no device is needed."""
+    global _hlib
+    with _lock:
+        if _hlib is None:
+            L = _load_cdll()
+            I32, I64 = ctypes.c_int32, ctypes.c_int64
+            D3 = ctypes.POINTER(ctypes.c_double)
+            L.vt_task_grid.argtypes = [I32, I32, I32, ctypes.POINTER(I32)]
+            L.vt_task_grid.restype = I32
+            L.vt_border_thresholds.argtypes = [I64, D3, D3, ctypes.POINTER(vt_border), D3]
+            L.vt_border_thresholds.restype = I32
+            _hlib = L
+    return _hlib
 
 
-def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, growth=1.1, steps=48, reruns=3, widen=2.0,
-                     ctx=None, **build_opts):
-    """Tessellate a periodic box as nt[0] x nt[1] x nt[2] tasks with AUTOBORDER buffers, all
-    tasks in one batched build; cells still incomplete are built again, owned alone, with their
-    tasks' buffers widened ``widen`` times (up to ``reruns`` passes).  An integer nt is a task
-    count split by scheme (a) (``task_grid``).
+def decomposed_build(pos, box_lo, box_hi, nt, border_factor=1.5, periodic=True, ctx=None, **build_opts):
+    """Tessellate a periodic box or a bounded world as nt[0] x nt[1] x nt[2] tasks with AUTOBORDER
+    buffers, in the library (vt_decomposed_build): all tasks in one batched build, cells left
+    incomplete built again with widened buffers.  An integer nt is a task count split by scheme (a).
 
-    Returns a dict with per-particle ``volume`` (numpy), ``status`` (numpy uint8: the last pass
-    that computed the cell), the neighbour CSR ``nbr_off``/``nbr_ids`` in particle order (numpy),
-    the thicknesses ``thick`` (n_tasks x 6) of the first pass, per-pass ``passes`` records and the
-    ``plan`` of each pass (thicknesses, owner mask, task list) to replay it.
+    Returns a dict with per-particle ``volume``, ``status`` and the neighbour CSR
+    ``nbr_off``/``nbr_ids`` in particle order (numpy), the first pass's thicknesses ``thick``
+    (n_tasks x 6) and per-pass records ``passes``.
     """
-    import torch
-
-    n = pos.shape[0]
     if np.ndim(nt) == 0:
         nt = task_grid(nt, "a")
     nt = tuple(int(x) for x in nt)
     ctx = ctx or Context()
-    thr = autoborder_thresholds(n, box_lo, box_hi, border_factor, growth, steps)
-    thick, n_own, n_gh = ctx.vt_decompose(pos, box_lo, box_hi, nt, thr)
-    tmax = task_limits(box_lo, box_hi, nt)
-    vol = np.full(n, np.nan)
-    status = np.full(n, 255, np.uint8)
-    last = np.full(n, -1, np.int64)     # pass that computed the cell
-    row = np.full(n, -1, np.int64)      # its row there
-    csr = []                            # per pass: (nbr_off, nbr_ids)
-    passes, plan = [], []
-    cur = thick.copy()
-    mask, tasks = None, None
-    for rnd in range(reruns + 1):
-        plan.append((cur.copy(), mask, tasks))
-        bpos, gid, items = ctx.vt_decompose_pack(pos, box_lo, box_hi, nt, cur, own_mask=mask, tasks=tasks)
-        bctx = Context().vt_build(bpos, items, global_id=gid, **build_opts)
-        cells = bctx.vt_cells()
-        g = gid.cpu().numpy()
-        own_gid = np.concatenate([g[it["offset"]:it["offset"] + it["n_owned"]] for it in items])
-        v = cells.volume.cpu().numpy()
-        st = cells.status.cpu().numpy()
-        off = cells.nbr_off.cpu().numpy()
-        ids = cells.nbr_ids.cpu().numpy()
-        vol[own_gid] = v
-        status[own_gid] = st
-        last[own_gid] = rnd
-        row[own_gid] = np.arange(len(own_gid))
-        csr.append((off, ids))
-        inc = own_gid[(st & CELL_INCOMPLETE) != 0]
-        passes.append(dict(tasks=len(items), particles=int(bpos.shape[0]), owned=int(len(own_gid)),
-                           incomplete=int(len(inc))))
-        del bctx, cells
-        if len(inc) == 0 or rnd == reruns:
-            break
-        # the incomplete cells again, owned alone, with their tasks' buffers widened
-        own = owner_tasks(pos.cpu().numpy(), box_lo, box_hi, nt)
-        tl = np.unique(own[inc]).astype(np.int32)
-        m = np.zeros(n, np.uint8)
-        m[inc] = 1
-        mask = torch.from_numpy(m).to(pos.device)
-        tasks = tl
-        cur = cur.copy()
-        cur[tl] = np.minimum(cur[tl] * widen, np.repeat(tmax, 2)[None, :])
-    # neighbour rows in particle order, each from the last pass that computed the cell
-    cnt = np.zeros(n, np.int64)
-    for k, (off, _) in enumerate(csr):
-        sel = last == k
-        cnt[sel] = off[row[sel] + 1] - off[row[sel]]
-    nbr_off = np.zeros(n + 1, np.int64)
-    nbr_off[1:] = np.cumsum(cnt)
-    nbr_ids = np.zeros(int(nbr_off[-1]), np.int32)
-    for k, (off, ids) in enumerate(csr):
-        p = np.nonzero(last == k)[0]
-        if len(p) == 0:
-            continue
-        ln = cnt[p]
-        src = np.repeat(off[row[p]] - np.cumsum(ln) + ln, ln) + np.arange(ln.sum())
-        dst = np.repeat(nbr_off[p] - np.cumsum(ln) + ln, ln) + np.arange(ln.sum())
-        nbr_ids[dst] = ids[src]
-    return dict(volume=vol, status=status, nbr_off=nbr_off, nbr_ids=nbr_ids, thick=thick, n_owned=n_own,
-                n_ghost=n_gh, passes=passes, plan=plan)
+    thick, stats = ctx.vt_decomposed_build(pos, box_lo, box_hi, nt, border_factor=border_factor,
+                                           periodic=periodic, **build_opts)
+    cells = ctx.vt_cells()
+    passes = [dict(tasks=int(r[0]), particles=int(r[1]), owned=int(r[2]), incomplete=int(r[3])) for r in stats]
+    return dict(volume=cells.volume.cpu().numpy(), status=cells.status.cpu().numpy(),
+                nbr_off=cells.nbr_off.cpu().numpy(), nbr_ids=cells.nbr_ids.cpu().numpy(), thick=thick,
+                passes=passes, ctx=ctx)
 
 
 def tessellate(pos, box_lo, box_hi, periodic=True, precision=PREC_FP64, want_faces=False, **kw):

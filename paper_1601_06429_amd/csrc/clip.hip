@@ -744,14 +744,14 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         const double amin = (double)(A.area_eps * exp2f(log2f((float)fabs(V)) * (2.0f / 3.0f)));
         // facets of positive area generated by particles -> neighbour rows, ascending global id
         uint64_t keys[VPL];
-        bool wall = false;
+        uint32_t wall = 0;  // walls (bit f for tag -1 - f) among this lane's facets
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
             const int f = r * 64 + lane;
             keys[r] = ~0ull;
             if ((P.fa[r] & mybit) && area_l[r] > amin) {
                 int32_t tag = S.P.ptag[f];
-                if (tag < 0) wall = true;
+                if (tag < 0) wall |= 1u << ((-1 - tag) & 7);
                 else keys[r] = ((uint64_t)(uint32_t)A.sgid[tag] << 9) | (uint64_t)f;
             }
         }
@@ -774,7 +774,10 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 }
             }
         }
-        const bool any_wall = __ballot(wall) != 0;
+        uint32_t wall_mask = 0;
+        for (int f = 0; f < 6; ++f)
+            if (__ballot((wall >> f) & 1u) != 0) wall_mask |= 1u << f;
+        const bool any_wall = wall_mask != 0;
         // topology record for the grid deposit, which then rebuilds the cell without clipping:
         // the tags of the faces in slot order, then each vertex's face triple as ranks in that
         // order (the triple's order, which fixes the orientation, is kept)
@@ -806,9 +809,13 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     st |= VT_CELL_FAILED;
                 }
             } else {
-                for (int a = 0; a < 3; ++a)
-                    if (xs[a] - 2.0 * Rfin < it.lo[a] || xs[a] + 2.0 * Rfin > it.lo[a] + it.L[a]) incomplete = true;
-                if (any_wall) incomplete = true;
+                // only cut walls (not the world's true boundaries) make a cell incomplete
+                const uint32_t cut = ~(uint32_t)it.walls;
+                for (int a = 0; a < 3; ++a) {
+                    if (((cut >> (2 * a)) & 1u) && xs[a] - 2.0 * Rfin < it.lo[a]) incomplete = true;
+                    if (((cut >> (2 * a + 1)) & 1u) && xs[a] + 2.0 * Rfin > it.lo[a] + it.L[a]) incomplete = true;
+                }
+                if (wall_mask & cut) incomplete = true;
             }
             if (incomplete) {
                 st |= VT_CELL_INCOMPLETE;

@@ -389,11 +389,22 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
             // seed position in the grid frame; grid line m of axis a lies at m h + del - g0 from the seed
             const double g0[3] = {xs[0] - it.lo[0], xs[1] - it.lo[1], xs[2] - it.lo[2]};
             int64_t i0[3], i1[3];
+            bool sane = true;
             for (int a = 0; a < 3; ++a) {
                 mn[a] = uni_d(wave_min(mn[a]));
                 mx[a] = uni_d(wave_max(mx[a]));
-                i0[a] = (int64_t)floor((g0[a] + mn[a] - del[a]) * ih[a]);
-                i1[a] = (int64_t)floor((g0[a] + mx[a] - del[a]) * ih[a]);
+                // a cell spans less than the box (2R < L/2 when periodic): its voxel range is at most
+                // the grid's; anything else (a vertex not finite, or far away) is a broken cell, and
+                // it must not drive the loops below
+                const double lo_ = (g0[a] + mn[a] - del[a]) * ih[a], hi_ = (g0[a] + mx[a] - del[a]) * ih[a];
+                sane = sane && isfinite(lo_) && isfinite(hi_) && hi_ >= lo_ && hi_ - lo_ <= (double)dims[a] + 1.0 &&
+                       fabs(lo_) < 1e15 && fabs(hi_) < 1e15;
+                i0[a] = sane ? (int64_t)floor(lo_) : 0;
+                i1[a] = sane ? (int64_t)floor(hi_) : 0;
+            }
+            if (!sane) {
+                if (lane == 0) atomicOr(&A.counters[CTR_STATUS], VT_DEV_TOPOLOGY);
+                continue;
             }
             if (i0[0] == i1[0] && i0[1] == i1[1] && i0[2] == i1[2]) {
                 if (lane == 0) {
@@ -624,7 +635,9 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
                         const double G = hs * Rg.G;
                         if (pi == 0) {
                             if (Rg.A != 0.0) {
-                                for (int64_t i = i0[0]; i < g.mm; ++i) emit(i, g.jj, g.kk, hs * h[0] * Rg.A);
+                                // full voxels below the face's x minimum, within the cell's own range
+                                const int64_t iend = g.mm < i0[0] + bx ? g.mm : i0[0] + bx;
+                                for (int64_t i = i0[0]; i < iend; ++i) emit(i, g.jj, g.kk, hs * h[0] * Rg.A);
                                 emit(g.mm, g.jj, g.kk, G);
                             }
                         } else {

@@ -6,7 +6,11 @@
 // and, per vertex, the ranks of its three faces.  Every face plane follows from its tag and
 // every vertex is the intersection of its three planes, computed in the same order as the clip
 // kernel computes it, so the rebuilt vertices are the clip kernel's own.  A cell without a
-// well-formed record is clipped again from its facet list.
+// record (cells of the large clip kernel, cells of more than VT_TOPO_FACES faces) is clipped
+// again from its facet list.  A record that exists but fails a check (a tag or rank out of
+// range, repeated ranks, a vertex that is not finite) can only come from a fault in the clip
+// kernel: it is counted (CTR_REC_REJECT), the device status takes VT_DEV_TOPOLOGY so that
+// vt_query reports it, and the cell is still rebuilt from its facets.
 #pragma once
 #include "poly.h"
 
@@ -54,6 +58,7 @@ __device__ __forceinline__ int rebuild_cell(const CellSrc &R, const DevItem &it,
     bool bad = false, over = false, have = false;
     if constexpr (!RETRY && VPL == 1) {
         const int nf = R.cnf[c], nv = R.cnv[c];
+        bool rejected = nf != 0;  // a record exists; cleared once it passes every check
         if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64) {
             const int64_t tb = (int64_t)c * VT_TOPO_STRIDE;
             bool ok = true;
@@ -118,9 +123,14 @@ __device__ __forceinline__ int rebuild_cell(const CellSrc &R, const DevItem &it,
                     P.alive[0] = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
                     P.fa[0] = (1ull << nf) - 1ull;
                     have = true;
+                    rejected = false;
                 }
                 wave_sync();
             }
+        }
+        if (rejected && lane == 0) {
+            atomicAdd(&R.counters[CTR_REC_REJECT], 1u);
+            atomicOr(&R.counters[CTR_STATUS], VT_DEV_TOPOLOGY);
         }
     }
     // otherwise from the facets: loaded lane-parallel; the normal kernel applies them nearest

@@ -112,6 +112,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
     for (int b = 0; b < n_items; ++b) {
         const vt_item &it = items[b];
         if (it.offset != n_total || it.n_owned < 1 || it.n_ghost < 0) return VT_ERR_ARG;
+        if (it.walls < 0 || it.walls > 63 || (it.periodic && it.walls != 0)) return VT_ERR_ARG;
         for (int a = 0; a < 3; ++a)
             if (!(it.hi[a] > it.lo[a])) return VT_ERR_ARG;
         if (it.periodic) {
@@ -141,6 +142,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
     c->n_owned = n_owned;
     c->n_items = n_items;
     c->built = false;
+    c->decomposed = false;
     c->faces_valid = false;
     int ib = 0;
     while ((1 << ib) < n_items) ++ib;
@@ -167,6 +169,8 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
         d.T = table_level(d.count);
         d.tab_off = tab_total;
         d.periodic = it.periodic ? 1 : 0;
+        d.walls = it.periodic ? 0 : it.walls;
+        d.pad = 0;
         tab_total += (1ll << (3 * d.T)) + 1;
         owned_base += it.n_owned;
     }
@@ -248,18 +252,23 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
 
 vt_status vt_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
                    uint8_t *cell_status, void *stream) {
-    if (!c || !c->built) return VT_ERR_STATE;
+    if (!c || !(c->built || c->decomposed)) return VT_ERR_STATE;
     if (!volume || !nbr_off || (!nbr_ids && nbr_cap > 0) || nbr_cap < 0) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    if (c->decomposed) return vt_dres_cells(c, volume, nbr_off, nbr_ids, nbr_cap, cell_status);
     clear_stale_error();
     TRY(vt_launch_cells(c, volume, nbr_off, nbr_ids, nbr_cap, cell_status));
     return VT_OK;
 }
 
 vt_status vt_density(vt_ctx *c, const void *mass, vt_dtype dtype, double *rho, void *stream) {
-    if (!c || !c->built) return VT_ERR_STATE;
+    if (!c || !(c->built || c->decomposed)) return VT_ERR_STATE;
     if (!rho || (dtype != VT_F32 && dtype != VT_F64)) return VT_ERR_ARG;
     c->stream = (hipStream_t)stream;
+    if (c->decomposed) {
+        clear_stale_error();
+        return vt_dres_density(c, mass, dtype, rho);
+    }
     clear_stale_error();
     TRY(vt_launch_density(c, mass, dtype, rho));
     return VT_OK;
@@ -349,12 +358,19 @@ vt_status vt_timings(vt_ctx *c, float ms[3]) {
 
 vt_status vt_sizes(vt_ctx *c, int64_t *n_owned_total, int64_t *n_total) {
     if (!c) return VT_ERR_ARG;
-    if (n_owned_total) *n_owned_total = c->n_owned;
-    if (n_total) *n_total = c->n_total;
+    if (n_owned_total) *n_owned_total = c->decomposed ? c->dres_n : c->n_owned;
+    if (n_total) *n_total = c->decomposed ? c->dres_n : c->n_total;
     return VT_OK;
 }
 
 vt_status vt_query(vt_ctx *c, int64_t *nnz, int64_t *n_retried, int64_t *n_incomplete) {
+    if (c && c->decomposed) {
+        TRY(hipStreamSynchronize(c->stream));
+        if (nnz) *nnz = c->dres_nnz;
+        if (n_retried) *n_retried = c->dres_retried;
+        if (n_incomplete) *n_incomplete = c->dres_incomplete;
+        return c->dres_capfail ? VT_ERR_CAPACITY : c->dres_status;
+    }
     if (!c || !c->built) return VT_ERR_STATE;
     TRY(hipStreamSynchronize(c->stream));
     TRY(hipMemcpy(c->h_counters, c->counters, sizeof(uint32_t) * CTR_COUNT, hipMemcpyDeviceToHost));
@@ -364,7 +380,8 @@ vt_status vt_query(vt_ctx *c, int64_t *nnz, int64_t *n_retried, int64_t *n_incom
     if (n_incomplete) *n_incomplete = h[CTR_INCOMPLETE];
     uint32_t st = h[CTR_STATUS];
     if (getenv("VT_DEBUG") && (st || h[CTR_DEBUG]))
-        fprintf(stderr, "libvt: device status 0x%x, debug 0x%x, queue %u\n", st, h[CTR_DEBUG], h[CTR_QUEUE]);
+        fprintf(stderr, "libvt: device status 0x%x, debug 0x%x, queue %u, rejected records %u\n", st, h[CTR_DEBUG],
+                h[CTR_QUEUE], h[CTR_REC_REJECT]);
     if (st & VT_DEV_DUPLICATE) return VT_ERR_DUPLICATE;  // the root cause of any later failure
     if (st & VT_DEV_TOPOLOGY) return VT_ERR_TOPOLOGY;
     if (st & VT_DEV_BOX_TOO_SMALL) return VT_ERR_BOX_TOO_SMALL;

@@ -14,6 +14,7 @@
 #define VT_FSTRIDE_BIG 136         // facet slots per cell, large kernel (F <= 130 when V <= 256)
 #define VT_TOPO_FACES 40           // face-table words of a topology record (F <= 34 when V <= 64)
 #define VT_TOPO_STRIDE 104         // topology record: VT_TOPO_FACES face tags + 64 vertex triples
+#define VT_DEC_MAX_PASSES 16       // vt_decomposed_build: at most 15 re-runs
 
 // device status word bits
 #define VT_DEV_DUPLICATE 1u
@@ -35,7 +36,8 @@
 #define CTR_DEBUG 9        // bit k set: a clip in the grid kernel returned -k (diagnostics)
 #define CTR_GRID_Q 10      // grid deposit: cells handed from the normal to the large kernel
 #define CTR_STRUCT_Q 11    // structure output: cells handed from the normal to the large kernel
-#define CTR_COUNT 12
+#define CTR_REC_REJECT 12  // topology records that failed their checks (a clip-kernel fault; 0 expected)
+#define CTR_COUNT 13
 
 // per-item description on the device
 struct DevItem {
@@ -50,6 +52,8 @@ struct DevItem {
     int64_t tab_off;    // offset of the level table in tab[]
     int32_t T;          // table level
     int32_t periodic;
+    int32_t walls;      // bounded: faces that are true boundaries (vt_item.walls)
+    int32_t pad;
 };
 
 // ---------------------------------------------------------------- context
@@ -113,6 +117,35 @@ struct vt_ctx {
     int32_t *dec_tpos = nullptr;   // task -> position in the list, -1 if not listed
     double *dec_thr = nullptr;     // thresholds (64)
     int64_t cap_dec_tasks = 0, cap_dec_hist = 0;
+    // whole decomposed build (decomp.hip): results in particle order, kept for vt_cells,
+    // vt_density and vt_query; per pass, the neighbour CSR of the cells it computed
+    bool decomposed = false;
+    int64_t dres_n = 0, dres_nnz = 0, dres_retried = 0, dres_incomplete = 0;
+    vt_status dres_status = VT_OK;
+    bool dres_capfail = false;
+    double *dres_vol = nullptr;
+    uint8_t *dres_stat = nullptr;
+    int64_t *dres_off = nullptr;
+    int32_t *dres_ids = nullptr;
+    int32_t *dres_last = nullptr;   // pass that computed the particle's cell
+    int32_t *dres_row = nullptr;    // its row in that pass
+    uint8_t *dres_mask = nullptr;   // owner mask of the next pass
+    int32_t *dres_tflag = nullptr;  // per task: owns a cell left incomplete
+    int64_t *dres_cnt = nullptr;
+    int64_t *dres_scan = nullptr;
+    int64_t cap_dres = 0, cap_dres_ids = 0, cap_dres_tasks = 0;
+    double *dpack_pos = nullptr;    // the batch of a pass
+    int32_t *dpack_gid = nullptr;
+    int64_t cap_dpack = 0;
+    int64_t *dpack_items = nullptr; // per listed task: first output row, batch offset, owned count
+    int64_t cap_dpack_items = 0;
+    double *dpass_vol = nullptr;    // one pass's cell outputs in its row order
+    uint8_t *dpass_stat = nullptr;
+    int64_t cap_dpass_rows = 0;
+    int64_t *dpass_off[VT_DEC_MAX_PASSES] = {};
+    int32_t *dpass_ids[VT_DEC_MAX_PASSES] = {};
+    int64_t dpass_cap_rows[VT_DEC_MAX_PASSES] = {}, dpass_cap_ids[VT_DEC_MAX_PASSES] = {};
+    vt_ctx *dchild = nullptr;       // context of the passes' builds
     // nearest-particle sampling: per sample point, the nearest particle (sorted index)
     int32_t *samp_fine = nullptr;
     int64_t cap_samp = 0;
@@ -149,6 +182,9 @@ hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 
 int64_t vt_scan_tmp_elems(int64_t n);
 void vt_dec_free(vt_ctx *c);
+vt_status vt_dres_cells(vt_ctx *c, double *volume, int64_t *nbr_off, int32_t *nbr_ids, int64_t nbr_cap,
+                        uint8_t *cell_status);
+vt_status vt_dres_density(vt_ctx *c, const void *mass, vt_dtype dt, double *rho);
 hipError_t vt_launch_structure(vt_ctx *c, int64_t *vert_off, double *verts, int64_t vert_cap, int64_t *face_off,
                                int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert,
                                int64_t loop_cap, int64_t sizes[3], bool *fits);

@@ -19,6 +19,8 @@ Workloads (seeds in SEEDS):
      density and mix, each with a ghost buffer of 3 mean spacings.
   diff262k          262,144 points, the clustered mix scaled to the periodic unit cube, plus a
      smooth sinusoidal target density for a density-matching loss.
+  survey_slab       262,144 points, the clustered mix in a bounded 10 x 1 x 1 box (an elongated
+     survey-like volume for the slab decomposition), FP32.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ import numpy as np
 SEED_BASE = 20160126
 # one seed per workload (kept stable so that stored results stay comparable)
 SEEDS = {"uniform4096": SEED_BASE + 1, "clustered2m": SEED_BASE + 2, "lattice_halos16m": SEED_BASE + 3,
-         "batched64": SEED_BASE + 4, "diff262k": SEED_BASE + 5}
+         "batched64": SEED_BASE + 4, "diff262k": SEED_BASE + 5, "survey_slab": SEED_BASE + 6}
 
 
 def rng_for(name: str) -> np.random.Generator:
@@ -298,6 +300,33 @@ def diff262k(n=262_144):
     info.update({"target_lambda": lam, "target_phase": phi, "target_amplitude": 0.5, "fd_rows":
                  np.sort(rng.choice(n, 512, replace=False))})
     return Workload("diff-262k-fp32", p, np.ones(n), np.zeros(3), np.ones(3), True, None, info)
+
+
+def survey_slab(n=262_144, sides=(10.0, 1.0, 1.0)):
+    """A bounded, elongated world (the survey slices and cones the paper's slab decomposition is
+    meant for): the clustered mix (half uniform background, half NFW-like halos with radii scaled to
+    the mean spacing like diff262k) in the non-periodic box [0, sides], FP32.  Halo points that fall
+    outside the box are replaced by background points, so the set holds exactly n points."""
+    rng = rng_for("survey_slab")
+    hi = np.asarray(sides, np.float64)
+    s = float(np.cbrt(np.prod(hi) / n))
+    scale = s / (100.0 / 2_097_152 ** (1.0 / 3.0))
+    n_halo = max(1, int(round(200 * n / 2_097_152)))
+    n_halo_pts = n // 2
+    masses = 10.0 ** rng.uniform(0.0, 2.0, n_halo)
+    counts = largest_remainder(masses, n_halo_pts)
+    centres = rng.random((n_halo, 3)) * hi
+    radii = rng.uniform(0.5 * scale, 3.0 * scale, n_halo)
+    conc = rng.uniform(5.0, 15.0, n_halo)
+    halos = halo_points(rng, counts, centres, radii, conc).astype(np.float32)
+    halos = halos[np.all((halos >= 0) & (halos < hi), axis=1)]
+    bg = (rng.random((n - len(halos), 3)) * hi).astype(np.float32)
+    p = np.concatenate([bg, halos])
+    p = np.minimum(p, np.nextafter(hi.astype(np.float32), np.float32(0)))
+    p = redraw_duplicates(rng, p, np.zeros(3), hi, np.float32)
+    p = p[rng.permutation(n)]
+    return Workload("survey-slab-262k-fp32", p, np.ones(n), np.zeros(3), hi, False, None,
+                    {"halo_counts": counts, "halo_centres": centres, "halo_radii": radii})
 
 
 def target_density(x, lam, phi, amplitude, mean_density):

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -91,3 +93,53 @@ def test_task_grid_schemes():
         task_grid(12)              # scheme (a) needs a power of two
     with pytest.raises(ValueError):
         task_grid(4, "c")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvt.so not built")
+def test_border_thresholds_reproduce_the_papers_worked_example():
+    """Section 2: BORDERFACTOR 1.5 with an inter-particle distance of 1.58 computed from the whole
+    input gives a 2.37 buffer.  The library's own thickness schedule (the one vt_decompose uses)
+    for 1000 particles in a cube of side 15.8, whose mean spacing is 1.58."""
+    import json
+
+    import paper_1601_06429_amd as vt
+
+    with open(os.path.join(ROOT, "tests", "golden", "ghost_width.json")) as f:
+        ex = json.load(f)
+    t = vt.border_thresholds(1000, 0.0, 15.8, border_factor=ex["border_factor"])
+    assert round(t[0], ex["printed_decimals"]) == ex["buffer_thickness"]
+    # and the growth: 48 thicknesses by default, each 1.1 times the one before
+    assert len(t) == 48
+    np.testing.assert_allclose(t[1:] / t[:-1], 1.1, rtol=1e-14)
+    # the spacing comes from the world's volume: a 4 x 1 x 1 slab of 4000 particles has spacing 0.1
+    t = vt.border_thresholds(4000, 0.0, [4.0, 1.0, 1.0], border_factor=1.5, n_steps=3, growth=1.5)
+    np.testing.assert_allclose(t, [0.15, 0.225, 0.3375], rtol=1e-14)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvt.so not built")
+def test_decomposition_argument_errors():
+    import paper_1601_06429_amd as vt
+
+    L = vt.lib()
+    ctx = ctypes.c_void_p(None)
+    lo, hi = vt._box3(0.0), vt._box3(1.0)
+    nt = (ctypes.c_int32 * 3)(2, 2, 2)
+    thick = np.zeros(48)
+    bad = vt._border(border_factor=-1.0)
+    ok = vt._border()
+    fake = ctypes.c_void_p(16)
+    assert L.vt_decompose(ctypes.byref(ctx), fake, vt.VT_F32, 100, lo, hi, 1, nt, ctypes.byref(bad),
+                          vt._dptr(thick), None, None, None) == 1
+    assert L.vt_decomposed_build(ctypes.byref(ctx), fake, vt.VT_F32, 100, lo, hi, 1, nt, ctypes.byref(bad),
+                                 None, None, None, None, None) == 1
+    zero_nt = (ctypes.c_int32 * 3)(0, 1, 1)
+    assert L.vt_decompose(ctypes.byref(ctx), fake, vt.VT_F32, 100, lo, hi, 1, zero_nt, ctypes.byref(ok),
+                          vt._dptr(thick), None, None, None) == 1
+    # a bounded world's exterior face takes no buffer: a positive thickness there is rejected
+    th = np.zeros(48)
+    th[0] = 0.1                      # face -x of task 0 lies on the world's -x face
+    items = (vt.vt_item * 8)()
+    n_out = ctypes.c_int64()
+    assert L.vt_decompose_pack(ctypes.byref(ctx), fake, vt.VT_F32, 100, lo, hi, 0, nt, vt._dptr(th), None, None,
+                               8, None, None, 0, items, ctypes.byref(n_out), None) == 1
+    assert ctx.value is None         # nothing was created or enqueued

@@ -1,10 +1,19 @@
 """GPU checks at the full sizes of the benchmark's workloads.
 
-* lattice+halos 16M (FP32, mixed and FP64 paths): sampled cells against the oracle, plus
+Reference values come from the oracle only: brute force over all particles where that takes
+seconds, otherwise ``oracle.local_cells`` (each cell in a ball around its particle, widened until
+the security radius proves it; pinned against the brute force in the CPU tests).
+
+* clustered 2M (the benchmark's workload), both precisions: 4096 seeded cells plus every cell the
+  large clip kernel computed, against the oracle: neighbour lists bit-exact, volumes and densities
+  within 1e-12 (FP64) / 2e-5 (mixed); density gradients of 512 seeded and the retried cells within
+  the same bars, scaled by max(|grad|, rho / V^(1/3));
+* lattice+halos 16M (FP32, mixed and FP64 paths): 4096 sampled cells against the oracle, plus
   volume conservation over the whole box;
 * clustered 2M at 256^3 (the benchmark's deposit): a field that is zero except on 96 sampled
   cells (random ones and cells the large kernels handle), every voxel against the oracle's
-  exact overlaps of those cells;
+  exact overlaps of those cells; and a unit field over every cell, every voxel 1 and the mass
+  conserved; no topology record may be rejected;
 * clustered 2M as 4 x 4 x 4 tasks with AUTOBORDER buffers (one batched build, incomplete cells
   re-run with wider buffers): neighbour lists identical to the whole-box build, volumes within
   1e-12;
@@ -13,14 +22,12 @@
 * clustered 2M deposit at 256^3: its tidal tensor against the oracle's discrete-Fourier
   reference, its trace against the density contrast;
 * clustered 2M full structure: every cell's face ids against its neighbour list, its volume
-  by the divergence theorem over its face loops, Euler's formula; 32 sampled cells (the eight
-  largest among them) against the oracle's structure;
+  by the divergence theorem over its face loops, Euler's formula on every cell; 32 sampled
+  cells (the eight largest among them) against the oracle's structure;
 * diff262k: the adjoint gradient of a density-matching loss at full size against central
-  finite differences (h = 1e-6, FP64) on the workload's 512 sampled particles.  Each
-  perturbed loss is evaluated exactly on a small bounded world around the moved particle
-  (its own cell and its neighbours' cells as owned cells, the surrounding particles as
-  buffer); all 3072 worlds go through one batched build, and every owned cell of every
-  world must be complete.
+  finite differences (h = 1e-6, FP64) of the oracle's own volumes on the workload's 512 sampled
+  particles; rows where a neighbour set changes within +-h (topology events, where the volume is
+  not twice differentiable) are counted and excluded from the 1e-6 bar.
 """
 import math
 
@@ -33,13 +40,32 @@ from paper_1601_06429_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
+TOL = {0: 1e-12, 1: 2e-5}
+
+
 @pytest.fixture(scope="module")
 def lattice16m():
     return wl.lattice_halos16m()
 
 
+@pytest.fixture(scope="module")
+def lattice16m_tree(lattice16m):
+    return cKDTree(lattice16m.pos.astype(np.float64), boxsize=1.0)
+
+
+@pytest.fixture(scope="module")
+def clustered2m():
+    return wl.clustered2m()
+
+
+@pytest.fixture(scope="module")
+def clustered2m_tree(clustered2m):
+    w = clustered2m
+    return cKDTree(w.pos.astype(np.float64) - w.box_lo, boxsize=w.box_len)
+
+
 @pytest.mark.parametrize("precision", [1, 0])
-def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, precision):
+def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, lattice16m_tree, precision):
     w = lattice16m
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision)
@@ -50,15 +76,76 @@ def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, precision
     assert abs(vol.sum() - 1.0) <= 1e-12
     off = cells.nbr_off.cpu().numpy()
     ids = cells.nbr_ids.cpu().numpy()
-    rng = np.random.default_rng(3003)
-    sample = np.sort(rng.choice(w.n, 256, replace=False))
-    ref = oracle.cells(w.pos.astype(np.float64), w.box_lo, w.box_hi, query=sample)
-    tol = 1e-12 if precision == 0 else 2e-5
-    for q, i in enumerate(sample):
-        assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
-        assert abs(vol[i] - ref.volume[q]) <= tol * ref.volume[q], i
     del ctx, cells, t
     torch_cuda.cuda.empty_cache()
+    rng = np.random.default_rng(3003)
+    sample = np.sort(rng.choice(w.n, 4096, replace=False))
+    ref = oracle.local_cells(w.pos.astype(np.float64), w.box_lo, w.box_hi, sample, tree=lattice16m_tree)
+    worst = 0.0
+    for q, i in enumerate(sample):
+        assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
+        worst = max(worst, abs(vol[i] - ref.volume[q]) / ref.volume[q])
+    print("lattice+halos 16M, precision %d: 4096 cells, worst volume error %.2e" % (precision, worst))
+    assert worst <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_clustered2m_cells_and_gradients_against_oracle(vt, torch_cuda, oracle, clustered2m, clustered2m_tree,
+                                                        precision):
+    """The benchmark's workload: 4096 seeded cells and every cell of the large clip kernel
+    (neighbours, volumes, densities), and the density gradients of 512 seeded and all retried
+    cells, against the oracle."""
+    T = torch_cuda
+    w = clustered2m
+    n = w.n
+    ctx = vt.Context().vt_build(T.from_numpy(w.pos).cuda(), vt.whole_box(n, w.box_lo, w.box_hi), precision=precision)
+    code, nnz, n_retried, inc = ctx.vt_query()
+    assert code == 0
+    cells = ctx.vt_cells()
+    m = np.random.default_rng(8008).uniform(0.5, 2.0, n)
+    rho = ctx.vt_density(T.from_numpy(m).cuda())
+    grad = ctx.vt_gradient(rho).cpu().numpy()
+    assert ctx.vt_query()[0] == 0
+    vol = cells.volume.cpu().numpy()
+    off = cells.nbr_off.cpu().numpy()
+    ids = cells.nbr_ids.cpu().numpy()
+    st = cells.status.cpu().numpy()
+    rho = rho.cpu().numpy()
+    del ctx, cells
+    T.cuda.empty_cache()
+    retried = np.nonzero(st & 2)[0]
+    assert len(retried) == n_retried and n_retried > 0
+    rng = np.random.default_rng(9009)
+    rows = np.unique(np.concatenate([rng.choice(n, 4096, replace=False), retried]))
+    p64 = w.pos.astype(np.float64)
+    ref = oracle.local_cells(p64, w.box_lo, w.box_hi, rows, tree=clustered2m_tree)
+    vworst = dworst = 0.0
+    for q, i in enumerate(rows):
+        assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
+        vworst = max(vworst, abs(vol[i] - ref.volume[q]) / ref.volume[q])
+        dref = m[i] / ref.volume[q]
+        dworst = max(dworst, abs(rho[i] - dref) / dref)
+    print("clustered 2M, precision %d: %d cells (%d retried), worst volume error %.2e, density %.2e"
+          % (precision, len(rows), len(retried), vworst, dworst))
+    assert vworst <= TOL[precision] and dworst <= TOL[precision]
+    # gradients: the oracle's densities of the rows and of all their neighbours
+    grows = np.unique(np.concatenate([rows[:512], retried]))
+    gq = np.searchsorted(rows, grows)
+    nb = np.unique(np.concatenate([ref.neighbours(q) for q in gq]))
+    need = np.setdiff1d(nb, rows)
+    refn = oracle.local_cells(p64, w.box_lo, w.box_hi, need, tree=clustered2m_tree)
+    rho_ref = np.full(n, np.nan)
+    rho_ref[rows] = m[rows] / ref.volume
+    rho_ref[need] = m[need] / refn.volume
+    goff = np.zeros(len(grows) + 1, np.int64)
+    goff[1:] = np.cumsum([ref.nnb[q] for q in gq])
+    gids = np.concatenate([ref.neighbours(q) for q in gq])
+    gref = oracle.gradient(p64, w.box_lo, w.box_hi, True, goff, gids, rho_ref, rows=grows)
+    vq = ref.volume[gq]
+    scale = np.maximum(np.linalg.norm(gref, axis=1), rho_ref[grows] / np.cbrt(vq))
+    err = np.linalg.norm(grad[grows] - gref, axis=1) / scale
+    print("clustered 2M, precision %d: %d gradients, worst scaled error %.2e" % (precision, len(grows), err.max()))
+    assert err.max() <= TOL[precision]
 
 
 def test_clustered2m_grid_sampled_cells(vt, torch_cuda, oracle):
@@ -78,9 +165,40 @@ def test_clustered2m_grid_sampled_cells(vt, torch_cuda, oracle):
     g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
     assert ctx.vt_query()[0] == 0
     gref = oracle.grid(w.pos.astype(np.float64), w.box_lo, w.box_hi, True, val, dims, query=sample)
-    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    # per voxel: relative to the voxel's own value, with a floor of 1e-13 of the largest value for
+    # voxels that a cell only grazes (their share of the cell is tiny, so is their absolute error)
+    err = np.abs(g - gref)
+    big = np.abs(gref).max()
+    print("clustered 2M deposit of 96 cells: worst error %.2e of the largest voxel, worst relative error of "
+          "voxels above 1e-6 of it %.2e" % (err.max() / big, (err / np.abs(gref))[np.abs(gref) > 1e-6 * big].max()))
+    assert np.all(err <= 1e-11 * np.abs(gref) + 1e-13 * big)
     del ctx, t
     torch_cuda.cuda.empty_cache()
+
+
+def test_clustered2m_unit_field_over_every_cell(vt, torch_cuda, clustered2m):
+    """Every cell deposits 1 at 256^3: every voxel must be 1 (the cells tile the box), the mass
+    (sum of grid h^3) equals the total volume, and no topology record is rejected (a record that
+    fails its checks would be a clip-kernel fault; vt_query reports it)."""
+    T = torch_cuda
+    w = clustered2m
+    ctx = vt.Context().vt_build(T.from_numpy(w.pos).cuda(), vt.whole_box(w.n, w.box_lo, w.box_hi))
+    assert ctx.vt_query()[0] == 0
+    dims = (256, 256, 256)
+    g = ctx.vt_grid_deposit(T.ones(w.n, dtype=T.float64, device="cuda"), dims)
+    assert ctx.vt_query()[0] == 0
+    dev = (g - 1.0).abs().max().item()
+    print("clustered 2M unit field at 256^3: worst voxel deviation %.2e" % dev)
+    assert dev <= 1e-12
+    hv = float(np.prod(w.box_len)) / float(np.prod(dims))
+    assert abs(g.sum().item() * hv - float(np.prod(w.box_len))) <= 1e-12 * float(np.prod(w.box_len))
+    # densities: mass conservation of the benchmark's own deposit
+    rho = ctx.vt_density(T.from_numpy(w.mass).cuda())
+    g = ctx.vt_grid_deposit(rho, dims)
+    assert ctx.vt_query()[0] == 0
+    assert abs(g.sum().item() * hv - w.mass.sum()) <= 1e-12 * w.mass.sum()
+    del ctx, g
+    T.cuda.empty_cache()
 
 
 def test_clustered2m_autoborder_decomposition_equals_whole_box(vt, torch_cuda):
@@ -154,9 +272,14 @@ def test_clustered2m_structure(vt, torch_cuda, oracle):
     assert ((vol - cells.volume).abs() / cells.volume).max().item() <= 1e-11
     V, F = voff.diff(), foff.diff()
     Lc = T.bincount(c, minlength=n)
-    closed = Lc == 3 * V
-    assert T.all((V - Lc // 2 + F)[closed] == 2)
-    assert closed.double().mean().item() >= 0.999
+    # Euler's formula V - E + F = 2 holds for every closed polytope whatever its vertex degrees
+    # (E = loop entries / 2).  On this general-position input every vertex is simple (on 3 faces)
+    # and no face falls below the facet threshold (a dropped face would leave a hole): then every
+    # cell has exactly 3 V loop entries, and Euler's formula is checked on every cell
+    n_open = int((Lc != 3 * V).sum().item())
+    print("clustered 2M structure: %d cells whose loops are not 3 per vertex" % n_open)
+    assert n_open == 0
+    assert T.all(V - Lc // 2 + F == 2)
     del v, N, c, face_of_loop, cell_of_face
     # sampled cells against the oracle, the largest (cells of the large kernels) among them
     nv = V.cpu().numpy()
@@ -202,7 +325,14 @@ def _target(torch, x, lam, phi, amp, mean):
     return mean * (1.0 + amp * s)
 
 
-def test_diff262k_adjoint_vs_finite_differences(vt, torch_cuda):
+def test_diff262k_adjoint_vs_finite_differences(vt, torch_cuda, oracle):
+    """dL/dx of L = sum_i (log rho_i - log rho_t(x_i))^2 through the adjoint kernel (autograd), at
+    full size, against central differences of the oracle's FP64 volumes: for each of the 512 rows
+    and each axis, x_k moves by +-h and the loss change is summed over the cells that change,
+    x_k's cell and those of its neighbours before and after the move.  Rows where a neighbour set
+    changes between -h and +h are topology events (V is continuously differentiable there but
+    not twice, so the central difference carries an O(h) error); they are counted and reported,
+    and every other row must agree within 1e-6."""
     torch = torch_cuda
     w = wl.diff262k()
     n = w.n
@@ -214,73 +344,49 @@ def test_diff262k_adjoint_vs_finite_differences(vt, torch_cuda):
     loss = ((torch.log(1.0 / V) - torch.log(_target(torch, x, lam, phi, amp, mean))) ** 2).sum()
     loss.backward()
     grad = x.grad.cpu().numpy()
+    del x, V, loss
+    torch.cuda.empty_cache()
 
-    # neighbour lists of the unperturbed set
-    ctx = vt.Context().vt_build(torch.from_numpy(p64).cuda(), vt.whole_box(n, 0.0, 1.0))
-    cells = ctx.vt_cells()
-    off = cells.nbr_off.cpu().numpy()
-    ids = cells.nbr_ids.cpu().numpy()
-    tree = cKDTree(p64, boxsize=1.0)
     rows = w.extra["fd_rows"]
     h = 1e-6
+    tree = cKDTree(p64, boxsize=1.0)
+    base = oracle.local_cells(p64, 0.0, 1.0, rows, tree=tree)
 
-    def mind(a, b):
-        d = a - b
-        return d - np.rint(d)
+    def ell(q, vol, xk_new, k):
+        xq = p64[q].copy()
+        xq[q == k] = xk_new
+        rt = wl.target_density(np.mod(xq, 1.0), lam, phi, amp, mean)
+        return (np.log(w.mass[q] / vol) - np.log(rt)) ** 2
 
-    def worlds_for(ks, factor):
-        # radius: every affected cell's offset from x_k plus `factor` times its largest
-        # neighbour distance (a generous scale for twice its security radius)
-        worlds, meta = [], []
-        for k in ks:
-            aff = np.concatenate([[k], ids[off[k]:off[k + 1]]]).astype(np.int64)
-            r = 0.0
-            for i in aff:
-                nb = ids[off[i]:off[i + 1]]
-                far = np.sqrt((mind(p64[nb], p64[i]) ** 2).sum(1)).max()
-                r = max(r, np.sqrt((mind(p64[i], p64[k]) ** 2).sum()) + factor * far)
-            near = np.asarray(tree.query_ball_point(p64[k], min(r, 0.45)), dtype=np.int64)
-            loc = np.concatenate([aff, np.setdiff1d(near, aff)])
-            d = mind(p64[loc], p64[k])
-            rb = np.abs(d).max() * 1.0000001
-            base = p64[k] + d
-            for a in range(3):
-                for s in (1.0, -1.0):
-                    q = base.copy()
-                    q[0, a] += s * h
-                    worlds.append((q[:len(aff)], q[len(aff):], p64[k] - rb, p64[k] + rb))
-                    meta.append((k, a, s, len(aff)))
-        return worlds, meta
-
-    fd = {}
-    todo, factor = list(rows), 2.0
-    while todo:
-        assert factor <= 16.0, "local worlds keep missing particles"
-        worlds, meta = worlds_for(todo, factor)
-        pos, desc, gid = vt.pack_worlds(worlds)
-        bctx = vt.Context().vt_build(torch.from_numpy(pos).cuda(), desc, global_id=torch.from_numpy(gid).cuda())
-        assert bctx.vt_query()[0] == 0
-        bc = bctx.vt_cells()
-        bvol = bc.volume.cpu().numpy()
-        bst = bc.status.cpu().numpy()
-        row, redo, part = 0, set(), {}
-        for (k, a, s, na), (owned, _, _, _) in zip(meta, worlds):
-            v = bvol[row:row + na]
-            if (bst[row:row + na] & 1).any():
-                redo.add(k)
-            rt = wl.target_density(np.mod(owned, 1.0), lam, phi, amp, mean)
-            part.setdefault(k, np.zeros(3))[a] += s * float(np.sum((np.log(1.0 / v) - np.log(rt)) ** 2)) / (2 * h)
-            row += na
-        for k in part:
-            if k not in redo:
-                fd[k] = part[k]
-        print("local worlds: factor %.0f, %d particles, %d to redo" % (factor, len(pos), len(redo)))
-        todo, factor = sorted(redo), factor * 2.0
-        del bctx, bc
-    fd = np.array([fd[k] for k in rows])
+    fd = np.zeros((len(rows), 3))
+    event = np.zeros(len(rows), bool)
+    for t, k in enumerate(rows):
+        for a in range(3):
+            xs = {}
+            for sgn in (1.0, -1.0):
+                xk = p64[k].copy()
+                xk[a] += sgn * h
+                xs[sgn] = xk
+            # the affected cells: x_k's own and its neighbours', at -h, 0 and +h
+            aff = {int(k)} | set(base.neighbours(t).tolist())
+            while True:
+                q = np.array(sorted(aff), np.int64)
+                cp = oracle.local_cells(p64, 0.0, 1.0, q, moved={int(k): xs[1.0]}, tree=tree)
+                cm = oracle.local_cells(p64, 0.0, 1.0, q, moved={int(k): xs[-1.0]}, tree=tree)
+                me = int(np.searchsorted(q, k))
+                more = (set(cp.neighbours(me).tolist()) | set(cm.neighbours(me).tolist())) - aff
+                if not more:
+                    break
+                aff |= more
+            dl = ell(q, cp.volume, xs[1.0], k) - ell(q, cm.volume, xs[-1.0], k)
+            fd[t, a] = dl.sum() / (2 * h)
+            event[t] |= any(not np.array_equal(cp.neighbours(j), cm.neighbours(j)) for j in range(len(q)))
     g = grad[rows]
-    scale = np.abs(g).max(axis=1, keepdims=True)
-    err = np.abs(fd - g) / np.maximum(scale, 1e-3 * np.abs(g).max())
-    print("finite differences: max scaled error %.3e, median %.3e" % (err.max(), np.median(err)))
-    assert np.median(err) < 1e-6
-    assert np.quantile(err, 0.99) < 1e-4
+    scale = np.maximum(np.abs(g).max(axis=1, keepdims=True), 1e-3 * np.abs(g).max())
+    err = np.abs(fd - g) / scale
+    row_err = err.max(axis=1)
+    print("finite differences on %d rows: %d topology-event rows (worst scaled error %.3e there); other rows: "
+          "worst %.3e, median %.3e" % (len(rows), event.sum(), row_err[event].max() if event.any() else 0.0,
+                                       row_err[~event].max(), np.median(row_err[~event])))
+    assert event.sum() <= len(rows) // 20
+    assert row_err[~event].max() <= 1e-6

@@ -254,11 +254,41 @@ def test_autotune_picks_a_candidate_and_results_do_not_depend_on_it(vt, torch_cu
             assert np.array_equal(cur[1], ref[1]) and np.array_equal(cur[2], ref[2]), opts
             assert np.max(np.abs(cur[0] - ref[0]) / ref[0]) < 1e-13, opts
 
+def test_batched_large_items_match_oracle(vt, torch_cuda, oracle):
+    """The batched workload's shape: four uneven clustered items of 1e5 - 1e6 owned particles with
+    their buffer particles, one build; 1024 seeded owned cells per item against the oracle on that
+    item's bounded world (every particle of it), flags included."""
+    items = wl.batched64(n_items=4, n_range=(1e5, 1e6), seed_offset=4)
+    worlds = [(it.owned, it.ghosts, it.buffered_lo, it.buffered_hi) for it in items]
+    pos, desc, gid = vt.pack_worlds(worlds)
+    assert all(d["n_owned"] >= 50_000 for d in desc) and max(d["n_owned"] for d in desc) >= 300_000
+    ctx = vt.Context().vt_build(torch_cuda.from_numpy(pos).cuda(), desc, global_id=torch_cuda.from_numpy(gid).cuda())
+    code, nnz, retried, n_inc = ctx.vt_query()
+    assert code == 0
+    cells = ctx.vt_cells()
+    st = cells.status.cpu().numpy()
+    rng = np.random.default_rng(4242)
+    row = 0
+    for d in desc:
+        n_w = d["n_owned"] + d["n_ghost"]
+        p64 = pos[d["offset"]:d["offset"] + n_w].astype(np.float64)
+        q = np.sort(rng.choice(d["n_owned"], 1024, replace=False))
+        ref = oracle.cells(p64, d["lo"], d["hi"], periodic=False, query=q,
+                           gid=gid[d["offset"]:d["offset"] + n_w].astype(np.int64), nthreads=16)
+        compare_rows(cells, ref, row + q, TOL[0], "large item at row %d" % row)
+        flag_ref = (ref.flags & (oracle.FLAG_WALL | oracle.FLAG_INCOMPLETE)) != 0
+        assert np.array_equal((st[row + q] & 1) != 0, flag_ref)
+        row += d["n_owned"]
+
+
 # ---------------------------------------------------------------- derived outputs
-def test_gradient_matches_oracle(vt, torch_cuda, oracle):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gradient_matches_oracle(vt, torch_cuda, oracle, precision):
+    """Every cell's least-squares gradient against the oracle's, scaled by
+    max(|grad|, rho / V^(1/3)): within 1e-12 on the FP64 path, 2e-5 on the mixed one."""
     w = wl.uniform4096()
     t = torch_cuda.from_numpy(w.pos).cuda()
-    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi))
+    ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision)
     cells = ctx.vt_cells()
     rng = np.random.default_rng(4)
     m = rng.uniform(0.5, 2.0, w.n)
@@ -270,7 +300,8 @@ def test_gradient_matches_oracle(vt, torch_cuda, oracle):
     gref = oracle.gradient(w.pos, w.box_lo, w.box_hi, True, off, ids, rho_ref)
     scale = np.maximum(np.linalg.norm(gref, axis=1), rho_ref / ref.volume ** (1.0 / 3.0))
     err = np.linalg.norm(grad - gref, axis=1) / scale
-    assert err.max() < 1e-10, err.max()
+    print("uniform4096 gradients, precision %d: worst scaled error %.2e" % (precision, err.max()))
+    assert err.max() <= TOL[precision], err.max()
 
 
 def test_gradient_linear_field_bounded(vt, torch_cuda):
@@ -299,7 +330,11 @@ def test_grid_matches_oracle(vt, torch_cuda, oracle, dims):
     assert code == 0
     ref_cells = oracle.cells(w.pos, w.box_lo, w.box_hi)
     gref = oracle.grid(w.pos, 0.0, 1.0, True, oracle.density(m, ref_cells.volume), dims)
-    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    # per voxel, relative to its own value (a positive field: every voxel is an average of positive
+    # densities, so no voxel is near zero)
+    rel = np.abs(g - gref) / np.abs(gref)
+    print("uniform4096 deposit %s: worst voxel relative error %.2e" % (dims, rel.max()))
+    assert rel.max() <= 1e-12
     assert abs(g.sum() / np.prod(dims) - m.sum()) <= 1e-12 * m.sum()
 
 
@@ -314,7 +349,7 @@ def test_grid_bounded_world_matches_oracle(vt, torch_cuda, oracle):
     g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
     assert ctx.vt_query()[0] == 0
     gref = oracle.grid(p, 0.0, 1.0, False, val, dims)
-    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    assert np.all(np.abs(g - gref) <= 1e-12 * np.abs(gref))
 
 
 def test_grid_large_cell(vt, torch_cuda, oracle):
@@ -338,7 +373,9 @@ def test_grid_large_cell(vt, torch_cuda, oracle):
     g = ctx.vt_grid_deposit(torch_cuda.from_numpy(val).cuda(), dims).cpu().numpy()
     assert ctx.vt_query()[0] == 0
     gref = oracle.grid(p, 0.0, 1.0, True, val, dims, query=np.arange(m + 1))
-    assert np.abs(g - gref).max() <= 1e-11 * np.abs(gref).max()
+    # only 91 cells carry values: voxels they graze hold tiny values, so a floor of 1e-13 of the
+    # largest voxel stands beside the relative bar
+    assert np.all(np.abs(g - gref) <= 1e-11 * np.abs(gref) + 1e-13 * np.abs(gref).max())
 
 
 def test_grid_unit_field_and_aligned_lattice(vt, torch_cuda):
@@ -374,8 +411,15 @@ def test_backward_matches_oracle_adjoint(vt, torch_cuda, oracle, precision):
     dx = ctx.vt_backward(torch_cuda.from_numpy(g).cuda()).cpu().numpy()
     ref = oracle.cells(w.pos, w.box_lo, w.box_hi)
     dref = oracle.adjoint(ref, g)
-    scale = np.abs(dref).max()
-    assert np.abs(dx - dref).max() <= 1e-10 * scale
+    # per particle, relative to the magnitude of the terms it sums,
+    # sum_j |g_k - g_j| A_kj |c_kj| / d_kj (a component can cancel to near zero)
+    mag = np.zeros(w.n)
+    for q in range(w.n):
+        A, C, d = ref.faces(q)
+        mag[q] = np.sum(np.abs(g[q] - g[ref.neighbours(q)]) * A / d * np.linalg.norm(C, axis=1))
+    err = np.abs(dx - dref).max(axis=1) / mag
+    print("uniform4096 adjoint, precision %d: worst error relative to the summed terms %.2e" % (precision, err.max()))
+    assert err.max() <= (1e-12 if precision == 0 else 2e-5)
 
 
 def test_backward_requires_faces(vt, torch_cuda):

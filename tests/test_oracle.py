@@ -472,44 +472,81 @@ def test_workload_shapes():
 # ---- AUTOBORDER (section 2, buffer zones): pins of the reference rule
 
 
+def test_autoborder_mean_spacing_is_the_papers_worked_example(oracle):
+    # section 2: an inter-particle distance of 1.58 computed from the whole input; 1000 particles
+    # in a cube of side 15.8 have exactly that mean spacing
+    with open(os.path.join(GOLDEN, "ghost_width.json")) as f:
+        ex = json.load(f)
+    s = oracle.mean_spacing(1000, 0.0, 15.8)
+    assert round(s, ex["printed_decimals"]) == ex["inter_particle_distance"]
+    assert round(ex["border_factor"] * s, ex["printed_decimals"]) == ex["buffer_thickness"]
+
+
 def test_autoborder_lattice_at_mean_density_keeps_first_thickness(oracle):
-    # simple-cubic lattice, spacing 1/16: a slab of thickness 2 spacings beyond any face holds two
-    # full layers, exactly the mean density times the face area times the thickness
+    # simple-cubic lattice, spacing 1/16 (the mean spacing): with BORDERFACTOR 2 a slab two
+    # spacings thick beyond any face holds two full layers, exactly the mean density times the face
+    # area times the thickness
     a = 1.0 / 16
     g = (np.arange(16) + 0.5) * a
     p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
-    thr = 2 * a * 1.1 ** np.arange(8)
-    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), thr)
-    assert np.all(t == thr[0])
+    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), border_factor=2.0, growth=1.1, steps=8)
+    assert np.all(t == 2 * a)
 
 
 def test_autoborder_empty_neighbour_reaches_cap(oracle):
-    # every particle in the octant of task 0: the faces of the opposite task see empty slabs
+    # every particle in the octant of task 0: the faces of the opposite task see empty slabs and
+    # take the periodic cap (a buffered task spans less than one period)
     rng = np.random.default_rng(7)
     p = rng.random((4000, 3)) * 0.5
-    thr = 0.05 * 1.1 ** np.arange(30)
-    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), thr)
-    cap = oracle.thickness_cap(0.0, 1.0, (2, 2, 2))
-    assert np.all(t[7] == cap[0])
+    t = oracle.autoborder(p, 0.0, 1.0, (2, 2, 2), border_factor=0.8, growth=1.1, steps=30)
+    assert np.all(t[7] == 0.25 * (1.0 - 1e-12))
+
+
+def _hand_counted_slab():
+    # 64 particles in the unit box: mean spacing 1/4; BORDERFACTOR 1/2 and growth 3/2 give the
+    # thicknesses 1/8, 3/16, 9/32, and the expected count 64 * 1 * 1/8 = 8.  Four slabs along x;
+    # beyond the +x face of task 0 (x = 1/4) lie 8 particles at distances counted by hand:
+    # 2 below 1/8, 5 below 3/16, 8 below 9/32
+    d = np.array([1, 3, 4.5, 5, 5.5, 6.5, 7.5, 8.5]) / 32
+    rng = np.random.default_rng(3)
+    beyond = np.column_stack([0.25 + d, rng.random(8), rng.random(8)])
+    far = np.column_stack([rng.uniform(0.6, 1.0, 56), rng.random(56), rng.random(56)])
+    return np.concatenate([beyond, far]), d
 
 
 def test_autoborder_hand_counted_slab(oracle):
-    # two slabs along x (one task along y and z): 32 particles, mean density 32, face area 1,
-    # expected 32 * 1 * 1/8 = 4 particles.  Beyond the +x face of task 0 (x = 1/2) lie particles
-    # at distances 1/16, 5/32, 11/64, 13/64, 7/32: slab counts 1 (< 1/8), 3 (< 3/16), 4 (< 7/32)
-    d = np.array([1 / 16, 5 / 32, 11 / 64, 13 / 64, 7 / 32])
-    rng = np.random.default_rng(3)
-    beyond = np.column_stack([0.5 + d, rng.random(5), rng.random(5)])
-    own = np.column_stack([rng.uniform(0.0, 0.25, 27), rng.random(27), rng.random(27)])
-    p = np.concatenate([own, beyond])
-    thr = np.array([1 / 8, 3 / 16, 7 / 32])
-    t = oracle.autoborder(p, 0.0, 1.0, (2, 1, 1), thr)
-    assert t[0, 1] == 7 / 32
-    # with 13/64 moved beyond the last threshold, no threshold reaches 4: the last one is taken
+    p, d = _hand_counted_slab()
+    t = oracle.autoborder(p, 0.0, 1.0, (4, 1, 1), border_factor=0.5, growth=1.5, steps=3)
+    assert t[0, 1] == 9 / 32
+    # with the farthest one moved past the last thickness, none reaches 8: the last one is taken
     p2 = p.copy()
-    p2[-2, 0] = 0.5 + 15 / 64
-    assert oracle.autoborder(p2, 0.0, 1.0, (2, 1, 1), thr)[0, 1] == 7 / 32
-    assert oracle.autoborder(p2, 0.0, 1.0, (2, 1, 1), thr[:2])[0, 1] == 3 / 16
+    p2[7, 0] = 0.25 + 9.5 / 32
+    assert oracle.autoborder(p2, 0.0, 1.0, (4, 1, 1), border_factor=0.5, growth=1.5, steps=3)[0, 1] == 9 / 32
+    assert oracle.autoborder(p2, 0.0, 1.0, (4, 1, 1), border_factor=0.5, growth=1.5, steps=2)[0, 1] == 3 / 16
+    # the other side of the face does not count: mirrored inside task 0 they are not beyond it
+    p3 = p.copy()
+    p3[:8, 0] = 0.25 - d
+    assert oracle.autoborder(p3, 0.0, 1.0, (4, 1, 1), border_factor=0.5, growth=1.5, steps=3)[0, 1] == 9 / 32
+    assert oracle.autoborder(p3, 0.0, 1.0, (4, 1, 1), border_factor=0.5, growth=1.5, steps=2)[0, 1] == 3 / 16
+
+
+def test_autoborder_bounded_world_faces(oracle):
+    # a bounded slab world [0, 4] x [0, 1] x [0, 1] split into 4 slabs along x (the paper's scheme
+    # (b) for elongated volumes): the world's own faces get no buffer, an interior face's buffer
+    # stops at the world's face beyond it, and nothing wraps around
+    rng = np.random.default_rng(11)
+    p = rng.random((4000, 3)) * [4.0, 1.0, 1.0]
+    t = oracle.autoborder(p, 0.0, [4.0, 1.0, 1.0], (4, 1, 1), border_factor=1.5, periodic=False)
+    assert np.all(t[:, 2:] == 0.0)                   # y and z faces are the world's
+    assert t[0, 0] == 0.0 and t[3, 1] == 0.0         # the two ends
+    assert np.all(t[:3, 1] > 0.0) and np.all(t[1:, 0] > 0.0)
+    # an empty neighbouring task: the buffer grows across it to the particles beyond
+    q = p[(p[:, 0] < 1.0) | (p[:, 0] >= 2.0)]
+    tq = oracle.autoborder(q, 0.0, [4.0, 1.0, 1.0], (4, 1, 1), border_factor=1.5, growth=1.1, steps=48,
+                           periodic=False)
+    assert 1.0 < tq[0, 1] <= 3.0                     # it crossed the whole empty task
+    assert oracle.face_cap(0.0, [4.0, 1.0, 1.0], (4, 1, 1), (0, 0, 0), 1, periodic=False) == 3.0
+    assert oracle.face_cap(0.0, [4.0, 1.0, 1.0], (4, 1, 1), (2, 0, 0), 0, periodic=False) == 2.0
 
 
 def test_task_members_images_and_ownership(oracle):
@@ -520,6 +557,12 @@ def test_task_members_images_and_ownership(oracle):
     own, buf, sh = oracle.task_members(p, 0.0, 1.0, (2, 2, 2), thick, 0)
     assert list(own) == [0]
     assert sorted(zip(buf.tolist(), map(tuple, sh.tolist()))) == [(1, (-1, -1, -1)), (2, (0, 0, 0))]
+    # the same in a bounded world: no images; a particle on the world's upper face is owned
+    own, buf, sh = oracle.task_members(p, 0.0, 1.0, (2, 2, 2), thick, 0, periodic=False)
+    assert list(own) == [0] and sorted(buf.tolist()) == [2]
+    q = np.array([[1.0, 1.0, 1.0], [0.3, 0.3, 0.3]])
+    own, buf, _ = oracle.task_members(q, 0.0, 1.0, (2, 2, 2), np.zeros((8, 6)), 7, periodic=False)
+    assert list(own) == [0] and len(buf) == 0
 
 
 # ---- nearest-particle grid sampling (grid variant): pins of the reference
@@ -710,3 +753,41 @@ def test_grid_tensor_nyquist_convention(oracle):
     assert np.abs(H[3]).max() <= 1e-10 and np.abs(H[4]).max() <= 1e-10   # rounding only (|H_xx| ~ 600)
     np.testing.assert_allclose(H[0], -k[0] ** 2 * np.cos(arg), atol=1e-10)
     np.testing.assert_allclose(H[1], -k[1] ** 2 * np.cos(arg), atol=1e-10)
+
+
+# ---- local worlds: the same cells from a ball around each particle
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_local_cells_equal_brute_force(oracle, periodic):
+    # a clustered set (half background, half in NFW-like halos): cells in and next to halos need
+    # their local worlds widened; every one must equal the cell over all particles
+    w = wl.diff262k(n=20000)
+    p = w.pos.astype(np.float64)
+    rng = np.random.default_rng(41)
+    q = np.sort(rng.choice(len(p), 300, replace=False))
+    ref = oracle.cells(p, 0.0, 1.0, periodic=periodic, query=q, stride=256)
+    loc = oracle.local_cells(p, 0.0, 1.0, q, periodic=periodic)
+    for k in range(len(q)):
+        assert np.array_equal(loc.neighbours(k), ref.neighbours(k)), q[k]
+        a1, c1, d1 = loc.faces(k)
+        a0, c0, d0 = ref.faces(k)
+        np.testing.assert_allclose(a1, a0, rtol=1e-13, atol=1e-15 * ref.volume[k] ** (2 / 3))
+    np.testing.assert_allclose(loc.volume, ref.volume, rtol=1e-14)
+    assert np.array_equal(loc.flags & oracle.FLAG_WALL, ref.flags & oracle.FLAG_WALL) or periodic
+
+
+def test_local_cells_follow_a_moved_particle(oracle):
+    # moving one particle: its cell and its neighbours' cells as the brute-force oracle gives them
+    w = wl.diff262k(n=8000)
+    p = w.pos.astype(np.float64)
+    k = 123
+    new = p[k] + np.array([3e-3, -2e-3, 1e-3])
+    q = np.concatenate([[k], oracle.cells(p, 0.0, 1.0, query=[k]).neighbours(0)])
+    p2 = p.copy()
+    p2[k] = new
+    ref = oracle.cells(p2, 0.0, 1.0, query=q)
+    loc = oracle.local_cells(p, 0.0, 1.0, q, moved={k: new})
+    for t in range(len(q)):
+        assert np.array_equal(loc.neighbours(t), ref.neighbours(t))
+    np.testing.assert_allclose(loc.volume, ref.volume, rtol=1e-14)
