@@ -1,19 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the Voronoi hot path on one MI355X.
 
-One step = the whole per-particle path over the clustered 2,097,152-particle
-periodic box (side 100, FP32 positions, half uniform background and half in 200
-NFW-like halos): Morton sort + clipping (vt_build with facets kept), neighbour
-CSR and volumes (vt_cells), densities (vt_density), density gradients
-(vt_gradient), the exact 256^3 grid deposit (vt_grid_deposit) and the volume
-adjoint (vt_backward).  Inputs are resident in HBM before the timed region.
+The workload is the clustered 2,097,152-particle periodic box (side 100, FP32 positions, half
+uniform background and half in 200 NFW-like halos).  `value` is the metric's own rate,
+neighbours + volume + density: one step is the Morton sort and the clipping (vt_build, facets
+kept), the neighbour CSR and volumes (vt_cells) and the densities (vt_density), timed over K steps
+with the inputs resident in HBM.  The whole per-particle path (adding density gradients, the exact
+256^3 grid deposit and the volume adjoint) is timed separately (`whole_step`), with per-stage HIP
+event times.
 
-Printed (one JSON line): whole-step cells/s, the forward-only and backward
-rates, per-stage times from HIP events, the roofline of the dominant kernel
-(the clipping kernel; VALU-bound, algorithmic flops from the cost model
-6 P V + 60 V per cell, P = particles inside the security radius, V = final
-vertices) and the brute-force FP64 oracle timed on a bounded sample of the same
-workload on the host cores.
+Also printed on the same JSON line: the roofline of the dominant kernel (the clipping kernel;
+VALU-bound, algorithmic flops from the cost model 6 P V + 60 V per cell, P = particles inside the
+security radius, V = final vertices) with counter figures from the committed rocprofv3 summary,
+the backward rate of the 262k differentiation workload, the forward rates of the 4096 and 16.7M
+workloads, the precision variants, the batched and decomposed forms, and the brute-force FP64
+oracle timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
 import ctypes
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--no-decomposed", action="store_true", help="skip the AUTOBORDER decomposed form")
     ap.add_argument("--no-tune", action="store_true", help="library default launch options instead of the autotuner's")
     ap.add_argument("--fwd-only", action="store_true", help="time only vt_build + vt_cells + vt_density")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the backward (262k) and other-workload (4096, 16.7M) forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (traffic calibration for rocprofv3 counters)")
     return ap.parse_args()
@@ -94,6 +97,57 @@ def measured_traffic():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_clip_k_grid_clustered2m_counters.md")
+GRID_SOURCES = ["paper_1601_06429_amd/csrc/grid.hip", "paper_1601_06429_amd/csrc/rebuild.h",
+                "paper_1601_06429_amd/csrc/poly.h", "paper_1601_06429_amd/csrc/vt_internal.h"]
+
+
+def sources_sha1(files):
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _summary(path):
+    try:
+        with open(path) as fh:
+            return dict(line.strip("- \n").split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
+    except OSError:
+        return {}
+
+
+def clip_counters():
+    """Per-launch counter figures of the fast clip kernel from the committed rocprofv3 summary,
+    while the kernel's sources are the ones they were taken from; else None."""
+    kv = _summary(COUNTERS_FILE)
+    if kv.get("clip_source_sha1") != sources_sha1(CLIP_SOURCES):
+        return None
+    try:
+        return {"fp64_wave_flops": float(kv["clip_fp64_wave_flops"]), "valu_busy": float(kv["clip_valu_busy"]),
+                "valu_lane_util": float(kv["clip_valu_lane_util"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def grid_counters():
+    """The same for the grid deposit kernel: VALU issue and lane use against the VALU issue
+    peak (one wavefront instruction per SIMD every 4 cycles)."""
+    kv = _summary(COUNTERS_FILE)
+    if kv.get("grid_source_sha1") != sources_sha1(GRID_SOURCES):
+        return None
+    try:
+        busy = float(kv["grid_valu_busy"])
+        return {"achieved": busy, "peak": 1.0, "unit": "fraction of VALU issue cycles", "frac": busy,
+                "valu_lane_utilisation": float(kv["grid_valu_lane_util"]),
+                "traffic": float(kv["grid_hbm_bytes_per_launch"]) if "grid_hbm_bytes_per_launch" in kv else None}
     except (KeyError, ValueError):
         return None
 
@@ -208,6 +262,110 @@ def decomposed_form(torch, vt, w, nt=(4, 4, 4), border_factor=1.5, reps=3):
                                                           "max_rel_volume_diff": max_rel}}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _target(torch, x, lam, phi, amp, mean):
+    import math
+
+    s = torch.ones(x.shape[0], dtype=x.dtype, device=x.device)
+    for a in range(3):
+        s = s * torch.sin(2.0 * math.pi * x[:, a] / float(lam[a]) + float(phi[a]))
+    return mean * (1.0 + amp * s)
+
+
+def backward_form(torch, vt, reps=10):
+    """The differentiation workload: 262,144 clustered particles in the periodic unit cube, loss
+    sum_i (log rho_i - log rho_t(x_i))^2 against a smooth sinusoidal target.  Timed: the backward
+    pass of that loss, i.e. dL/dV (elementwise), the adjoint kernel vt_backward and the explicit
+    target term, with the forward build (facets kept) done once before; cells/s = N / time."""
+    from paper_1601_06429_amd import workloads as wl
+
+    w = wl.diff262k()
+    n = w.n
+    lam, phi, amp = w.extra["target_lambda"], w.extra["target_phase"], w.extra["target_amplitude"]
+    mean = float(w.mass.sum())
+    x = torch.from_numpy(w.pos.astype(np.float64)).cuda()
+    ctx = vt.Context().vt_build(x, vt.whole_box(n, 0.0, 1.0), want_faces=True)
+    vol = ctx.vt_cells().volume
+    xr = x.clone().requires_grad_(True)
+    rt = _target(torch, xr, lam, phi, amp, mean)
+    dx = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+
+    def bwd():
+        r = torch.log(1.0 / vol) - torch.log(rt.detach())
+        dldv = (-2.0 * r / vol).contiguous()
+        ctx.vt_backward(dldv, out=dx)
+        # the explicit dependence of rho_t on x_i
+        gt, = torch.autograd.grad(rt, xr, grad_outputs=-2.0 * r / rt.detach(), retain_graph=True)
+        dx.add_(gt)
+
+    bwd()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bwd()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        ctx.vt_backward(torch.ones(n, dtype=torch.float64, device="cuda"), out=dx)
+    e1.record()
+    e1.synchronize()
+    ms_k = e0.elapsed_time(e1) / reps
+    code = ctx.vt_query()[0]
+    return {"workload": w.name, "n_cells": n, "ms": ms, "cells_per_s": n / (ms * 1e-3), "adjoint_kernel_ms": ms_k,
+            "status": vt.STATUS_NAMES.get(code),
+            "step": "dL/dV + vt_backward + target term (backward of the density-matching loss)"}
+
+
+def other_configs(torch, vt, reps=5):
+    """Forward rate (build + cells + density) of the other workloads: the 4096-particle FP64
+    box (launch-bound at this size) and the 16.7M lattice+halos set in both precisions."""
+    from paper_1601_06429_amd import workloads as wl
+
+    res = {}
+    for name, w, precs in (("uniform4096", wl.uniform4096(), (vt.PREC_FP64,)),
+                           ("lattice16m", wl.lattice_halos16m(), (vt.PREC_FP64, vt.PREC_MIXED))):
+        pos = torch.from_numpy(w.pos).cuda()
+        items = vt.whole_box(w.n, w.box_lo, w.box_hi)
+        for p in precs:
+            ctx = vt.Context().vt_build(pos, items, precision=p)
+            nnz = ctx.vt_query()[1]
+            vol = torch.empty(w.n, dtype=torch.float64, device="cuda")
+            off = torch.empty(w.n + 1, dtype=torch.int64, device="cuda")
+            ids = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device="cuda")
+            rho = torch.empty(w.n, dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                ctx.vt_build(pos, items, precision=p)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(reps):
+                ctx.vt_build(pos, items, precision=p)
+                ctx.vt_cells_into(vol, off, ids)
+                ctx.vt_density(None, out=rho)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            code = ctx.vt_query()[0]
+            res["%s_%s" % (name, "fp64" if p == vt.PREC_FP64 else "mixed")] = {
+                "workload": w.name, "n_cells": w.n, "fwd_cells_per_s": w.n * reps / (tb - ta),
+                "ms": (tb - ta) * 1e3 / reps, "status": vt.STATUS_NAMES.get(code)}
+            del ctx, vol, off, ids, rho
+        del pos
+        torch.cuda.empty_cache()
+    return res
+
+
 def load_workload(name):
     from paper_1601_06429_amd import workloads as wl
 
@@ -292,15 +450,34 @@ def main():
             if record:
                 ev[6].record()
 
+    def fwd_step():
+        ctx.vt_build(pos, items, precision=prec, want_faces=True, **tuned)
+        ctx.vt_cells_into(vol, off, ids, st)
+        ctx.vt_density(mass, out=rho)
+
+    # the metric's own rate: neighbours + volume + density (build, CSR, densities), K timed steps
     for _ in range(args.warmup):
-        step(False)
+        fwd_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(False)
+        fwd_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # the whole per-particle path (adds gradients, the grid deposit and the adjoint), K timed steps
+    whole_ms = None
+    if not args.fwd_only:
+        for _ in range(max(1, args.warmup // 2)):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        whole_ms = (t1 - t0) * 1e3 / args.steps
 
     # stage breakdown (separate, event-recorded steps)
     nrec = 3
@@ -326,8 +503,10 @@ def main():
     clip_ms = build_ms[1]
     achieved = alg_flops / (clip_ms * 1e-3) / 1e12
     dtype = "f64" if prec == vt.PREC_FP64 else "f32"
+    counters = clip_counters() if prec == vt.PREC_FP64 else None
+    bench_vol, bench_off = vol.cpu().numpy(), off.cpu().numpy()
+    bench_ids, bench_rho = ids[: int(bench_off[-1])].cpu().numpy(), rho.cpu().numpy()
 
-    fwd_ms = stage_ms[0] + stage_ms[1] + stage_ms[2]
     out = {
         "metric": METRIC,
         "value": N / (ms_per_step * 1e-3),
@@ -342,11 +521,12 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "n_cells": N, "box": float(w.box_len[0]), "positions": str(w.pos.dtype),
-                   "grid": list(grid_dims) if not args.fwd_only else None, "precision": args.precision,
-                   "step": "build+cells+density" + ("" if args.fwd_only else "+gradient+grid+backward"),
+                   "precision": args.precision,
+                   "step": "build (sort + clip, facets kept) + neighbour CSR and volumes + densities",
                    "launch_options": tuned or "defaults"},
-        "fwd_cells_per_s": N / (fwd_ms * 1e-3),
-        "bwd_cells_per_s": (N / (stage_ms[5] * 1e-3)) if not args.fwd_only else None,
+        "whole_step": None if whole_ms is None else {
+            "ms": whole_ms, "cells_per_s": N / (whole_ms * 1e-3), "grid": list(grid_dims),
+            "step": "build + cells + density + gradient + grid deposit + adjoint"},
         "stage_ms": {"build": stage_ms[0], "cells": stage_ms[1], "density": stage_ms[2],
                      "gradient": stage_ms[3], "grid": stage_ms[4], "backward": stage_ms[5],
                      "sort": build_ms[0], "clip": build_ms[1], "clip_large": build_ms[2]},
@@ -356,9 +536,17 @@ def main():
                      "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype],
                      "traffic": measured_traffic() if prec == vt.PREC_FP64 else None,
                      "alg_flops_per_launch": alg_flops, "launch_ms": clip_ms,
+                     "issued_fp64_lane_flops_per_alg_flop": (counters["fp64_wave_flops"] * 64.0 / alg_flops)
+                     if counters else None,
+                     "valu_busy": counters["valu_busy"] if counters else None,
+                     "valu_lane_utilisation": counters["valu_lane_util"] if counters else None,
                      "mean_planes": float(npl.mean()), "mean_vertices": float(nv.mean()),
                      "mean_tested": float(ntest.to(torch.float64).mean())},
     }
+    gc = grid_counters()
+    if gc and not args.fwd_only:
+        out["grid_roofline"] = dict(gc, kernel="k_grid_fused (256^3 deposit)", bound="alu",
+                                    launch_ms=stage_ms[4])
 
     if not args.fwd_only:
         # the cheaper grid variant: nearest-particle sampling at the same grid
@@ -454,10 +642,17 @@ def main():
         torch.cuda.empty_cache()
         out["decomposed"] = decomposed_form(torch, vt, w)
 
+    if not args.no_extra:
+        torch.cuda.empty_cache()
+        out["backward"] = backward_form(torch, vt)
+        out["other_configs"] = other_configs(torch, vt)
+
     if not args.no_cpu_baseline:
         import oracle
 
-        nthr = min(os.cpu_count() or 1, 16)
+        # the machine's CPU share is 16 cores whatever the host shows; the oracle runs its OpenMP loop
+        # over that many threads, and once more on one thread (a smaller sample)
+        nthr = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1), 16)
         rng = np.random.default_rng(12345)
         sample = np.sort(rng.choice(N, min(args.cpu_sample, N), replace=False))
         p64 = w.pos.astype(np.float64)
@@ -466,19 +661,22 @@ def main():
         ref = oracle.cells(p64, w.box_lo, w.box_hi, query=sample, nthreads=nthr)
         dens = oracle.density(w.mass[sample], ref.volume)
         tb = time.perf_counter()
+        one = sample[: max(16, len(sample) // 32)]
+        tc = time.perf_counter()
+        oracle.cells(p64, w.box_lo, w.box_hi, query=one, nthreads=1)
+        td = time.perf_counter()
         out["cpu_baseline"] = {"value": len(sample) / (tb - ta), "unit": "cells/s", "cores": nthr, "kind": "oracle",
                                "sample": "%d seeded cells of the same workload (neighbours+volume+density, "
                                          "brute force over all %d particles per cell), %.1f s wall" %
-                                         (len(sample), N, tb - ta)}
+                                         (len(sample), N, tb - ta),
+                               "one_thread": {"value": len(one) / (td - tc), "cells": int(len(one))},
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         # parity of the benchmarked configuration on the same sample
-        vol_h = vol.cpu().numpy()
-        off_h = off.cpu().numpy()
-        ids_h = ids.cpu().numpy()
-        same = all(np.array_equal(ids_h[off_h[i]:off_h[i + 1]], ref.neighbours(q)) for q, i in enumerate(sample))
-        rel = np.abs(vol_h[sample] - ref.volume) / ref.volume
+        same = all(np.array_equal(bench_ids[bench_off[i]:bench_off[i + 1]], ref.neighbours(q))
+                   for q, i in enumerate(sample))
+        rel = np.abs(bench_vol[sample] - ref.volume) / ref.volume
         out["parity_on_sample"] = {"neighbours_bit_exact": bool(same), "max_rel_volume_err": float(rel.max()),
-                                   "max_rel_density_err": float(np.max(np.abs(
-                                       rho.cpu().numpy()[sample] - dens) / dens))}
+                                   "max_rel_density_err": float(np.max(np.abs(bench_rho[sample] - dens) / dens))}
     print(json.dumps(out))
 
 

@@ -94,16 +94,39 @@ typedef struct {
     double hi[3];
 } vt_item;
 
-/* Options; a zero field selects the default. */
+/*
+ * Options; a zero field selects the default.  None of them changes a result, only speed (the
+ * cell is certified by the security radius whatever the search does).
+ *   radius_factor, k_init  the first search shell: its radius in local mean spacings, or the
+ *                          number of particles it should hold on average (k_init, which sets
+ *                          radius_factor = (3 k_init / (4 pi))^(1/3) when given).  Later
+ *                          shells grow until the security radius is reached, with no cap on k
+ *                          other than the box (a periodic cell must stay within a quarter
+ *                          period, else VT_ERR_BOX_TOO_SMALL).
+ *   pts_per_grid_cell      resolution of the uniform-grid (Morton level) table of the kNN
+ *                          search: level T = round(log8(n / pts_per_grid_cell)), clamped to
+ *                          [1, 9], per item (default 1).
+ *   waves_per_cu           resident wavefronts of the persistent clip kernel (one cell per
+ *                          wavefront; cells that outgrow 64 vertices move to a kernel with one
+ *                          wavefront per block and 256 vertex slots).
+ *   cell_mapping           which cells each wavefront takes (VT_MAP_*).
+ */
 typedef struct {
-    int32_t precision;     /* vt_precision, default VT_PREC_FP64 */
-    int32_t want_faces;    /* keep facet areas and centroids (needed by vt_backward) */
-    float radius_factor;   /* first search radius in local mean spacings (default 2.0) */
-    float area_eps;        /* facets with area <= area_eps * V^(2/3) are not facets (default 1e-12) */
-    int32_t waves_per_cu;  /* persistent clip kernel occupancy (default 16) */
-    int32_t timing;        /* record HIP events around the sort and clip kernels (see vt_timings) */
-    int32_t reserved[2];
+    int32_t precision;       /* vt_precision, default VT_PREC_FP64 */
+    int32_t want_faces;      /* keep facet areas and centroids (needed by vt_backward) */
+    float radius_factor;     /* first search radius in local mean spacings (default 2.0) */
+    float area_eps;          /* facets with area <= area_eps * V^(2/3) are not facets (default 1e-12) */
+    int32_t waves_per_cu;    /* persistent clip kernel occupancy (default 16) */
+    int32_t timing;          /* record HIP events around the sort and clip kernels (see vt_timings) */
+    float pts_per_grid_cell; /* kNN grid resolution, particles per finest table cell (default 1) */
+    int32_t k_init;          /* first shell in particles (overrides radius_factor when > 0) */
+    int32_t cell_mapping;    /* VT_MAP_*: which cells the clip kernel's wavefronts take (default XCD segments) */
+    int32_t reserved;
 } vt_opts;
+
+/* vt_opts.cell_mapping: how the persistent clip kernel deals cells (in Morton order) to wavefronts */
+#define VT_MAP_XCD 0     /* each XCD (its own L2) takes a contiguous eighth, then helps the others */
+#define VT_MAP_GLOBAL 1  /* one queue: consecutive cells go to wavefronts on all XCDs in turn */
 
 /*
  * vt_build -- tessellate.  Sorts the particles of each item along a Morton
@@ -216,6 +239,7 @@ vt_status vt_grid_sample(vt_ctx *ctx, const double *value, int32_t nx, int32_t n
  */
 vt_status vt_grid_tensor(vt_ctx *ctx, const double *grid, int32_t nx, int32_t ny, int32_t nz, int32_t kind,
                          double *out, void *stream);
+
 
 /*
  * vt_structure -- the full tessellation structure of the owned cells (the

@@ -36,6 +36,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 TENSOR_TIDAL, TENSOR_HESSIAN = 0, 1
 TENSOR_COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
 CELL_INCOMPLETE, CELL_RETRIED, CELL_FAILED = 1, 2, 4
+MAP_XCD, MAP_GLOBAL = 0, 1
 
 
 class VTError(RuntimeError):
@@ -58,7 +59,8 @@ class vt_border(ctypes.Structure):
 class vt_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("want_faces", ctypes.c_int32), ("radius_factor", ctypes.c_float),
                 ("area_eps", ctypes.c_float), ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("pts_per_grid_cell", ctypes.c_float), ("k_init", ctypes.c_int32), ("cell_mapping", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def _load_cdll():
@@ -259,7 +261,8 @@ class Context:
             pass
 
     def vt_build(self, pos, items, global_id=None, precision=PREC_FP64, want_faces=False, radius_factor=0.0,
-                 area_eps=0.0, waves_per_cu=0, timing=False, stream=None):
+                 area_eps=0.0, waves_per_cu=0, timing=False, pts_per_grid_cell=0.0, k_init=0, cell_mapping=0,
+                 stream=None):
         import torch
 
         _require_cuda(pos, "pos")
@@ -282,6 +285,9 @@ class Context:
         o.area_eps = float(area_eps)
         o.waves_per_cu = int(waves_per_cu)
         o.timing = 1 if timing else 0
+        o.pts_per_grid_cell = float(pts_per_grid_cell)
+        o.k_init = int(k_init)
+        o.cell_mapping = int(cell_mapping)
         arr = _items(items)
         self._keep = [pos, global_id]
         _check(lib().vt_build(ctypes.byref(self._ctx), _ptr(pos), dt, _ptr(global_id), arr, len(items),

@@ -1,30 +1,33 @@
 """Autotuner for the build's launch options.
 
-Two knobs change only speed, never results:
-  * ``radius_factor`` -- the first search shell in local mean spacings, i.e. how
-    many candidates the first clipping pass gathers (the paper's equivalent is
-    the buffer thickness, section 2: too thin needs more passes, too thick
+The knobs change only speed, never results (every cell is certified by its security radius
+whatever the search does):
+  * ``k_init`` -- the first search shell, as the number of particles it holds on average (the
+    paper's equivalent is the buffer thickness, section 2: too thin needs more passes, too thick
     wastes work);
-  * ``waves_per_cu`` -- how many wavefronts (one cell each) the persistent
-    clipping kernel keeps resident per compute unit.
+  * ``pts_per_grid_cell`` -- the resolution of the uniform-grid (Morton level) table the kNN
+    search walks: about this many particles per finest cell;
+  * ``waves_per_cu`` -- how many wavefronts (one cell each) the persistent clipping kernel keeps
+    resident per compute unit.
 
-``tune`` times ``vt_build`` with device events for each candidate on the
-caller's inputs (or a representative subset of items), keeps the fastest, and
-caches the choice per input signature for the life of the process.
+``tune`` times ``vt_build`` with device events for each candidate on the caller's inputs (or a
+representative subset of items), keeps the fastest, and caches the choice per input signature
+for the life of the process.
 """
 from __future__ import annotations
 
 import itertools
 
-RADIUS_FACTORS = (1.8, 2.0, 2.3, 2.6)
+K_INITS = (24, 34, 50, 74)
+PTS_PER_GRID_CELL = (1.0, 0.125)
 WAVES_PER_CU = (8, 12)
 
 _cache = {}
 
 
-def candidates(radius_factors=RADIUS_FACTORS, waves_per_cu=WAVES_PER_CU):
-    return [dict(radius_factor=float(r), waves_per_cu=int(w)) for r, w in itertools.product(radius_factors,
-                                                                                           waves_per_cu)]
+def candidates(k_inits=K_INITS, pts_per_grid_cell=PTS_PER_GRID_CELL, waves_per_cu=WAVES_PER_CU):
+    return [dict(k_init=int(k), pts_per_grid_cell=float(g), waves_per_cu=int(w))
+            for k, g, w in itertools.product(k_inits, pts_per_grid_cell, waves_per_cu)]
 
 
 def signature(device_name, dtype, n_total, n_items, precision):

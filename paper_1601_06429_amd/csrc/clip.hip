@@ -69,6 +69,7 @@ struct ClipArgs {
     int want_faces;
     float radius_factor;
     float area_eps;
+    int xcd_segments;         // fast kernel: 1 = one queue; VT_XCD_SEGMENTS = per-XCD Morton segments
 };
 
 __device__ __forceinline__ int find_item_d(const DevItem *items, int n_items, int64_t p) {
@@ -160,12 +161,30 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
     const uint64_t mybit = 1ull << lane;
 
     const int64_t ntodo = RETRY ? (int64_t)min((uint64_t)A.counters[CTR_QUEUE], (uint64_t)A.queue_cap) : A.ncells;
+    // Work distribution.  The large kernel (and the one-queue mapping) hands out cells from one
+    // counter.  With XCD segments, the cells (in Morton order) are cut into nseg contiguous
+    // segments; a wavefront of workgroup b starts on segment b % nseg, the XCD its workgroup runs
+    // on, so each XCD's L2 serves one compact region, and when that segment is exhausted the
+    // wavefront moves to the next one, until it has found all nseg exhausted.  Every counter only
+    // grows and a segment is left only once exhausted, so every cell is taken exactly once and
+    // every wavefront exits after at most nseg exhausted segments.
+    const int nseg = RETRY ? 1 : A.xcd_segments;
+    int seg = RETRY ? 0 : (int)(blockIdx.x % (unsigned)nseg);
+    int left = nseg;
 
     for (;;) {
+        const int64_t s_lo = RETRY ? 0 : ntodo * seg / nseg, s_hi = RETRY ? ntodo : ntodo * (seg + 1) / nseg;
         int64_t w = 0;
-        if (lane == 0) w = (int64_t)atomicAdd(&A.counters[RETRY ? CTR_RETRY : CTR_CELL], 1u);
-        w = (int64_t)uni_i((int)__shfl((long long)w, 0));
-        if (w >= ntodo) break;
+        if (lane == 0) {
+            uint32_t *ctr = RETRY ? &A.counters[CTR_RETRY] : nseg == 1 ? &A.counters[CTR_CELL] : &A.counters[CTR_SEG0 + seg];
+            w = (int64_t)atomicAdd(ctr, 1u);
+        }
+        w = (int64_t)uni_i((int)__shfl((long long)w, 0)) + s_lo;
+        if (w >= s_hi) {
+            if (--left == 0) break;
+            seg = seg + 1 == nseg ? 0 : seg + 1;
+            continue;
+        }
         const int32_t cslot = uni_i(RETRY ? A.queue[w] : (int32_t)w);
         const int32_t j0 = uni_i(A.cells[cslot]);
         const int bi = uni_i(find_item_d(A.items, A.n_items, j0));
@@ -914,6 +933,7 @@ hipError_t vt_launch_clip(vt_ctx *c) {
     a.want_faces = c->opts.want_faces ? 1 : 0;
     a.radius_factor = c->opts.radius_factor > 0 ? c->opts.radius_factor : 2.0f;
     a.area_eps = c->opts.area_eps > 0 ? c->opts.area_eps : 1e-12f;
+    a.xcd_segments = c->opts.cell_mapping == VT_MAP_GLOBAL ? 1 : VT_XCD_SEGMENTS;
     const bool mixed = c->opts.precision == VT_PREC_MIXED;
     if (c->dtype == VT_F32) return mixed ? launch_prec<float, float4>(c, a) : launch_prec<double, float4>(c, a);
     return mixed ? launch_prec<float, double4>(c, a) : launch_prec<double, double4>(c, a);

@@ -188,17 +188,11 @@ static hipError_t fft3(double2 *d, const int n[3], double sign, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind, double *out) {
+// The transforms of one call: the grid's spectrum F and the work array G (ntot complex values
+// each, both fully written before they are read).
+static hipError_t grid_tensor_into(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind, double *out,
+                                   double2 *F, double2 *G) {
     const int64_t ntot = (int64_t)nx * ny * nz;
-    if (c->cap_spec < ntot) {
-        (void)hipFree(c->spec_buf);
-        c->spec_buf = nullptr;
-        c->cap_spec = 0;
-        hipError_t e = hipMalloc(&c->spec_buf, sizeof(double2) * 2 * (size_t)ntot);
-        if (e != hipSuccess) return e;
-        c->cap_spec = ntot;
-    }
-    double2 *F = (double2 *)c->spec_buf, *G = F + ntot;
     const int n[3] = {nx, ny, nz};
     const unsigned nb = (unsigned)((ntot + 255) / 256);
     k_real_to_complex<<<nb, 256, 0, c->stream>>>(grid, F, ntot);
@@ -222,6 +216,20 @@ hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, 
         k_unpack<<<nb, 256, 0, c->stream>>>(G, out + a.ca * ntot, out + a.cb * ntot, ntot, scale);
     }
     return hipGetLastError();
+}
+
+hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind, double *out) {
+    const int64_t ntot = (int64_t)nx * ny * nz;
+    if (c->cap_spec < ntot) {
+        (void)hipFree(c->spec_buf);
+        c->spec_buf = nullptr;
+        c->cap_spec = 0;
+        hipError_t e = hipMalloc(&c->spec_buf, sizeof(double2) * 2 * (size_t)ntot);
+        if (e != hipSuccess) return e;
+        c->cap_spec = ntot;
+    }
+    double2 *F = (double2 *)c->spec_buf;
+    return grid_tensor_into(c, grid, nx, ny, nz, kind, out, F, F + ntot);
 }
 
 void vt_spec_free(vt_ctx *c) {

@@ -79,8 +79,9 @@ vt_status hip_fail(hipError_t e, const char *what, int line) {
 // unrelated runtime call may have left there before enqueueing anything.
 void clear_stale_error() { (void)hipGetLastError(); }
 
-int table_level(int64_t count) {
-    int T = (int)lround(log((double)std::max<int64_t>(count, 1)) / log(8.0));
+// level of the dense Morton table: about pts particles per finest cell
+int table_level(int64_t count, double pts) {
+    int T = (int)lround(log((double)std::max<int64_t>(count, 1) / pts) / log(8.0));
     return std::min(std::max(T, 1), 9);
 }
 
@@ -128,6 +129,12 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
     vt_opts o{};
     if (opts) o = *opts;
     if (o.precision != VT_PREC_FP64 && o.precision != VT_PREC_MIXED) return VT_ERR_ARG;
+    if (!(o.pts_per_grid_cell >= 0.0f) || o.pts_per_grid_cell > 4096.0f || o.k_init < 0 || o.k_init > 100000 ||
+        !(o.radius_factor >= 0.0f) || o.radius_factor > 64.0f || o.waves_per_cu < 0 ||
+        (o.cell_mapping != VT_MAP_XCD && o.cell_mapping != VT_MAP_GLOBAL))
+        return VT_ERR_ARG;
+    if (o.pts_per_grid_cell == 0.0f) o.pts_per_grid_cell = 1.0f;
+    if (o.k_init > 0) o.radius_factor = (float)cbrt(3.0 * o.k_init / (4.0 * M_PI));
 
     vt_ctx *c = *pctx;
     if (!c) {
@@ -166,7 +173,7 @@ vt_status vt_build(vt_ctx **pctx, const void *pos, vt_dtype dtype, const int32_t
         d.count = it.n_owned + it.n_ghost;
         d.n_owned = it.n_owned;
         d.owned_base = owned_base;
-        d.T = table_level(d.count);
+        d.T = table_level(d.count, o.pts_per_grid_cell);
         d.tab_off = tab_total;
         d.periodic = it.periodic ? 1 : 0;
         d.walls = it.periodic ? 0 : it.walls;

@@ -37,7 +37,9 @@
 #define CTR_GRID_Q 10      // grid deposit: cells handed from the normal to the large kernel
 #define CTR_STRUCT_Q 11    // structure output: cells handed from the normal to the large kernel
 #define CTR_REC_REJECT 12  // topology records that failed their checks (a clip-kernel fault; 0 expected)
-#define CTR_COUNT 13
+#define CTR_SEG0 13        // fast clip kernel: work counters of the XCD segments (VT_XCD_SEGMENTS words)
+#define VT_XCD_SEGMENTS 8  // XCDs of an MI355X; workgroups are dealt to them round-robin
+#define CTR_COUNT (CTR_SEG0 + VT_XCD_SEGMENTS)
 
 // per-item description on the device
 struct DevItem {
