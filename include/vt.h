@@ -240,6 +240,26 @@ vt_status vt_grid_sample(vt_ctx *ctx, const double *value, int32_t nx, int32_t n
 vt_status vt_grid_tensor(vt_ctx *ctx, const double *grid, int32_t nx, int32_t ny, int32_t nz, int32_t kind,
                          double *out, void *stream);
 
+/* Largest grid (points) vt_grid_tensor_noalloc takes: 2^21, e.g. 128^3 (64 MiB of scratch). */
+#define VT_NOALLOC_TENSOR_POINTS (1 << 21)
+
+/*
+ * vt_grid_tensor_noalloc -- vt_grid_tensor for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same result, bit for bit, with the 32 bytes per
+ * grid point of FFT scratch taken from a static device array of the library
+ * instead of the context.  The array holds VT_NOALLOC_TENSOR_POINTS points; each
+ * device the library runs this on keeps its own copy (64 MiB) until the process
+ * ends.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).  Every call on one device shares that device's array, so
+ * calls that overlap on one device (different streams, or different host
+ * threads) race and must be serialised by the caller; the array needs no
+ * clearing between calls (each call writes its scratch before reading it).
+ * Arguments as vt_grid_tensor; nx * ny * nz above VT_NOALLOC_TENSOR_POINTS is
+ * rejected with VT_ERR_ARG (synchronously, nothing enqueued).
+ */
+vt_status vt_grid_tensor_noalloc(vt_ctx *ctx, const double *grid, int32_t nx, int32_t ny, int32_t nz, int32_t kind,
+                                 double *out, void *stream);
 
 /*
  * vt_structure -- the full tessellation structure of the owned cells (the

@@ -114,13 +114,14 @@ def lib():
                                               ctypes.POINTER(I32), P]
             L.vt_structure.argtypes = [P, P, P, I64, P, P, I64, P, P, I64, ctypes.POINTER(I64), P]
             L.vt_grid_tensor.argtypes = [P, P, I32, I32, I32, I32, P, P]
+            L.vt_grid_tensor_noalloc.argtypes = [P, P, I32, I32, I32, I32, P, P]
             L.vt_destroy.argtypes = [P]
             L.vt_destroy.restype = None
             L.vt_status_string.argtypes = [I32]
             L.vt_status_string.restype = ctypes.c_char_p
             for f in ("vt_build", "vt_cells", "vt_density", "vt_gradient", "vt_grid_deposit", "vt_backward",
                       "vt_query", "vt_stats", "vt_sizes", "vt_timings", "vt_decompose", "vt_decompose_pack",
-                      "vt_grid_sample", "vt_structure", "vt_grid_tensor", "vt_task_grid", "vt_border_thresholds",
+                      "vt_grid_sample", "vt_structure", "vt_grid_tensor", "vt_grid_tensor_noalloc", "vt_task_grid", "vt_border_thresholds",
                       "vt_decomposed_build"):
                 getattr(L, f).restype = ctypes.c_int32
             _lib = L
@@ -412,6 +413,16 @@ class Context:
         _check(lib().vt_grid_tensor(self._ctx, _ptr(grid), nx, ny, nz, int(kind), _ptr(o), _stream(stream)),
                "vt_grid_tensor")
         return o
+
+    def vt_grid_tensor_noalloc(self, grid, kind, out, stream=None):
+        """vt_grid_tensor with the library's static scratch instead of the context's: the caller
+        passes the output (6 x nx x ny x nz float64); nothing is allocated."""
+        _require_cuda(grid, "grid")
+        _require_cuda(out, "out")
+        nx, ny, nz = grid.shape
+        _check(lib().vt_grid_tensor_noalloc(self._ctx, _ptr(grid), nx, ny, nz, int(kind), _ptr(out),
+                                            _stream(stream)), "vt_grid_tensor_noalloc")
+        return out
 
     def vt_backward(self, dL_dV, out=None, stream=None):
         import torch

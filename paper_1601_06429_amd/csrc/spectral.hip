@@ -16,6 +16,8 @@
 // order), two stages per pass over the LDS; the twiddles are computed once per block with
 // sincospi in FP64.  Two real components go through one inverse transform as the real and
 // imaginary parts of one complex field.
+#include <mutex>
+
 #include "vt_internal.h"
 
 #define FFT_TPB 256
@@ -229,6 +231,45 @@ hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, 
         c->cap_spec = ntot;
     }
     double2 *F = (double2 *)c->spec_buf;
+    return grid_tensor_into(c, grid, nx, ny, nz, kind, out, F, F + ntot);
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+// Scratch for vt_grid_tensor_noalloc: the two complex work arrays of a grid of at most
+// VT_NOALLOC_TENSOR_POINTS points (64 MiB), one copy per device, held until the process ends.
+// In host code `scratch` names a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double2 scratch[2 * (size_t)VT_NOALLOC_TENSOR_POINTS];
+
+#define VT_MAX_DEVICES 64
+static void *g_scratch_ptr[VT_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// the calling thread's current device's copy of `scratch` (looked up once per device)
+static hipError_t scratch_address(double2 **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= VT_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = (double2 *)g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t vt_launch_grid_tensor_noalloc(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind,
+                                         double *out) {
+    const int64_t ntot = (int64_t)nx * ny * nz;
+    if (ntot > VT_NOALLOC_TENSOR_POINTS) return hipErrorInvalidValue;
+    double2 *F = nullptr;
+    hipError_t e = scratch_address(&F);
+    if (e != hipSuccess) return e;
     return grid_tensor_into(c, grid, nx, ny, nz, kind, out, F, F + ntot);
 }
 

@@ -324,6 +324,20 @@ vt_status vt_grid_tensor(vt_ctx *c, const double *grid, int32_t nx, int32_t ny, 
     return VT_OK;
 }
 
+vt_status vt_grid_tensor_noalloc(vt_ctx *c, const double *grid, int32_t nx, int32_t ny, int32_t nz, int32_t kind,
+                                 double *out, void *stream) {
+    if (!c || !c->built) return VT_ERR_STATE;
+    if (!grid || !out || c->n_items != 1 || !c->h_items || !c->h_items[0].periodic) return VT_ERR_ARG;
+    if (kind != VT_TENSOR_TIDAL && kind != VT_TENSOR_HESSIAN) return VT_ERR_ARG;
+    for (int32_t d : {nx, ny, nz})
+        if (d < 2 || d > 4096 || (d & (d - 1))) return VT_ERR_ARG;
+    if ((int64_t)nx * ny * nz > VT_NOALLOC_TENSOR_POINTS) return VT_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    clear_stale_error();
+    TRY(vt_launch_grid_tensor_noalloc(c, grid, nx, ny, nz, kind, out));
+    return VT_OK;
+}
+
 vt_status vt_structure(vt_ctx *c, int64_t *vert_off, double *verts, int64_t vert_cap, int64_t *face_off,
                        int32_t *face_nbr, int64_t face_cap, int64_t *loop_off, int32_t *loop_vert, int64_t loop_cap,
                        int64_t sizes[3], void *stream) {

@@ -192,6 +192,8 @@ hipError_t vt_launch_structure(vt_ctx *c, int64_t *vert_off, double *verts, int6
                                int64_t loop_cap, int64_t sizes[3], bool *fits);
 void vt_struct_free(vt_ctx *c);
 hipError_t vt_launch_grid_tensor(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind, double *out);
+hipError_t vt_launch_grid_tensor_noalloc(vt_ctx *c, const double *grid, int nx, int ny, int nz, int kind,
+                                         double *out);
 void vt_spec_free(vt_ctx *c);
 
 // ---------------------------------------------------------------- device helpers
