@@ -320,8 +320,10 @@ vt_status vt_query(vt_ctx *ctx, int64_t *nnz, int64_t *n_retried, int64_t *n_inc
 /*
  * vt_stats -- per-owned-cell diagnostics (device, n_owned_total int32 each,
  * output rows, any may be NULL): final vertex count, planes the security
- * criterion had to examine (particles closer than 2R, plus one), and
- * candidates actually tested.  Used by the benchmark's cost model.
+ * criterion had to examine (particles closer than 2R, R the cell's largest
+ * vertex distance, plus one; counted exactly by a pass of its own), and
+ * candidates the clip kernel actually tested.  Used by the benchmark's cost
+ * model.
  */
 vt_status vt_stats(vt_ctx *ctx, int32_t *n_vertices, int32_t *n_planes, int32_t *n_tested, void *stream);
 

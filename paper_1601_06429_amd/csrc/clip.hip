@@ -15,6 +15,8 @@
 // and applied one by one; the loop stops at the first candidate beyond 2R.
 // Cells that outgrow 64 vertices are handed to a second, persistent kernel
 // with room for 256.
+#include <algorithm>
+
 #include "poly.h"
 
 #define WAVE 64
@@ -58,7 +60,7 @@ struct ClipArgs {
     int32_t *ccnt;
     int64_t *crow;
     uint8_t *cstat;
-    int32_t *cnv, *cnp, *cnt;
+    int32_t *cnv, *cnt;
     int32_t *ctopo;           // fast kernel: topology record per cell (VT_TOPO_STRIDE words)
     int32_t *cnf;             // faces in the record, 0 = no record
     int32_t *stage_ids;
@@ -109,35 +111,53 @@ __device__ __forceinline__ void cell_range(const ClipArgs &A, const DevItem &it,
 }
 
 // local mean spacing around particle j0, from the particle count of the
-// smallest Morton cell containing it that holds between 8 and 64 particles
+// smallest Morton cell containing it that holds between 8 and 64 particles.
+// The counts of its cells at levels T .. T-3 are prefix differences in the
+// dense level-T table, read with independent loads; coarser levels and the
+// finer ones a crowded level-T cell needs (binary searches) follow as before.
 __device__ double local_spacing(const ClipArgs &A, const DevItem &it, int ib, int32_t j0) {
     const uint64_t lmask = (1ull << VT_LOCAL_KEY_BITS) - 1;
     const uint64_t key = A.skey[j0] & lmask;
-    int l = it.T;
-    uint64_t m = key >> (3 * (VT_MORTON_BITS - l));
-    int32_t b = A.tab[it.tab_off + (int64_t)m];
-    int32_t e = A.tab[it.tab_off + (int64_t)m + 1];
-    int cnt = e - b;
+    const int T = it.T;
+    int cnt4[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int l = T - d < 0 ? 0 : T - d;
+        const int sh = 3 * (T - l);
+        const uint64_t ml = key >> (3 * (VT_MORTON_BITS - l));
+        cnt4[d] = A.tab[it.tab_off + (int64_t)((ml + 1) << sh)] - A.tab[it.tab_off + (int64_t)(ml << sh)];
+    }
+    int l = T, cnt = cnt4[0];
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+        if (cnt < 8 && l > 0) {
+            --l;
+            cnt = cnt4[d];
+        }
+    int32_t b = 0, e = 0;
     while (cnt < 8 && l > 0) {
         --l;
-        int sh = 3 * (it.T - l);
-        uint64_t ml = key >> (3 * (VT_MORTON_BITS - l));
-        b = A.tab[it.tab_off + (int64_t)(ml << sh)];
-        e = A.tab[it.tab_off + (int64_t)((ml + 1) << sh)];
-        cnt = e - b;
+        const int sh = 3 * (T - l);
+        const uint64_t ml = key >> (3 * (VT_MORTON_BITS - l));
+        cnt = A.tab[it.tab_off + (int64_t)((ml + 1) << sh)] - A.tab[it.tab_off + (int64_t)(ml << sh)];
+    }
+    if (cnt > 64 && l == T) {
+        const uint64_t m = key >> (3 * (VT_MORTON_BITS - T));
+        b = A.tab[it.tab_off + (int64_t)m];
+        e = A.tab[it.tab_off + (int64_t)m + 1];
     }
     const uint64_t base = (uint64_t)ib << VT_LOCAL_KEY_BITS;
-    while (cnt > 64 && l < VT_MORTON_BITS) {
+    while (cnt > 64 && l >= T && l < VT_MORTON_BITS) {
         ++l;
-        int sh = 3 * (VT_MORTON_BITS - l);
-        uint64_t ml = key >> sh;
-        int32_t nb = lower_bound_key(A.skey, b, e, base | (ml << sh));
-        int32_t ne = lower_bound_key(A.skey, nb, e, base | ((ml + 1) << sh));
+        const int sh = 3 * (VT_MORTON_BITS - l);
+        const uint64_t ml = key >> sh;
+        const int32_t nb = lower_bound_key(A.skey, b, e, base | (ml << sh));
+        const int32_t ne = lower_bound_key(A.skey, nb, e, base | ((ml + 1) << sh));
         b = nb;
         e = ne;
         cnt = e - b;
     }
-    double cs = it.S / (double)(1ll << l);
+    const double cs = it.S / (double)(1ll << l);
     return cs / cbrt((double)(cnt > 0 ? cnt : 1));
 }
 
@@ -212,7 +232,8 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
 
         uint32_t dup = 0;
         bool overflow = false, corrupt = false;
-        int ntested = 0, nplanes = 1;
+        int ntested = 0;
+        int ncut = 0;  // planes that have cut the cell so far
 
         // ---------------- search and clip
         // The first shell [0, r0) is fitted to LDS (a d^2 histogram picks a radius
@@ -234,8 +255,12 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         // [r/2, r), pruned by their distance to the seed (boxes widened by one
         // quantum, the rounding of the keys), empty ranges dropped; ranges go to
         // S.rb / S.rp compacted.  Returns the number of ranges; *total the particles.
+        // With `prune` (sweeps), a box is also dropped when no vertex's empty sphere
+        // (centre v, radius |v|, staged in S.u.f.vp with its error bound in S.u.f.fa)
+        // reaches it: a particle cuts the current cell only if it lies in such a
+        // sphere, and the cell only shrinks, so no particle of the box ever will.
         const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
-        auto cover = [&](double r, double rmin, int &total) -> int {
+        auto cover = [&](double r, double rmin, int &total, bool prune) -> int {
             int lvl = 0;
             double c = it.S;
             while (lvl < VT_MORTON_BITS && c >= r) {
@@ -279,8 +304,12 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     double dmin2 = 0.0, dmax2 = 0.0;
                     for (int a = 0; a < 3; ++a) {
                         double dn = 1e300, df = 1e300;
+                        // the window [a0, a0 + na) is centred on the seed, so its unwrapped boxes are
+                        // the nearest images; only a window that spans the whole period (wrapped to
+                        // [0, ncl)) needs the three images
+                        const bool all_img = it.periodic && na[a] == ncl;
                         for (int sh_ = -1; sh_ <= 1; ++sh_) {
-                            if (sh_ != 0 && !it.periodic) continue;
+                            if (sh_ != 0 && !all_img) continue;
                             const double off_ = sh_ * it.L[a];
                             const double blo_ = it.lo[a] + (double)u[a] * c - quantum + off_;
                             const double bhi_ = it.lo[a] + (double)(u[a] + 1) * c + quantum + off_;
@@ -292,6 +321,32 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                         dmax2 += df * df;
                     }
                     keep = dmin2 < r2 && dmax2 >= rmin2;
+                    if (keep && prune && !(it.periodic && (na[0] == ncl || na[1] == ncl || na[2] == ncl))) {
+                        // the box relative to the seed (the unwrapped window is the nearest image)
+                        double bl[3], bh[3];
+                        for (int a = 0; a < 3; ++a) {
+                            bl[a] = it.lo[a] + (double)u[a] * c - quantum - xs[a];
+                            bh[a] = it.lo[a] + (double)(u[a] + 1) * c + quantum - xs[a];
+                        }
+                        bool reached = false;
+#pragma unroll
+                        for (int s_ = 0; s_ < VPL; ++s_) {
+                            uint64_t m = P.alive[s_];
+                            while (m && !reached) {
+                                const int kv = __builtin_ctzll(m);
+                                m &= m - 1;
+                                const double *v = S.u.f.vp[s_ * 64 + kv];
+                                const double ex = fmax(0.0, fmax(bl[0] - v[0], v[0] - bh[0]));
+                                const double ey = fmax(0.0, fmax(bl[1] - v[1], v[1] - bh[1]));
+                                const double ez = fmax(0.0, fmax(bl[2] - v[2], v[2] - bh[2]));
+                                // radius |v|, widened for rounding and (mixed) the vertex error bound
+                                const double rv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * (1.0 + 1e-7) +
+                                                  2.0 * S.u.f.fa[s_ * 64 + kv];
+                                reached = ex * ex + ey * ey + ez * ez < rv * rv;
+                            }
+                        }
+                        keep = reached;
+                    }
                     if (keep) {
                         uint64_t cc[3];
                         for (int a = 0; a < 3; ++a) cc[a] = (uint64_t)(it.periodic ? (u[a] & (ncl - 1)) : u[a]);
@@ -323,18 +378,20 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             return uni_i(count);
         };
         // particle f of the flattened cover -> sorted index, separation, d^2
-        auto fetch = [&](int f, int ncq, int32_t &j, double &dx, double &dy, double &dz) -> double {
+        // particle f of the flattened cover -> its sorted index
+        auto locate = [&](int f, int ncq) -> int32_t {
             int lo = 0, hi = ncq - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
                 if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
             }
-            j = S.rb[lo] + (f - S.rp[lo]);
-            double px, py, pz;
-            load_pos<PT4>(A.spos, j, px, py, pz);
-            dx = px - sx;
-            dy = py - sy;
-            dz = pz - sz;
+            return S.rb[lo] + (f - S.rp[lo]);
+        };
+        // a loaded position -> separation from the seed (minimum image), d^2
+        auto separation = [&](const PT4 &p, double &dx, double &dy, double &dz) -> double {
+            dx = (double)p.x - sx;
+            dy = (double)p.y - sy;
+            dz = (double)p.z - sz;
             if (it.periodic) {
                 dx -= it.L[0] * rint(dx * invL[0]);
                 dy -= it.L[1] * rint(dy * invL[1]);
@@ -348,15 +405,38 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         auto sweep = [&](double r_lo, double r_hi) {
             const double rl2 = r_lo * r_lo, rh2 = r_hi * r_hi;
             int total;
-            const int ncq = cover(r_hi, r_lo, total);
-            bool dirty = true;
+            // stage the cell's vertices for the box pruning of the cover (and the first chunk)
+            P.update_r2();
+#pragma unroll
+            for (int s = 0; s < VPL; ++s)
+                if (P.alive[s] & mybit) {
+                    S.u.f.vp[s * 64 + lane][0] = (double)P.vx[s];
+                    S.u.f.vp[s * 64 + lane][1] = (double)P.vy[s];
+                    S.u.f.vp[s * 64 + lane][2] = (double)P.vz[s];
+                    S.u.f.fa[s * 64 + lane] = (double)P.ve[s];
+                }
+            wave_sync();
+            const int ncq = cover(r_hi, r_lo, total, true);
+            bool dirty = false;
+            // positions of the next 64 particles are loaded while the current 64 are tested
+            int32_t jn = -1;
+            PT4 pn{};
+            if (lane < total) {
+                jn = locate(lane, ncq);
+                pn = ((const PT4 *)A.spos)[jn];
+            }
             for (int base = 0; base < total && !overflow && !corrupt; base += WAVE) {
                 const int f = base + lane;
                 bool keep = false;
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
-                int32_t j = -1;
+                const int32_t j = jn;
+                const PT4 pc = pn;
+                if (f + WAVE < total) {
+                    jn = locate(f + WAVE, ncq);
+                    pn = ((const PT4 *)A.spos)[jn];
+                }
                 if (f < total) {
-                    d2 = fetch(f, ncq, j, dx, dy, dz);
+                    d2 = separation(pc, dx, dy, dz);
                     if (j != j0) {
                         if (d2 == 0.0) dup = 1;
                         keep = (d2 > 0.0) && (d2 >= rl2) && (d2 < rh2) && (d2 < 4.0 * P.R2);
@@ -364,7 +444,6 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 }
                 const uint64_t km = __ballot(keep);
                 if (km == 0) continue;
-                nplanes += __popcll(km);
                 ntested += __popcll(km);
                 if (dirty) {
                     P.update_r2();
@@ -439,6 +518,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     const int rc = P.clip(S.P, p64, tag);
                     if (rc == CLIP_CUT) {
                         dirty = true;
+                        ++ncut;
                     } else if (rc == CLIP_OVERFLOW) {
                         overflow = true;
                         break;
@@ -457,18 +537,30 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             const double rh2 = r_next * r_next, rl2 = r_done * r_done;
             const double inv_rh2 = 1.0 / rh2, inv_bin = 64.0 / (rh2 - rl2);
             int total;
-            const int ncq = cover(r_next, r_done, total);
+            const int ncq = cover(r_next, r_done, total, false);
             S.hist[lane] = 0;
             wave_sync();
-            // ---- gather particles with r_done <= d < r_next (and a d^2 histogram)
+            // ---- gather particles with r_done <= d < r_next (and a d^2 histogram); the positions
+            // of the next 64 are loaded while the current 64 are processed
             int n = 0;
+            int32_t jn = -1;
+            PT4 pn{};
+            if (lane < total) {
+                jn = locate(lane, ncq);
+                pn = ((const PT4 *)A.spos)[jn];
+            }
             for (int base = 0; base < total; base += WAVE) {
                 const int f = base + lane;
                 bool keep = false;
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
-                int32_t j = -1;
+                const int32_t j = jn;
+                const PT4 pc = pn;
+                if (f + WAVE < total) {
+                    jn = locate(f + WAVE, ncq);
+                    pn = ((const PT4 *)A.spos)[jn];
+                }
                 if (f < total) {
-                    d2 = fetch(f, ncq, j, dx, dy, dz);
+                    d2 = separation(pc, dx, dy, dz);
                     if (j != j0) {
                         // a coincident particle has no bisector: report it, do not clip with it
                         if (d2 == 0.0) dup = 1;
@@ -493,8 +585,11 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 n += __popcll(km);
             }
             wave_sync();
-            if (n > VT_CAND_MAX && r_done == 0.0 && refine < 16) {
-                // first shell too full: the largest b with at most VT_CAND_MAX particles in bins [0, b)
+            if (n > VT_CAND_MAX && (r_done == 0.0 || ncut < 4) && refine < 16) {
+                // Shell too full while the cell is still (nearly) the initial box: the first shell,
+                // or a later one when the earlier shells were empty (a sweep applies planes in
+                // chunk order, which on an unclipped box can grow the polytope past its slots).
+                // The largest b with at most VT_CAND_MAX particles in bins [r_done, b) bounds it.
                 const int h = S.hist[lane];
                 int tot;
                 const int pre = wave_excl_scan(h, &tot);
@@ -607,6 +702,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             const int rc = P.clip(S.P, p64, S.u.c.cid[slot]);
                             if (rc == CLIP_CUT) {
                                 stale = true;
+                                ++ncut;
                                 if (!RETRY && ++cuts == 8 && __popcll(am) >= 16) {
                                     pend = am;
                                     break;
@@ -625,14 +721,6 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     }
                 }
                 if (stale) P.update_r2();
-                // particles the security criterion had to examine in this shell
-                int cntp = 0;
-                for (int b2 = lane; b2 < n; b2 += 64) {
-                    double x = S.u.c.cd[b2][0], y = S.u.c.cd[b2][1], z = S.u.c.cd[b2][2];
-                    if (x * x + y * y + z * z < 4.0 * P.R2) ++cntp;
-                }
-                nplanes += wave_sum_i(cntp);
-                wave_sync();
             }
             if (overflow || corrupt) break;
             r_done = r_next;
@@ -672,7 +760,6 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 A.cstat[cslot] = VT_CELL_FAILED | (RETRY ? VT_CELL_RETRIED : 0);
                 A.cnv[cslot] = 0;
                 A.cnf[cslot] = 0;
-                A.cnp[cslot] = nplanes;
                 A.cnt[cslot] = ntested;
             }
             continue;
@@ -850,11 +937,165 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             A.cstat[cslot] = st;
             A.cnv[cslot] = nvert;
             A.cnf[cslot] = nf_rec;
-            A.cnp[cslot] = nplanes;
             A.cnt[cslot] = ntested;
             atomicAdd((unsigned long long *)&A.counters[CTR_NNZ_LO], (unsigned long long)kept);
         }
     }
+}
+
+// ---------------------------------------------------------------- cost-model statistic
+// P_i = |{j != i : d_ij < 2 R_i}| + 1 for every computed cell, R_i its largest vertex distance:
+// the particles the security criterion has to examine, counted exactly after the build (the clip
+// kernel itself may skip particles it can prove irrelevant).  One wavefront per cell: the Morton
+// boxes of side in [r/2, r) around the seed, r = 2 R; a box entirely inside the ball counts its
+// whole range, a box the sphere crosses has its particles tested one by one.
+struct PlanesMem {
+    int32_t rb[216];
+    int32_t rp[216];
+};
+
+template <typename PT4>
+__global__ void __launch_bounds__(256) k_planes(ClipArgs A, int32_t *out) {
+    __shared__ PlanesMem SM[4];
+    PlanesMem &S = SM[threadIdx.x >> 6];
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < A.ncells; c += nw) {
+        const uint8_t st = A.cstat[c];
+        if (st & VT_CELL_FAILED) {
+            if (lane == 0) out[c] = 0;
+            continue;
+        }
+        const int32_t j0 = A.cells[c];
+        const int bi = find_item_d(A.items, A.n_items, j0);
+        const DevItem &it = A.items[bi];
+        double xs[3];
+        load_pos<PT4>(A.spos, j0, xs[0], xs[1], xs[2]);
+        const double r = 2.0 * A.crad[c], r2 = r * r;
+        int lvl = 0;
+        double cside = it.S;
+        while (lvl < VT_MORTON_BITS && cside >= r) {
+            cside *= 0.5;
+            ++lvl;
+        }
+        const int sh = VT_MORTON_BITS - lvl;
+        const int64_t ncl = 1ll << lvl;
+        const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
+        int64_t a0[3];
+        int na[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t i0 = (vt_qraw(xs[a] - r, it.lo[a], it.inv_res) - 1) >> sh;
+            int64_t i1 = (vt_qraw(xs[a] + r, it.lo[a], it.inv_res) + 1) >> sh;
+            if (it.periodic) {
+                if (i1 - i0 + 1 >= ncl) {
+                    i0 = 0;
+                    i1 = ncl - 1;
+                }
+            } else {
+                if (i0 < 0) i0 = 0;
+                if (i1 > ncl - 1) i1 = ncl - 1;
+            }
+            a0[a] = i0;
+            na[a] = i1 >= i0 ? (int)(i1 - i0 + 1) : 0;
+        }
+        const int nbox = na[0] * na[1] * na[2];
+        int whole = 0, npart = 0;
+        for (int base = 0; base < nbox; base += WAVE) {
+            const int k = base + lane;
+            bool part = false;
+            int32_t b = 0, e = 0;
+            if (k < nbox) {
+                const int64_t u[3] = {a0[0] + k % na[0], a0[1] + (k / na[0]) % na[1], a0[2] + k / (na[0] * na[1])};
+                double dmin2 = 0.0, dmax2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const bool all_img = it.periodic && na[a] == ncl;
+                    double dn = 1e300, df = 1e300;
+                    for (int s_ = -1; s_ <= 1; ++s_) {
+                        if (s_ != 0 && !all_img) continue;
+                        const double lo_ = it.lo[a] + (double)u[a] * cside - quantum + s_ * it.L[a];
+                        const double hi_ = it.lo[a] + (double)(u[a] + 1) * cside + quantum + s_ * it.L[a];
+                        const double dl = lo_ - xs[a], dh = xs[a] - hi_;
+                        dn = fmin(dn, fmax(0.0, fmax(dl, dh)));
+                        df = fmin(df, fmax(fabs(dl), fabs(dh)));
+                    }
+                    dmin2 += dn * dn;
+                    dmax2 += df * df;
+                }
+                if (dmin2 < r2) {
+                    uint64_t cc[3];
+                    for (int a = 0; a < 3; ++a) cc[a] = (uint64_t)(it.periodic ? (u[a] & (ncl - 1)) : u[a]);
+                    cell_range(A, it, bi, lvl, cc[0], cc[1], cc[2], b, e);
+                    if (e > b) {
+                        // a box whose farthest point (over its images) is within r lies inside the ball
+                        // for the minimum-image distances too, which are no larger
+                        if (dmax2 < r2 && !(it.periodic && (na[0] == ncl || na[1] == ncl || na[2] == ncl)))
+                            whole += (e - b) - ((j0 >= b && j0 < e) ? 1 : 0);
+                        else
+                            part = true;
+                    }
+                }
+            }
+            const uint64_t pm = __ballot(part);
+            if (part) {
+                const int slot = npart + __popcll(pm & lt);
+                S.rb[slot] = b;
+                S.rp[slot] = e - b;
+            }
+            npart += __popcll(pm);
+        }
+        wave_sync();
+        int carry = 0;
+        for (int base = 0; base < npart; base += WAVE) {
+            const int k = base + lane;
+            const int len = k < npart ? S.rp[k] : 0;
+            int tot;
+            const int pre = wave_excl_scan(len, &tot);
+            if (k < npart) S.rp[k] = carry + pre;
+            carry += tot;
+        }
+        wave_sync();
+        int inside = 0;
+        for (int f = lane; f < carry; f += WAVE) {
+            int lo = 0, hi = npart - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            const int32_t j = S.rb[lo] + (f - S.rp[lo]);
+            if (j == j0) continue;
+            double px, py, pz;
+            load_pos<PT4>(A.spos, j, px, py, pz);
+            double dx = px - xs[0], dy = py - xs[1], dz = pz - xs[2];
+            if (it.periodic) {
+                dx -= it.L[0] * rint(dx / it.L[0]);
+                dy -= it.L[1] * rint(dy / it.L[1]);
+                dz -= it.L[2] * rint(dz / it.L[2]);
+            }
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 > 0.0 && d2 < r2) ++inside;
+        }
+        const int total = wave_sum_i(inside) + whole;
+        if (lane == 0) out[c] = total + 1;
+        wave_sync();
+    }
+}
+
+hipError_t vt_launch_planes(vt_ctx *c) {
+    ClipArgs a{};
+    a.spos = c->spos;
+    a.skey = c->skey;
+    a.tab = c->tab;
+    a.items = c->items;
+    a.n_items = c->n_items;
+    a.cells = c->cells;
+    a.ncells = c->n_owned;
+    a.crad = c->crad;
+    a.cstat = c->cstat;
+    const int64_t blocks = std::min<int64_t>((c->n_owned + 3) / 4, 256 * 16);
+    if (c->dtype == VT_F32) k_planes<float4><<<(unsigned)blocks, 256, 0, c->stream>>>(a, c->cnp);
+    else k_planes<double4><<<(unsigned)blocks, 256, 0, c->stream>>>(a, c->cnp);
+    return hipGetLastError();
 }
 
 // The fast kernel is register-capped at three resident waves per SIMD: the extra
@@ -923,7 +1164,6 @@ hipError_t vt_launch_clip(vt_ctx *c) {
     a.crow = c->crow;
     a.cstat = c->cstat;
     a.cnv = c->cnv;
-    a.cnp = c->cnp;
     a.cnt = c->cnt;
     a.ctopo = c->ctopo;
     a.cnf = c->cnf;

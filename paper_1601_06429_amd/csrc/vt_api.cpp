@@ -366,6 +366,7 @@ vt_status vt_stats(vt_ctx *c, int32_t *n_vertices, int32_t *n_planes, int32_t *n
     if (!c || !c->built) return VT_ERR_STATE;
     c->stream = (hipStream_t)stream;
     clear_stale_error();
+    if (n_planes) TRY(vt_launch_planes(c));
     TRY(vt_launch_stats(c, n_vertices, n_planes, n_tested));
     return VT_OK;
 }

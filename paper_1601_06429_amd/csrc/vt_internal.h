@@ -180,6 +180,7 @@ hipError_t vt_launch_grid_sample(vt_ctx *c, const double *value, int nx, int ny,
                                  int32_t *nearest);
 hipError_t vt_launch_backward(vt_ctx *c, const double *g, double *out);
 hipError_t vt_launch_stats(vt_ctx *c, int32_t *nv, int32_t *np, int32_t *nt);
+hipError_t vt_launch_planes(vt_ctx *c);  // exact planes-examined count of every cell into cnp
 hipError_t vt_launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 
 int64_t vt_scan_tmp_elems(int64_t n);
