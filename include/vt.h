@@ -129,11 +129,15 @@ typedef struct {
 #define VT_MAP_GLOBAL 1  /* one queue: consecutive cells go to wavefronts on all XCDs in turn */
 
 /*
- * vt_build -- tessellate.  Sorts the particles of each item along a Morton
- * curve, builds the per-item cell tables, then computes every owned cell by
- * clipping with bisector planes in increasing distance order until the
- * security radius certifies it (all particles closer than twice the largest
- * vertex distance have been used).
+ * vt_build -- tessellate.  The cell of a particle is the region closer to it
+ * than to any other particle (section 1; with periodic conditions, closer than
+ * to any periodic image).  A sub-volume is tessellated together with its
+ * buffer particles, which clip the owned cells but get none of their own
+ * (section 2, the buffer zone between tasks).  Sorts the particles of each item
+ * along a Morton curve, builds the per-item cell tables, then computes every
+ * owned cell by clipping with bisector planes in increasing distance order
+ * until the security radius certifies it (all particles closer than twice the
+ * largest vertex distance have been used).
  *   ctx        in/out: *ctx == NULL creates a context; a context from an
  *              earlier build is reused (its scratch grows only if needed).
  *   pos        device, n_total x 3 positions (AoS), dtype VT_F32 or VT_F64,
