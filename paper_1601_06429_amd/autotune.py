@@ -20,7 +20,7 @@ import itertools
 
 K_INITS = (24, 34, 50, 74)
 PTS_PER_GRID_CELL = (1.0, 0.125, 1.0 / 64)
-WAVES_PER_CU = (8, 12)
+WAVES_PER_CU = (12, 16)
 
 _cache = {}
 

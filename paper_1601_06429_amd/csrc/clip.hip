@@ -21,6 +21,10 @@
 
 #define WAVE 64
 
+// Face slots of the polytope: the fast kernel's cells have at most 64 vertices, so at most 34 faces,
+// and its topology record holds VT_TOPO_FACES; fewer slots than 64 leave LDS for a fourth wave per SIMD.
+__host__ __device__ constexpr int clip_faces(int vpl) { return vpl == 1 ? VT_TOPO_FACES : 64 * vpl; }
+
 template <typename T, int VPL>
 struct ClipMem {
     union {
@@ -39,7 +43,7 @@ struct ClipMem {
     int32_t rb[216];                     // gather: cell range starts
     int32_t rp[216];                     // gather: prefix of range lengths
     int32_t hist[64];                    // gather: d^2 histogram of the shell
-    PolyMem<T, VPL> P;
+    PolyMem<T, VPL, clip_faces(VPL)> P;
 };
 
 struct ClipArgs {
@@ -227,7 +231,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 bhi[a] = it.lo[a] + it.L[a] - xs[a];
             }
         }
-        Poly<T, VPL> P;
+        Poly<T, VPL, clip_faces(VPL)> P;
         P.init_box(S.P, blo, bhi);
 
         uint32_t dup = 0;
@@ -1098,11 +1102,11 @@ hipError_t vt_launch_planes(vt_ctx *c) {
     return hipGetLastError();
 }
 
-// The fast kernel is register-capped at three resident waves per SIMD: the extra
-// occupancy hides LDS latency better than the few spills cost.  The large kernel
-// (rare cells, four vertices per lane) keeps its registers.
+// The fast kernel is register-capped at four resident waves per SIMD (128 VGPRs; with 40 face
+// slots its LDS also fits four): the extra occupancy hides LDS latency better than the spills
+// cost.  The large kernel (rare cells, four vertices per lane) keeps its registers.
 template <typename T, typename PT4>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_clip(ClipArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_clip(ClipArgs A) {
     clip_cells<T, PT4, 1, false>(A);
 }
 

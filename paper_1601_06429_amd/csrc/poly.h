@@ -206,9 +206,12 @@ __device__ __forceinline__ T side(T x, T y, T z, const P4<T> &p) {
 }
 
 // ------------------------------------------------------------------ per-wave LDS
-template <typename T, int VPL>
+// NF face slots (at most 64 * VPL): a simple polytope with V vertices has V / 2 + 2 faces, so a
+// kernel bounded to 64 vertices needs 34 and may hold fewer slots than 64 to save LDS.
+template <typename T, int VPL, int NF = 64 * VPL>
 struct PolyMem {
-    static constexpr int PMAX = 64 * VPL;
+    static_assert(NF <= 64 * VPL && NF >= 8, "face slots");
+    static constexpr int PMAX = NF;
     static constexpr int VMAX = 64 * VPL;
     static constexpr bool MIXED = std::is_same<T, float>::value;
     P4<double> pl64[PMAX];             // planes in FP64 (walls: unit normal, d = distance)
@@ -224,9 +227,9 @@ struct PolyMem {
 
 enum { CLIP_NONE = 0, CLIP_CUT = 1, CLIP_OVERFLOW = -1, CLIP_CORRUPT = -2, CLIP_EMPTY = -3 };
 
-template <typename T, int VPL>
+template <typename T, int VPL, int NF = 64 * VPL>
 struct Poly {
-    using Mem = PolyMem<T, VPL>;
+    using Mem = PolyMem<T, VPL, NF>;
     static constexpr bool MIXED = Mem::MIXED;
     static constexpr int PMAX = Mem::PMAX;
     static constexpr float U32 = 5.9604645e-08f;  // 2^-24
@@ -294,7 +297,8 @@ struct Poly {
                 for (int k = 0; k < 8; ++k)
                     if ((((k >> a) & 1) != 0) == pos) m |= 1ull << k;
             }
-            for (int s2 = 0; s2 < VPL; ++s2) S.fm[f][s2] = (s2 == 0) ? m : 0ull;
+            if (f < PMAX)
+                for (int s2 = 0; s2 < VPL; ++s2) S.fm[f][s2] = (s2 == 0) ? m : 0ull;
         }
         double hx = fmax(-blo[0], bhi[0]), hy = fmax(-blo[1], bhi[1]), hz = fmax(-blo[2], bhi[2]);
         R2 = (hx * hx + hy * hy + hz * hz) * (1.0 + 1e-12);
@@ -366,7 +370,7 @@ struct Poly {
 #pragma unroll
         for (int s = 0; s < VPL; ++s)
             if (q < 0 && ~fa[s] != 0ull) q = s * 64 + __builtin_ctzll(~fa[s]);
-        if (q < 0) return CLIP_OVERFLOW;
+        if (q < 0 || q >= PMAX) return CLIP_OVERFLOW;
         // 3. cut edges: an edge of a clipped vertex whose twin vertex is kept
         int nbv[VPL];
         uint32_t emask[VPL];
