@@ -470,10 +470,10 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 // dist(v, box)^2 - |v|^2 above the margin gives sv < -marg for every particle of
                 // the chunk, so skipping it leaves each lane's answer unchanged; the particles of
                 // a chunk are close together (consecutive Morton ranges), so few vertices remain.
-                const double bx0 = uni_d(wave_min(keep ? dx : 1e300)), bx1 = uni_d(wave_max(keep ? dx : -1e300));
-                const double by0 = uni_d(wave_min(keep ? dy : 1e300)), by1 = uni_d(wave_max(keep ? dy : -1e300));
-                const double bz0 = uni_d(wave_min(keep ? dz : 1e300)), bz1 = uni_d(wave_max(keep ? dz : -1e300));
-                const double pmax = uni_d(sqrt(wave_max(keep ? d2 : 0.0)));
+                const double bx0 = uni_d(wave_min_x(keep ? dx : 1e300)), bx1 = uni_d(wave_max_x(keep ? dx : -1e300));
+                const double by0 = uni_d(wave_min_x(keep ? dy : 1e300)), by1 = uni_d(wave_max_x(keep ? dy : -1e300));
+                const double bz0 = uni_d(wave_min_x(keep ? dz : 1e300)), bz1 = uni_d(wave_max_x(keep ? dz : -1e300));
+                const double pmax = uni_d(sqrt(wave_max_x(keep ? d2 : 0.0)));
                 uint64_t vm[VPL];
 #pragma unroll
                 for (int s = 0; s < VPL; ++s) {
@@ -509,16 +509,16 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 uint64_t am = __ballot(keep && act);
                 while (am) {
                     const double key = (am & mybit) ? d2 : 1e300;
-                    const double mn = wave_min(key);
+                    const double mn = wave_min_x(key);
                     const uint64_t who = __ballot((am & mybit) && d2 == mn);
-                    const int k = __builtin_ctzll(who);
+                    const int k = uni_i(__builtin_ctzll(who));
                     am &= ~(1ull << k);
                     P4<double> p64;
-                    p64.x = __shfl(dx, k);
-                    p64.y = __shfl(dy, k);
-                    p64.z = __shfl(dz, k);
+                    p64.x = readlane_dbl(dx, k);
+                    p64.y = readlane_dbl(dy, k);
+                    p64.z = readlane_dbl(dz, k);
                     p64.d = 0.5 * (p64.x * p64.x + p64.y * p64.y + p64.z * p64.z);
-                    const int32_t tag = __shfl(j, k);
+                    const int32_t tag = (int32_t)readlane_u32((uint32_t)j, k);
                     const int rc = P.clip(S.P, p64, tag);
                     if (rc == CLIP_CUT) {
                         dirty = true;
@@ -611,9 +611,9 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 uint32_t k0 = (lane < n) ? S.u.c.ckey[lane] : 0xFFFFFFFFu;
                 uint32_t k1 = (lane + 64 < n) ? S.u.c.ckey[lane + 64] : 0xFFFFFFFFu;
                 if (n > 64)
-                    bitonic128(k0, k1);
+                    bitonic128_x(k0, k1);
                 else if (n > 1)
-                    k0 = bitonic64(k0);
+                    k0 = bitonic64_x(k0);
                 // ---- clip in increasing distance; stop at the first particle beyond 2R
                 auto q4r = [&](double r2) -> uint32_t {
                     double x = 4.0 * r2 / rh2 * 16777216.0;
@@ -785,9 +785,19 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 r2max = fmax(r2max, x * x + y * y + z * z);
             }
         }
+        // the global ids of the faces' particles (the neighbour keys), loaded while the areas are computed
+        int32_t tag_l = -1;
+        uint32_t gid_l = 0;
+        if constexpr (VPL == 1) {
+            if (P.fa[0] & mybit) {
+                tag_l = S.P.ptag[lane];
+                if (tag_l >= 0) gid_l = (uint32_t)A.sgid[tag_l];
+            }
+        }
         wave_sync();
         double vol_l = 0.0;
         double area_l[VPL];
+        double cen_l[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
             area_l[r] = 0.0;
@@ -844,43 +854,77 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             double A_ = at;
             area_l[r] = A_;
             vol_l += vf;
-            S.u.f.fa[f] = A_;
-            S.u.f.fc[f][0] = at > 0 ? Cx / at : v0[0];
-            S.u.f.fc[f][1] = at > 0 ? Cy / at : v0[1];
-            S.u.f.fc[f][2] = at > 0 ? Cz / at : v0[2];
+            if constexpr (VPL == 1) {
+                cen_l[0] = at > 0 ? Cx / at : v0[0];
+                cen_l[1] = at > 0 ? Cy / at : v0[1];
+                cen_l[2] = at > 0 ? Cz / at : v0[2];
+            } else {
+                S.u.f.fa[f] = A_;
+                S.u.f.fc[f][0] = at > 0 ? Cx / at : v0[0];
+                S.u.f.fc[f][1] = at > 0 ? Cy / at : v0[1];
+                S.u.f.fc[f][2] = at > 0 ? Cz / at : v0[2];
+            }
         }
         const double V = wave_sum_d(vol_l);
-        const double Rfin = sqrt(wave_max(r2max));
+        const double Rfin = sqrt(wave_max_x(r2max));
         const double amin = (double)(A.area_eps * exp2f(log2f((float)fabs(V)) * (2.0f / 3.0f)));
         // facets of positive area generated by particles -> neighbour rows, ascending global id
         uint64_t keys[VPL];
         uint32_t wall = 0;  // walls (bit f for tag -1 - f) among this lane's facets
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            const int f = r * 64 + lane;
-            keys[r] = ~0ull;
-            if ((P.fa[r] & mybit) && area_l[r] > amin) {
-                int32_t tag = S.P.ptag[f];
-                if (tag < 0) wall |= 1u << ((-1 - tag) & 7);
-                else keys[r] = ((uint64_t)(uint32_t)A.sgid[tag] << 9) | (uint64_t)f;
-            }
-        }
         int cnt = 0;
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) cnt += __popcll(__ballot(keys[r] != ~0ull));
-        bitonic_u64<VPL>(keys);
-        wave_sync();
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            int k = r * 64 + lane;
-            if (k < cnt && k < A.fstride) {
-                int f = (int)(keys[r] & 511ull);
-                A.stage_ids[row + k] = S.P.ptag[f];  // sorted index; mapped to global ids on output
+        if constexpr (VPL == 1) {
+            // each face lane holds its facet; its row is the rank of its key (global id, then slot)
+            // among the kept facets, counted over their keys read lane by lane
+            keys[0] = ~0ull;
+            if ((P.fa[0] & mybit) && area_l[0] > amin) {
+                if (tag_l < 0) wall |= 1u << ((-1 - tag_l) & 7);
+                else keys[0] = ((uint64_t)gid_l << 9) | (uint64_t)lane;
+            }
+            const uint64_t kept = __ballot(keys[0] != ~0ull);
+            cnt = __popcll(kept);
+            int rank = 0;
+            for (uint64_t m = kept; m; m &= m - 1) {
+                const int g = uni_i(__builtin_ctzll(m));
+                const uint64_t kg = ((uint64_t)readlane_u32((uint32_t)(keys[0] >> 32), g) << 32) |
+                                    (uint64_t)readlane_u32((uint32_t)keys[0], g);
+                rank += kg < keys[0] ? 1 : 0;
+            }
+            if (keys[0] != ~0ull && rank < A.fstride) {
+                A.stage_ids[row + rank] = tag_l;  // sorted index; mapped to global ids on output
                 if (A.want_faces) {
-                    A.stage_area[row + k] = S.u.f.fa[f];
-                    A.stage_cen[3 * (row + k) + 0] = S.u.f.fc[f][0];
-                    A.stage_cen[3 * (row + k) + 1] = S.u.f.fc[f][1];
-                    A.stage_cen[3 * (row + k) + 2] = S.u.f.fc[f][2];
+                    A.stage_area[row + rank] = area_l[0];
+                    A.stage_cen[3 * (row + rank) + 0] = cen_l[0];
+                    A.stage_cen[3 * (row + rank) + 1] = cen_l[1];
+                    A.stage_cen[3 * (row + rank) + 2] = cen_l[2];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) {
+                const int f = r * 64 + lane;
+                keys[r] = ~0ull;
+                if ((P.fa[r] & mybit) && area_l[r] > amin) {
+                    int32_t tag = S.P.ptag[f];
+                    if (tag < 0) wall |= 1u << ((-1 - tag) & 7);
+                    else keys[r] = ((uint64_t)(uint32_t)A.sgid[tag] << 9) | (uint64_t)f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) cnt += __popcll(__ballot(keys[r] != ~0ull));
+            bitonic_u64<VPL>(keys);
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) {
+                int k = r * 64 + lane;
+                if (k < cnt && k < A.fstride) {
+                    int f = (int)(keys[r] & 511ull);
+                    A.stage_ids[row + k] = S.P.ptag[f];  // sorted index; mapped to global ids on output
+                    if (A.want_faces) {
+                        A.stage_area[row + k] = S.u.f.fa[f];
+                        A.stage_cen[3 * (row + k) + 0] = S.u.f.fc[f][0];
+                        A.stage_cen[3 * (row + k) + 1] = S.u.f.fc[f][1];
+                        A.stage_cen[3 * (row + k) + 2] = S.u.f.fc[f][2];
+                    }
                 }
             }
         }

@@ -81,6 +81,138 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 
+// Reductions whose cross-lane steps stay in the VALU: DPP moves within rows of 16 lanes (swap
+// neighbours, swap pairs, mirror within 8, mirror within 16), then the gfx950 row swaps, which
+// leave every lane holding its own value and its partner's 16 and 32 lanes away (in one order or
+// the other: the operation is commutative, so either serves).  The result is in every lane.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <bool ROW32>
+__device__ __forceinline__ void row_swap_d(double x, double &a, double &b) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    uint32_t alo, blo, ahi, bhi;
+    if constexpr (ROW32) {
+        auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        alo = rl[0], blo = rl[1], ahi = rh[0], bhi = rh[1];
+    } else {
+        auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        alo = rl[0], blo = rl[1], ahi = rh[0], bhi = rh[1];
+    }
+    a = __longlong_as_double((long long)(((uint64_t)ahi << 32) | alo));
+    b = __longlong_as_double((long long)(((uint64_t)bhi << 32) | blo));
+}
+enum { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+template <bool MAX>
+__device__ __forceinline__ double wave_ext_d(double v) {
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    v = op(v, dpp_d<DPP_XOR1>(v));
+    v = op(v, dpp_d<DPP_XOR2>(v));
+    v = op(v, dpp_d<DPP_HALF_MIRROR>(v));
+    v = op(v, dpp_d<DPP_MIRROR>(v));
+    double a, b;
+    row_swap_d<false>(v, a, b);
+    v = op(a, b);
+    row_swap_d<true>(v, a, b);
+    return op(a, b);
+}
+__device__ __forceinline__ double wave_max_x(double v) { return wave_ext_d<true>(v); }
+__device__ __forceinline__ double wave_min_x(double v) { return wave_ext_d<false>(v); }
+
+// The value of lane l ^ J, without LDS: DPP for J < 16 (neighbour and pair swaps within quads;
+// for 4 and 8, shifts within the row whose bank mask picks the lanes that read upwards or
+// downwards), the gfx950 row swaps for 16 and 32 (each lane then holds its own value and its
+// partner's: the one that differs from its own, or either when they are equal).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t x) {
+    if constexpr (J == 1) {
+        return dpp_u32<DPP_XOR1>(x);
+    } else if constexpr (J == 2) {
+        return dpp_u32<DPP_XOR2>(x);
+    } else if constexpr (J == 4 || J == 8) {
+        constexpr int SHL = 0x100 + J, SHR = 0x110 + J;
+        constexpr int LOW = J == 4 ? 0x5 : 0x3;  // banks (4 lanes each) whose lanes have bit J clear
+        const int up = __builtin_amdgcn_update_dpp((int)x, (int)x, SHL, 0xF, LOW, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(up, (int)x, SHR, 0xF, 0xF ^ LOW, false);
+    } else {
+        static_assert(J == 16 || J == 32, "lane distance");
+        uint32_t a, b;
+        if constexpr (J == 16) {
+            auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+            a = r[0];
+            b = r[1];
+        } else {
+            auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+            a = r[0];
+            b = r[1];
+        }
+        return a != x ? a : b;
+    }
+}
+
+// one compare-exchange stage of a bitonic network at lane distance J (size: the merge size)
+template <int J>
+__device__ __forceinline__ uint32_t bitonic_step(uint32_t k, int e, int size, bool last) {
+    const uint32_t o = xor_lane_u32<J>(k);
+    const bool up = (e & size) == 0 || last;
+    const bool lower = (e & J) == 0;
+    const uint32_t mn = k < o ? k : o, mx = k < o ? o : k;
+    return (lower == up) ? mn : mx;
+}
+template <int J>
+__device__ __forceinline__ void bitonic_merge(uint32_t &k, int e, int size, bool last) {
+    k = bitonic_step<J>(k, e, size, last);
+    if constexpr (J > 1) bitonic_merge<J / 2>(k, e, size, last);
+}
+
+// bitonic64 / bitonic128 with the cross-lane steps above (same networks, same results)
+__device__ __forceinline__ uint32_t bitonic64_x(uint32_t k) {
+    const int l = lane_id();
+    bitonic_merge<1>(k, l, 2, false);
+    bitonic_merge<2>(k, l, 4, false);
+    bitonic_merge<4>(k, l, 8, false);
+    bitonic_merge<8>(k, l, 16, false);
+    bitonic_merge<16>(k, l, 32, false);
+    bitonic_merge<32>(k, l, 64, true);
+    return k;
+}
+__device__ __forceinline__ void bitonic128_x(uint32_t &k0, uint32_t &k1) {
+    const int l = lane_id();
+#define VT_BM2(J, SIZE)                          \
+    bitonic_merge<J>(k0, l, SIZE, false);        \
+    bitonic_merge<J>(k1, 64 + l, SIZE, false);
+    VT_BM2(1, 2)
+    VT_BM2(2, 4)
+    VT_BM2(4, 8)
+    VT_BM2(8, 16)
+    VT_BM2(16, 32)
+    VT_BM2(32, 64)
+#undef VT_BM2
+    // size 128: the exchange at distance 64 is between the two registers, then distances 32 .. 1
+    const uint32_t mn = k0 < k1 ? k0 : k1, mx = k0 < k1 ? k1 : k0;
+    k0 = mn;
+    k1 = mx;
+    bitonic_merge<32>(k0, l, 128, false);
+    bitonic_merge<32>(k1, 64 + l, 128, false);
+}
+
+// a double held by lane l (l the same in every lane)
+__device__ __forceinline__ double readlane_dbl(double x, int l) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = readlane_u32((uint32_t)u, l), hi = readlane_u32((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 // exclusive prefix sum over the wave
 __device__ __forceinline__ int wave_excl_scan(int v, int *total) {
     int l = lane_id();
@@ -320,7 +452,7 @@ struct Poly {
                 r2l = fmax(r2l, d);
             }
         }
-        R2 = uni_d(wave_max(r2l) * (1.0 + 1e-12));
+        R2 = uni_d(wave_max_x(r2l) * (1.0 + 1e-12));
     }
 
     // Clip by {y : p.y <= p.d} (p64 in FP64); `tag` identifies the plane.
