@@ -39,6 +39,11 @@ struct ClipMem {
             double fa[64 * VPL];         // facet area
             double fc[64 * VPL][3];      // facet centroid (seed-relative)
         } f;
+        struct {
+            double vp[64 * VPL][3];      // search: vertex positions (FP64)
+            double ve[64 * VPL];         // their error bounds (mixed path; 0 in FP64)
+            double vr[64 * VPL];         // radius of each vertex's empty sphere, widened for rounding
+        } s;
     } u;
     int32_t rb[216];                     // gather: cell range starts
     int32_t rp[216];                     // gather: prefix of range lengths
@@ -259,11 +264,26 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         // [r/2, r), pruned by their distance to the seed (boxes widened by one
         // quantum, the rounding of the keys), empty ranges dropped; ranges go to
         // S.rb / S.rp compacted.  Returns the number of ranges; *total the particles.
-        // With `prune` (sweeps), a box is also dropped when no vertex's empty sphere
-        // (centre v, radius |v|, staged in S.u.f.vp with its error bound in S.u.f.fa)
+        // With `prune` (sweeps and later passes), a box is also dropped when no vertex's empty sphere
+        // (centre v, radius |v| widened, staged by stage_search in S.u.s)
         // reaches it: a particle cuts the current cell only if it lies in such a
         // sphere, and the cell only shrinks, so no particle of the box ever will.
         const double invL[3] = {1.0 / it.L[0], 1.0 / it.L[1], 1.0 / it.L[2]};
+        // the cell's vertices for the search-side tests: positions, error bounds and the radius of
+        // each vertex's empty sphere (|v|, widened for rounding and, mixed, the vertex error bound)
+        auto stage_search = [&]() {
+#pragma unroll
+            for (int s = 0; s < VPL; ++s)
+                if (P.alive[s] & mybit) {
+                    const double x = (double)P.vx[s], y = (double)P.vy[s], z = (double)P.vz[s];
+                    S.u.s.vp[s * 64 + lane][0] = x;
+                    S.u.s.vp[s * 64 + lane][1] = y;
+                    S.u.s.vp[s * 64 + lane][2] = z;
+                    S.u.s.ve[s * 64 + lane] = (double)P.ve[s];
+                    S.u.s.vr[s * 64 + lane] = sqrt(x * x + y * y + z * z) * (1.0 + 1e-7) + 2.0 * (double)P.ve[s];
+                }
+            wave_sync();
+        };
         auto cover = [&](double r, double rmin, int &total, bool prune) -> int {
             int lvl = 0;
             double c = it.S;
@@ -339,13 +359,11 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             while (m && !reached) {
                                 const int kv = __builtin_ctzll(m);
                                 m &= m - 1;
-                                const double *v = S.u.f.vp[s_ * 64 + kv];
+                                const double *v = S.u.s.vp[s_ * 64 + kv];
                                 const double ex = fmax(0.0, fmax(bl[0] - v[0], v[0] - bh[0]));
                                 const double ey = fmax(0.0, fmax(bl[1] - v[1], v[1] - bh[1]));
                                 const double ez = fmax(0.0, fmax(bl[2] - v[2], v[2] - bh[2]));
-                                // radius |v|, widened for rounding and (mixed) the vertex error bound
-                                const double rv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * (1.0 + 1e-7) +
-                                                  2.0 * S.u.f.fa[s_ * 64 + kv];
+                                const double rv = S.u.s.vr[s_ * 64 + kv];
                                 reached = ex * ex + ey * ey + ez * ez < rv * rv;
                             }
                         }
@@ -411,15 +429,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             int total;
             // stage the cell's vertices for the box pruning of the cover (and the first chunk)
             P.update_r2();
-#pragma unroll
-            for (int s = 0; s < VPL; ++s)
-                if (P.alive[s] & mybit) {
-                    S.u.f.vp[s * 64 + lane][0] = (double)P.vx[s];
-                    S.u.f.vp[s * 64 + lane][1] = (double)P.vy[s];
-                    S.u.f.vp[s * 64 + lane][2] = (double)P.vz[s];
-                    S.u.f.fa[s * 64 + lane] = (double)P.ve[s];
-                }
-            wave_sync();
+            stage_search();
             const int ncq = cover(r_hi, r_lo, total, true);
             bool dirty = false;
             // positions of the next 64 particles are loaded while the current 64 are tested
@@ -452,15 +462,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 if (dirty) {
                     P.update_r2();
                     // vertex positions (and, mixed, their error bounds) for the lane-parallel test
-#pragma unroll
-                    for (int s = 0; s < VPL; ++s)
-                        if (P.alive[s] & mybit) {
-                            S.u.f.vp[s * 64 + lane][0] = (double)P.vx[s];
-                            S.u.f.vp[s * 64 + lane][1] = (double)P.vy[s];
-                            S.u.f.vp[s * 64 + lane][2] = (double)P.vz[s];
-                            S.u.f.fa[s * 64 + lane] = (double)P.ve[s];
-                        }
-                    wave_sync();
+                    stage_search();
                     dirty = false;
                 }
                 const double pd = 0.5 * d2;
@@ -496,12 +498,12 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     while (m) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
-                        const double *v = S.u.f.vp[s * 64 + k];
+                        const double *v = S.u.s.vp[s * 64 + k];
                         const double sv = fma(v[0], dx, fma(v[1], dy, v[2] * dz)) - pd;  // the clip's rounding
                         // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
                         double marg = 0.0;
                         if (std::is_same<T, float>::value)
-                            marg = nn * (S.u.f.fa[s * 64 + k] +
+                            marg = nn * (S.u.s.ve[s * 64 + k] +
                                          1e-6 * (sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + 0.5 * nn));
                         act |= sv > -marg;
                     }
@@ -541,7 +543,11 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             const double rh2 = r_next * r_next, rl2 = r_done * r_done;
             const double inv_rh2 = 1.0 / rh2, inv_bin = 64.0 / (rh2 - rl2);
             int total;
-            const int ncq = cover(r_next, r_done, total, false);
+            // once the cell has been cut a few times, covering boxes that no vertex's empty sphere
+            // reaches hold no particle that can still cut it, as in the sweeps
+            const bool prune = r_done > 0.0 && ncut >= 4;
+            if (prune) stage_search();
+            const int ncq = cover(r_next, r_done, total, prune);
             S.hist[lane] = 0;
             wave_sync();
             // ---- gather particles with r_done <= d < r_next (and a d^2 histogram); the positions
