@@ -315,6 +315,15 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             const int ncells = na[0] * na[1] * na[2];
             const double r2 = r * r, rmin2 = rmin * rmin;
             int count = 0;
+            // only vertices whose (widened) sphere reaches past rmin matter: every point of the
+            // sphere of v lies within |v| + vr <= 2 vr of the seed, and the shell starts at rmin
+            uint64_t farv[VPL];
+#pragma unroll
+            for (int s_ = 0; s_ < VPL; ++s_) {
+                farv[s_] = P.alive[s_];
+                if (prune)
+                    farv[s_] = __ballot((P.alive[s_] & mybit) && 2.0 * S.u.s.vr[s_ * 64 + lane] * (1.0 + 1e-7) >= rmin);
+            }
             for (int base = 0; base < ncells; base += WAVE) {
                 const int k = base + lane;
                 bool keep = false;
@@ -355,7 +364,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                         bool reached = false;
 #pragma unroll
                         for (int s_ = 0; s_ < VPL; ++s_) {
-                            uint64_t m = P.alive[s_];
+                            uint64_t m = farv[s_];
                             while (m && !reached) {
                                 const int kv = __builtin_ctzll(m);
                                 m &= m - 1;
@@ -647,14 +656,32 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     // of them than applying them one by one would find cutting.
                     uint64_t pend = __ballot(near);
                     while (pend && !done) {
+                        // A candidate at distance |D| cuts vertex v only if it lies in the sphere with
+                        // centre v through the seed, so only if |D| <= 2 |v|; the smallest pending key
+                        // bounds |D| from below, and vertices short of it (with a margin far above the
+                        // rounding of the side test and, mixed, the vertex error bound) are not tested.
+                        const uint32_t kmin = readlane_u32(key, uni_i(__builtin_ctzll(pend))) >> 8;
+                        const double dlo2 = (double)kmin * rh2 * (1.0 / 16777216.0) * (1.0 - 1e-12);
+                        uint64_t farv[VPL];
 #pragma unroll
-                        for (int s = 0; s < VPL; ++s)
+                        for (int s = 0; s < VPL; ++s) {
+                            bool f = false;
                             if (P.alive[s] & mybit) {
                                 S.P.st[s * 64 + lane][0] = P.vx[s];
                                 S.P.st[s * 64 + lane][1] = P.vy[s];
                                 S.P.st[s * 64 + lane][2] = P.vz[s];
                                 if constexpr (std::is_same<T, float>::value) S.P.ste[s * 64 + lane] = P.ve[s];
+                                const double x = (double)P.vx[s], y = (double)P.vy[s], z = (double)P.vz[s];
+                                const double r2v = x * x + y * y + z * z;
+                                if constexpr (std::is_same<T, float>::value) {
+                                    const double fv = 2.0 * (sqrt(r2v) + (double)P.ve[s]) * (1.0 + 1e-5);
+                                    f = fv * fv >= dlo2;
+                                } else {
+                                    f = 4.0 * r2v * (1.0 + 2.1e-5) >= dlo2;  // (2 |v| (1 + 1e-5))^2
+                                }
                             }
+                            farv[s] = __ballot(f);
+                        }
                         wave_sync();
                         bool act = false;
                         if (pend & mybit) {
@@ -665,7 +692,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             const double nn = sqrt(d2);
 #pragma unroll
                             for (int s = 0; s < VPL; ++s) {
-                                uint64_t m = P.alive[s];
+                                uint64_t m = farv[s];
                                 while (m && !act) {
                                     const int k = __builtin_ctzll(m);
                                     m &= m - 1;
