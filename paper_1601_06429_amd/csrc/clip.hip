@@ -100,6 +100,30 @@ __device__ __forceinline__ int32_t lower_bound_key(const uint64_t *skey, int32_t
     return a;
 }
 
+// The item's fields, read once into scalar registers: through a reference the compiler reloads
+// them from memory at every use (the kernel's own stores might alias them), each load waited on.
+__device__ __forceinline__ DevItem uniform_item(const DevItem &g) {
+    DevItem it;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        it.lo[a] = uni_d(g.lo[a]);
+        it.L[a] = uni_d(g.L[a]);
+    }
+    it.S = uni_d(g.S);
+    it.inv_res = uni_d(g.inv_res);
+    it.start = g.start;
+    it.count = g.count;
+    it.n_owned = g.n_owned;
+    it.owned_base = g.owned_base;
+    const int64_t to = g.tab_off;
+    it.tab_off = ((int64_t)uni_i((int)(to >> 32)) << 32) | (int64_t)(uint32_t)uni_i((int)(uint32_t)to);
+    it.T = uni_i(g.T);
+    it.periodic = uni_i(g.periodic);
+    it.walls = uni_i(g.walls);
+    it.pad = 0;
+    return it;
+}
+
 // sorted-index range of the Morton cell (cx, cy, cz) at level l of item `ib`
 __device__ __forceinline__ void cell_range(const ClipArgs &A, const DevItem &it, int ib, int l, uint64_t cx,
                                            uint64_t cy, uint64_t cz, int32_t &b, int32_t &e) {
@@ -217,7 +241,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
         const int32_t cslot = uni_i(RETRY ? A.queue[w] : (int32_t)w);
         const int32_t j0 = uni_i(A.cells[cslot]);
         const int bi = uni_i(find_item_d(A.items, A.n_items, j0));
-        const DevItem &it = A.items[bi];
+        const DevItem it = uniform_item(A.items[bi]);
         double sx, sy, sz;
         load_pos<PT4>(A.spos, j0, sx, sy, sz);
         sx = uni_d(sx);
@@ -1050,7 +1074,7 @@ __global__ void __launch_bounds__(256) k_planes(ClipArgs A, int32_t *out) {
         }
         const int32_t j0 = A.cells[c];
         const int bi = find_item_d(A.items, A.n_items, j0);
-        const DevItem &it = A.items[bi];
+        const DevItem it = uniform_item(A.items[bi]);
         double xs[3];
         load_pos<PT4>(A.spos, j0, xs[0], xs[1], xs[2]);
         const double r = 2.0 * A.crad[c], r2 = r * r;
