@@ -654,8 +654,10 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 else if (n > 1)
                     k0 = bitonic64_x(k0);
                 // ---- clip in increasing distance; stop at the first particle beyond 2R
+                // the key of distance 2R: the keys' own scaling (d^2 * inv_rh2 * 2^24, rounded down),
+                // so every candidate within 2R has a key below it; one more for safety
                 auto q4r = [&](double r2) -> uint32_t {
-                    double x = 4.0 * r2 / rh2 * 16777216.0;
+                    double x = 4.0 * r2 * inv_rh2 * 16777216.0;
                     return x >= 16777215.0 ? 0xFFFFFFu : (uint32_t)x + 1u;
                 };
                 // Candidates go in chunks of 64 in increasing distance.  Each lane tests its
@@ -898,19 +900,24 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 double ax = v1[0] - v0[0], ay = v1[1] - v0[1], az = v1[2] - v0[2];
                 double bx = v2[0] - v0[0], by = v2[1] - v0[1], bz = v2[2] - v0[2];
                 double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+                // triangle area along the face normal; 3 x its centroid times the area; 6 x the volume
+                // of the tetrahedron (seed, v0, v1, v2): the constant factors are applied per face
                 double ta = 0.5 * (cx * ux + cy * uy + cz * uz);
-                Cx += ta * (v0[0] + v1[0] + v2[0]) / 3.0;
-                Cy += ta * (v0[1] + v1[1] + v2[1]) / 3.0;
-                Cz += ta * (v0[2] + v1[2] + v2[2]) / 3.0;
+                Cx += ta * (v0[0] + v1[0] + v2[0]);
+                Cy += ta * (v0[1] + v1[1] + v2[1]);
+                Cz += ta * (v0[2] + v1[2] + v2[2]);
                 at += ta;
-                vf += (v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
-                       v0[2] * (v1[0] * v2[1] - v1[1] * v2[0])) / 6.0;
+                vf += v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
+                      v0[2] * (v1[0] * v2[1] - v1[1] * v2[0]);
                 prev = cur;
                 ++guard;
             }
+            Cx /= 3.0;
+            Cy /= 3.0;
+            Cz /= 3.0;
             double A_ = at;
             area_l[r] = A_;
-            vol_l += vf;
+            vol_l += vf / 6.0;
             if constexpr (VPL == 1) {
                 cen_l[0] = at > 0 ? Cx / at : v0[0];
                 cen_l[1] = at > 0 ? Cy / at : v0[1];
