@@ -100,30 +100,6 @@ __device__ __forceinline__ int32_t lower_bound_key(const uint64_t *skey, int32_t
     return a;
 }
 
-// The item's fields, read once into scalar registers: through a reference the compiler reloads
-// them from memory at every use (the kernel's own stores might alias them), each load waited on.
-__device__ __forceinline__ DevItem uniform_item(const DevItem &g) {
-    DevItem it;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        it.lo[a] = uni_d(g.lo[a]);
-        it.L[a] = uni_d(g.L[a]);
-    }
-    it.S = uni_d(g.S);
-    it.inv_res = uni_d(g.inv_res);
-    it.start = g.start;
-    it.count = g.count;
-    it.n_owned = g.n_owned;
-    it.owned_base = g.owned_base;
-    const int64_t to = g.tab_off;
-    it.tab_off = ((int64_t)uni_i((int)(to >> 32)) << 32) | (int64_t)(uint32_t)uni_i((int)(uint32_t)to);
-    it.T = uni_i(g.T);
-    it.periodic = uni_i(g.periodic);
-    it.walls = uni_i(g.walls);
-    it.pad = 0;
-    return it;
-}
-
 // sorted-index range of the Morton cell (cx, cy, cz) at level l of item `ib`
 __device__ __forceinline__ void cell_range(const ClipArgs &A, const DevItem &it, int ib, int l, uint64_t cx,
                                            uint64_t cy, uint64_t cz, int32_t &b, int32_t &e) {

@@ -866,7 +866,7 @@ __global__ void __launch_bounds__(256) k_sample_claim(SampleArgs A) {
     __shared__ ClaimMem Ms[4];
     ClaimMem &M = Ms[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const DevItem &it = A.items[0];
+    const DevItem it = uniform_item(A.items[0]);
     const int sub = A.sub;
     const int dims[3] = {A.nx, A.ny, A.nz};
     const int64_t F[3] = {(int64_t)A.nx * sub, (int64_t)A.ny * sub, (int64_t)A.nz * sub};
@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(256) k_sample_tiles(SampleArgs A) {
     SampleMem &S = *reinterpret_cast<SampleMem *>(smem + (size_t)(threadIdx.x >> 6) * sizeof(SampleMem));
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const DevItem &it = A.items[0];
+    const DevItem it = uniform_item(A.items[0]);
     const int sub = A.sub;
     const int64_t fd[3] = {(int64_t)A.nx * sub, (int64_t)A.ny * sub, (int64_t)A.nz * sub};
     const int64_t ntile[3] = {(fd[0] + 3) / 4, (fd[1] + 3) / 4, (fd[2] + 3) / 4};
@@ -1131,7 +1131,7 @@ __global__ void k_sample_fixup(SampleArgs A) {
     if (p >= F[0] * F[1] * F[2]) return;
     unsigned long long s = A.slot[p];
     if (s == ~0ull) {
-        const DevItem &it = A.items[0];
+        const DevItem it = uniform_item(A.items[0]);
         const int dims[3] = {A.nx, A.ny, A.nz};
         const int64_t f[3] = {p / (F[1] * F[2]), (p / F[2]) % F[1], p % F[2]};
         double q[3];

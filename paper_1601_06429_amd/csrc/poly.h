@@ -213,6 +213,31 @@ __device__ __forceinline__ double readlane_dbl(double x, int l) {
     return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
+// An item's fields, read once into scalar registers (the item must be the same for the whole
+// wavefront): through a reference the compiler reloads them from memory at every use, since the
+// kernel's own stores might alias them, and waits on each load.
+__device__ __forceinline__ DevItem uniform_item(const DevItem &g) {
+    DevItem it;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        it.lo[a] = uni_d(g.lo[a]);
+        it.L[a] = uni_d(g.L[a]);
+    }
+    it.S = uni_d(g.S);
+    it.inv_res = uni_d(g.inv_res);
+    it.start = g.start;
+    it.count = g.count;
+    it.n_owned = g.n_owned;
+    it.owned_base = g.owned_base;
+    const int64_t to = g.tab_off;
+    it.tab_off = ((int64_t)uni_i((int)(to >> 32)) << 32) | (int64_t)(uint32_t)uni_i((int)(uint32_t)to);
+    it.T = uni_i(g.T);
+    it.periodic = uni_i(g.periodic);
+    it.walls = uni_i(g.walls);
+    it.pad = 0;
+    return it;
+}
+
 // exclusive prefix sum over the wave
 __device__ __forceinline__ int wave_excl_scan(int v, int *total) {
     int l = lane_id();

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_gradient(const int32_t *cells, const in
     const int lane = threadIdx.x & (CG - 1);
     const int32_t i = cells[c];
     const int32_t r = srow[i];
-    const DevItem &it = items[find_item_p(items, n_items, i)];
+    const DevItem it = items[find_item_p(items, n_items, i)];  // a copy: read once, not at every use
     const double ri = rho[sorig[i]];
     double g00 = 0, g01 = 0, g02 = 0, g11 = 0, g12 = 0, g22 = 0, b0 = 0, b1 = 0, b2 = 0;
     const int64_t src = crow[c];
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_backward(const int32_t *cells, const in
     const int lane = threadIdx.x & (CG - 1);
     const int32_t i = cells[c];
     const int32_t r = srow[i];
-    const DevItem &it = items[find_item_p(items, n_items, i)];
+    const DevItem it = items[find_item_p(items, n_items, i)];  // a copy: read once, not at every use
     const double gk = g[r];
     double ox = 0, oy = 0, oz = 0;
     const int64_t src = crow[c];

@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_structure(StructArgs A) {
             if (!A.write && lane == 0) A.nvert[row] = A.nface[row] = A.nloop[row] = 0;
             continue;
         }
-        const DevItem &it = A.items[item_of(A.items, A.n_items, j0)];
+        const DevItem it = uniform_item(A.items[item_of(A.items, A.n_items, j0)]);
         if (!RETRY && !A.write && it.periodic) {
             const int nf = A.src.cnf[c], nv = A.src.cnv[c];
             if (nf >= 4 && nf <= VT_TOPO_FACES && nv >= 4 && nv <= 64 && A.src.ccnt[c] == nf) {
