@@ -100,6 +100,34 @@ __device__ __forceinline__ int32_t lower_bound_key(const uint64_t *skey, int32_t
     return a;
 }
 
+// the low 10 bits of x to every third bit (Morton codes of levels up to 10 fit 32 bits)
+__device__ __forceinline__ uint32_t spread3_10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// sorted-index range of the Morton cell with code m at level l of item `ib`
+__device__ __forceinline__ void cell_range_m(const ClipArgs &A, const DevItem &it, int ib, int l, uint64_t m,
+                                             int32_t &b, int32_t &e) {
+    const int T = it.T;
+    if (l <= T) {
+        const int sh = 3 * (T - l);
+        b = A.tab[it.tab_off + (int64_t)(m << sh)];
+        e = A.tab[it.tab_off + (int64_t)((m + 1) << sh)];
+    } else {
+        const uint64_t mT = m >> (3 * (l - T));
+        const int32_t lo = A.tab[it.tab_off + (int64_t)mT], hi = A.tab[it.tab_off + (int64_t)mT + 1];
+        const int sh = 3 * (VT_MORTON_BITS - l);
+        const uint64_t base = (uint64_t)ib << VT_LOCAL_KEY_BITS;
+        b = lower_bound_key(A.skey, lo, hi, base | (m << sh));
+        e = lower_bound_key(A.skey, b, hi, base | ((m + 1) << sh));
+    }
+}
+
 // sorted-index range of the Morton cell (cx, cy, cz) at level l of item `ib`
 __device__ __forceinline__ void cell_range(const ClipArgs &A, const DevItem &it, int ib, int l, uint64_t cx,
                                            uint64_t cy, uint64_t cz, int32_t &b, int32_t &e) {
@@ -292,10 +320,10 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 ++lvl;
             }
             const int sh = VT_MORTON_BITS - lvl;
-            const int64_t ncl = 1ll << lvl;
+            const int ncl = 1 << lvl;
             const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
-            int64_t a0[3];
-            int na[3];
+            int a0[3], na[3];
+            bool all_img = false;  // a periodic window that spans the whole period along some axis
             for (int a = 0; a < 3; ++a) {
                 int64_t q0 = vt_qraw(xs[a] - r, it.lo[a], it.inv_res) - 1;
                 int64_t q1 = vt_qraw(xs[a] + r, it.lo[a], it.inv_res) + 1;
@@ -304,16 +332,26 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     if (i1 - i0 + 1 >= ncl) {
                         i0 = 0;
                         i1 = ncl - 1;
+                        all_img = true;
                     }
                 } else {
                     if (i0 < 0) i0 = 0;
                     if (i1 > ncl - 1) i1 = ncl - 1;
                 }
-                a0[a] = i0;
+                a0[a] = (int)i0;
                 na[a] = i1 >= i0 ? (int)(i1 - i0 + 1) : 0;  // at most 6
             }
-            const int ncells = na[0] * na[1] * na[2];
+            const int nbox = na[0] * na[1] * na[2];
             const double r2 = r * r, rmin2 = rmin * rmin;
+            // box u along axis a, widened by one quantum (the rounding of the keys), relative to the
+            // seed: [u c + off_lo[a], u c + off_lo[a] + cw]
+            const double cw = c + 2.0 * quantum;
+            double off_lo[3];
+            for (int a = 0; a < 3; ++a) off_lo[a] = it.lo[a] - quantum - xs[a];
+            // lane -> (ix, iy, iz): k = ix + na0 (iy + na1 iz) with k < 216, so (k + 1/2) / n in FP32 is
+            // at least 1/72 away from an integer and truncates to the exact quotient
+            const int na01 = na[0] * na[1];
+            const float inv0 = 1.0f / (float)(na[0] > 0 ? na[0] : 1), inv01 = 1.0f / (float)(na01 > 0 ? na01 : 1);
             int count = 0;
             // only vertices whose (widened) sphere reaches past rmin matter: every point of the
             // sphere of v lies within |v| + vr <= 2 vr of the seed, and the shell starts at rmin
@@ -324,43 +362,62 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 if (prune)
                     farv[s_] = __ballot((P.alive[s_] & mybit) && 2.0 * S.u.s.vr[s_ * 64 + lane] * (1.0 + 1e-7) >= rmin);
             }
-            for (int base = 0; base < ncells; base += WAVE) {
+            for (int base = 0; base < nbox; base += WAVE) {
                 const int k = base + lane;
                 bool keep = false;
                 int32_t b = 0, e = 0;
-                if (k < ncells) {
-                    const int ix = k % na[0], iy = (k / na[0]) % na[1], iz = k / (na[0] * na[1]);
-                    const int64_t u[3] = {a0[0] + ix, a0[1] + iy, a0[2] + iz};
-                    // per axis: nearest and farthest distance from the seed to the cell,
-                    // minimised over the periodic images (a lower / upper bound for the
-                    // minimum-image distance of every particle in the cell)
+                if (k < nbox) {
+                    const int iz = (int)(((float)k + 0.5f) * inv01);
+                    const int rem = k - iz * na01;
+                    const int iy = (int)(((float)rem + 0.5f) * inv0);
+                    const int u[3] = {a0[0] + rem - iy * na[0], a0[1] + iy, a0[2] + iz};
+                    // per axis: nearest and farthest distance from the seed to the box (a lower / upper
+                    // bound for the minimum-image distance of every particle in it)
                     double dmin2 = 0.0, dmax2 = 0.0;
-                    for (int a = 0; a < 3; ++a) {
-                        double dn = 1e300, df = 1e300;
-                        // the window [a0, a0 + na) is centred on the seed, so its unwrapped boxes are
-                        // the nearest images; only a window that spans the whole period (wrapped to
-                        // [0, ncl)) needs the three images
-                        const bool all_img = it.periodic && na[a] == ncl;
-                        for (int sh_ = -1; sh_ <= 1; ++sh_) {
-                            if (sh_ != 0 && !all_img) continue;
-                            const double off_ = sh_ * it.L[a];
-                            const double blo_ = it.lo[a] + (double)u[a] * c - quantum + off_;
-                            const double bhi_ = it.lo[a] + (double)(u[a] + 1) * c + quantum + off_;
-                            const double dl = blo_ - xs[a], dh = xs[a] - bhi_;
-                            dn = fmin(dn, fmax(0.0, fmax(dl, dh)));
-                            df = fmin(df, fmax(fabs(dl), fabs(dh)));
+                    if (!all_img) {
+                        // the window [a0, a0 + na) is centred on the seed: its unwrapped boxes are the
+                        // nearest images
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double bl = fma((double)u[a], c, off_lo[a]), bh = bl + cw;
+                            const double dn = fmax(0.0, fmax(bl, -bh));
+                            const double df = fmax(fabs(bl), fabs(bh));
+                            dmin2 = fma(dn, dn, dmin2);
+                            dmax2 = fma(df, df, dmax2);
                         }
-                        dmin2 += dn * dn;
-                        dmax2 += df * df;
+                    } else {
+                        // a window that spans the whole period (wrapped to [0, ncl)) needs the three images
+                        for (int a = 0; a < 3; ++a) {
+                            double dn = 1e300, df = 1e300;
+                            const bool img = na[a] == ncl;
+                            for (int sh_ = -1; sh_ <= 1; ++sh_) {
+                                if (sh_ != 0 && !img) continue;
+                                const double lo_ = fma((double)u[a], c, off_lo[a]) + sh_ * it.L[a];
+                                const double hi_ = lo_ + cw;
+                                dn = fmin(dn, fmax(0.0, fmax(lo_, -hi_)));
+                                df = fmin(df, fmax(fabs(lo_), fabs(hi_)));
+                            }
+                            dmin2 += dn * dn;
+                            dmax2 += df * df;
+                        }
                     }
                     keep = dmin2 < r2 && dmax2 >= rmin2;
-                    if (keep && prune && !(it.periodic && (na[0] == ncl || na[1] == ncl || na[2] == ncl))) {
-                        // the box relative to the seed (the unwrapped window is the nearest image)
+                    if (keep && prune && !all_img) {
                         double bl[3], bh[3];
+#pragma unroll
                         for (int a = 0; a < 3; ++a) {
-                            bl[a] = it.lo[a] + (double)u[a] * c - quantum - xs[a];
-                            bh[a] = it.lo[a] + (double)(u[a] + 1) * c + quantum - xs[a];
+                            bl[a] = fma((double)u[a], c, off_lo[a]);
+                            bh[a] = bl[a] + cw;
                         }
+                        // does the empty sphere of vertex k reach the box?
+                        auto reaches = [&](int k) -> bool {
+                            const double *v = S.u.s.vp[k];
+                            const double ex = fmax(0.0, fmax(bl[0] - v[0], v[0] - bh[0]));
+                            const double ey = fmax(0.0, fmax(bl[1] - v[1], v[1] - bh[1]));
+                            const double ez = fmax(0.0, fmax(bl[2] - v[2], v[2] - bh[2]));
+                            const double rv = S.u.s.vr[k];
+                            return ex * ex + ey * ey + ez * ez < rv * rv;
+                        };
                         bool reached = false;
 #pragma unroll
                         for (int s_ = 0; s_ < VPL; ++s_) {
@@ -368,20 +425,20 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             while (m && !reached) {
                                 const int kv = __builtin_ctzll(m);
                                 m &= m - 1;
-                                const double *v = S.u.s.vp[s_ * 64 + kv];
-                                const double ex = fmax(0.0, fmax(bl[0] - v[0], v[0] - bh[0]));
-                                const double ey = fmax(0.0, fmax(bl[1] - v[1], v[1] - bh[1]));
-                                const double ez = fmax(0.0, fmax(bl[2] - v[2], v[2] - bh[2]));
-                                const double rv = S.u.s.vr[s_ * 64 + kv];
-                                reached = ex * ex + ey * ey + ez * ez < rv * rv;
+                                reached = reaches(s_ * 64 + kv);
                             }
                         }
                         keep = reached;
                     }
                     if (keep) {
-                        uint64_t cc[3];
-                        for (int a = 0; a < 3; ++a) cc[a] = (uint64_t)(it.periodic ? (u[a] & (ncl - 1)) : u[a]);
-                        cell_range(A, it, bi, lvl, cc[0], cc[1], cc[2], b, e);
+                        uint32_t cc[3];
+                        for (int a = 0; a < 3; ++a) cc[a] = (uint32_t)(it.periodic ? (u[a] & (ncl - 1)) : u[a]);
+                        uint64_t mc;
+                        if (lvl <= 10)
+                            mc = (uint64_t)((spread3_10(cc[0]) << 2) | (spread3_10(cc[1]) << 1) | spread3_10(cc[2]));
+                        else
+                            mc = vt_morton(cc[0], cc[1], cc[2]);
+                        cell_range_m(A, it, bi, lvl, mc, b, e);
                         keep = e > b;
                     }
                 }
@@ -501,20 +558,22 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     vm[s] = __ballot(rel);
                 }
                 bool act = false;
+                auto cuts_v = [&](int k) -> bool {
+                    const double *v = S.u.s.vp[k];
+                    const double sv = fma(v[0], dx, fma(v[1], dy, v[2] * dz)) - pd;  // the clip's rounding
+                    // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
+                    double marg = 0.0;
+                    if (std::is_same<T, float>::value)
+                        marg = nn * (S.u.s.ve[k] + 1e-6 * (sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + 0.5 * nn));
+                    return sv > -marg;
+                };
 #pragma unroll
                 for (int s = 0; s < VPL; ++s) {
                     uint64_t m = vm[s];
                     while (m) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
-                        const double *v = S.u.s.vp[s * 64 + k];
-                        const double sv = fma(v[0], dx, fma(v[1], dy, v[2] * dz)) - pd;  // the clip's rounding
-                        // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
-                        double marg = 0.0;
-                        if (std::is_same<T, float>::value)
-                            marg = nn * (S.u.s.ve[s * 64 + k] +
-                                         1e-6 * (sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + 0.5 * nn));
-                        act |= sv > -marg;
+                        act |= cuts_v(s * 64 + k);
                     }
                 }
                 uint64_t am = __ballot(keep && act);
@@ -692,22 +751,24 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             const double d2 = dx * dx + dy * dy + dz * dz;
                             const double pd = 0.5 * d2;
                             const double nn = sqrt(d2);
+                            // does the candidate's plane cut staged vertex k?
+                            auto cuts_v = [&](int k) -> bool {
+                                const double vx = (double)S.P.st[k][0], vy = (double)S.P.st[k][1], vz = (double)S.P.st[k][2];
+                                // same rounding as the clip's own side test
+                                const double sv = fma(vx, dx, fma(vy, dy, vz * dz)) - pd;
+                                // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
+                                double marg = 0.0;
+                                if (std::is_same<T, float>::value)
+                                    marg = nn * ((double)S.P.ste[k] + 1e-6 * (sqrt(vx * vx + vy * vy + vz * vz) + 0.5 * nn));
+                                return sv > -marg;
+                            };
 #pragma unroll
                             for (int s = 0; s < VPL; ++s) {
                                 uint64_t m = farv[s];
                                 while (m && !act) {
                                     const int k = __builtin_ctzll(m);
                                     m &= m - 1;
-                                    const double vx = (double)S.P.st[s * 64 + k][0], vy = (double)S.P.st[s * 64 + k][1],
-                                                 vz = (double)S.P.st[s * 64 + k][2];
-                                    // same rounding as the clip's own side test
-                                    const double sv = fma(vx, dx, fma(vy, dy, vz * dz)) - pd;
-                                    // FP64 path: the exact predicate; mixed path: widened by the vertex error bound
-                                    double marg = 0.0;
-                                    if (std::is_same<T, float>::value)
-                                        marg = nn * ((double)S.P.ste[s * 64 + k] +
-                                                     1e-6 * (sqrt(vx * vx + vy * vy + vz * vz) + 0.5 * nn));
-                                    act = sv > -marg;
+                                    act = cuts_v(s * 64 + k);
                                 }
                             }
                         }
@@ -860,49 +921,53 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 }
                 return nx;
             };
-            const double *v0 = S.u.f.vp[i0];
-            // fan triangles are counter-clockwise seen from outside: their areas are
-            // half the component of the cross product along the face's unit normal
+            const double v0x = S.u.f.vp[i0][0], v0y = S.u.f.vp[i0][1], v0z = S.u.f.vp[i0][2];
+            // Fan triangles (v0, v1, v2) are counter-clockwise seen from outside: their areas are half
+            // the component of (v1 - v0) x (v2 - v0) along the face's unit normal.  With a = v1 - v0
+            // and b = v2 - v0 (the next step's a), the face's area is the sum of the triangles' and its
+            // centroid v0 + sum(ta (a + b)) / (3 A); the cell's volume is the sum over faces of
+            // A h / 3, h = d / |n| the distance of the face's plane from the seed.
             const P4<double> &pf = S.P.pl64[f];
             const double inn = 1.0 / sqrt(pf.x * pf.x + pf.y * pf.y + pf.z * pf.z);
-            const double ux = pf.x * inn, uy = pf.y * inn, uz = pf.z * inn;
-            double Cx = 0, Cy = 0, Cz = 0, at = 0, vf = 0;
+            const double hx = 0.5 * pf.x * inn, hy = 0.5 * pf.y * inn, hz = 0.5 * pf.z * inn;
+            double Mx = 0, My = 0, Mz = 0, at = 0;
             int prev = next_of(i0);
+            double ax = 0, ay = 0, az = 0;
+            if (prev >= 0) {
+                ax = S.u.f.vp[prev][0] - v0x;
+                ay = S.u.f.vp[prev][1] - v0y;
+                az = S.u.f.vp[prev][2] - v0z;
+            }
             int guard = 0;
             while (prev >= 0 && guard < VMAX) {
-                int cur = next_of(prev);
+                const int cur = next_of(prev);
                 if (cur < 0 || cur == i0) break;
-                const double *v1 = S.u.f.vp[prev], *v2 = S.u.f.vp[cur];
-                double ax = v1[0] - v0[0], ay = v1[1] - v0[1], az = v1[2] - v0[2];
-                double bx = v2[0] - v0[0], by = v2[1] - v0[1], bz = v2[2] - v0[2];
-                double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
-                // triangle area along the face normal; 3 x its centroid times the area; 6 x the volume
-                // of the tetrahedron (seed, v0, v1, v2): the constant factors are applied per face
-                double ta = 0.5 * (cx * ux + cy * uy + cz * uz);
-                Cx += ta * (v0[0] + v1[0] + v2[0]);
-                Cy += ta * (v0[1] + v1[1] + v2[1]);
-                Cz += ta * (v0[2] + v1[2] + v2[2]);
+                const double bx = S.u.f.vp[cur][0] - v0x, by = S.u.f.vp[cur][1] - v0y, bz = S.u.f.vp[cur][2] - v0z;
+                const double cx = fma(ay, bz, -(az * by)), cy = fma(az, bx, -(ax * bz)), cz = fma(ax, by, -(ay * bx));
+                const double ta = fma(cx, hx, fma(cy, hy, cz * hz));
+                Mx = fma(ta, ax + bx, Mx);
+                My = fma(ta, ay + by, My);
+                Mz = fma(ta, az + bz, Mz);
                 at += ta;
-                vf += v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
-                      v0[2] * (v1[0] * v2[1] - v1[1] * v2[0]);
+                ax = bx;
+                ay = by;
+                az = bz;
                 prev = cur;
                 ++guard;
             }
-            Cx /= 3.0;
-            Cy /= 3.0;
-            Cz /= 3.0;
-            double A_ = at;
-            area_l[r] = A_;
-            vol_l += vf / 6.0;
+            const double i3a = at > 0 ? 1.0 / (3.0 * at) : 0.0;
+            const double cfx = fma(Mx, i3a, v0x), cfy = fma(My, i3a, v0y), cfz = fma(Mz, i3a, v0z);
+            area_l[r] = at;
+            vol_l = fma(at, pf.d * inn * (1.0 / 3.0), vol_l);
             if constexpr (VPL == 1) {
-                cen_l[0] = at > 0 ? Cx / at : v0[0];
-                cen_l[1] = at > 0 ? Cy / at : v0[1];
-                cen_l[2] = at > 0 ? Cz / at : v0[2];
+                cen_l[0] = cfx;
+                cen_l[1] = cfy;
+                cen_l[2] = cfz;
             } else {
-                S.u.f.fa[f] = A_;
-                S.u.f.fc[f][0] = at > 0 ? Cx / at : v0[0];
-                S.u.f.fc[f][1] = at > 0 ? Cy / at : v0[1];
-                S.u.f.fc[f][2] = at > 0 ? Cz / at : v0[2];
+                S.u.f.fa[f] = at;
+                S.u.f.fc[f][0] = cfx;
+                S.u.f.fc[f][1] = cfy;
+                S.u.f.fc[f][2] = cfz;
             }
         }
         const double V = wave_sum_d(vol_l);
