@@ -8,7 +8,10 @@ whatever the search does):
   * ``pts_per_grid_cell`` -- the resolution of the uniform-grid (Morton level) table the kNN
     search walks: about this many particles per finest cell;
   * ``waves_per_cu`` -- how many wavefronts (one cell each) the persistent clipping kernel keeps
-    resident per compute unit.
+    resident per compute unit;
+  * ``cell_mapping`` -- the wavefront-to-cell mapping: each XCD (its own L2) takes a contiguous
+    eighth of the cells in Morton order and then helps the others (``VT_MAP_XCD``), or one queue
+    deals consecutive cells to wavefronts on every XCD in turn (``VT_MAP_GLOBAL``).
 
 ``tune`` times ``vt_build`` with device events for each candidate on the caller's inputs (or a
 representative subset of items), keeps the fastest, and caches the choice per input signature
@@ -18,16 +21,18 @@ from __future__ import annotations
 
 import itertools
 
-K_INITS = (24, 34, 50, 74)
+K_INITS = (24, 34, 50)
 PTS_PER_GRID_CELL = (1.0, 0.125, 1.0 / 64)
 WAVES_PER_CU = (12, 16)
+CELL_MAPPINGS = (0, 1)  # VT_MAP_XCD, VT_MAP_GLOBAL
 
 _cache = {}
 
 
-def candidates(k_inits=K_INITS, pts_per_grid_cell=PTS_PER_GRID_CELL, waves_per_cu=WAVES_PER_CU):
-    return [dict(k_init=int(k), pts_per_grid_cell=float(g), waves_per_cu=int(w))
-            for k, g, w in itertools.product(k_inits, pts_per_grid_cell, waves_per_cu)]
+def candidates(k_inits=K_INITS, pts_per_grid_cell=PTS_PER_GRID_CELL, waves_per_cu=WAVES_PER_CU,
+               cell_mappings=CELL_MAPPINGS):
+    return [dict(k_init=int(k), pts_per_grid_cell=float(g), waves_per_cu=int(w), cell_mapping=int(m))
+            for k, g, w, m in itertools.product(k_inits, pts_per_grid_cell, waves_per_cu, cell_mappings)]
 
 
 def signature(device_name, dtype, n_total, n_items, precision):

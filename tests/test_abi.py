@@ -68,8 +68,9 @@ def test_autotune_selection_logic():
     from paper_1601_06429_amd import autotune
 
     c = autotune.candidates()
-    assert len(c) == len(autotune.K_INITS) * len(autotune.PTS_PER_GRID_CELL) * len(autotune.WAVES_PER_CU)
-    assert all(set(o) == {"k_init", "pts_per_grid_cell", "waves_per_cu"} for o in c)
+    assert len(c) == (len(autotune.K_INITS) * len(autotune.PTS_PER_GRID_CELL) * len(autotune.WAVES_PER_CU) *
+                      len(autotune.CELL_MAPPINGS))
+    assert all(set(o) == {"k_init", "pts_per_grid_cell", "waves_per_cu", "cell_mapping"} for o in c)
     t = [(c[0], 3.0), (c[1], 1.5), (c[2], 1.5), (c[3], 9.0)]
     assert autotune.pick(t) == c[1]  # fastest, earlier one on ties
     a = autotune.signature("MI355X", "torch.float32", 2_097_152, 1, 0)
