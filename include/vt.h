@@ -146,8 +146,8 @@ typedef struct {
  *              the particle's index in pos.
  *   items      host, n_items >= 1 worlds (see vt_item).
  *   opts       host, nullable.
- * Errors: VT_ERR_ARG (bad sizes, unpacked items, non-cubic periodic box),
- * VT_ERR_OOM, VT_ERR_HIP.
+ * Errors: VT_ERR_ARG (bad sizes, an item without owned particles, unpacked
+ * items, non-cubic periodic box), VT_ERR_OOM, VT_ERR_HIP.
  */
 vt_status vt_build(vt_ctx **ctx, const void *pos, vt_dtype dtype, const int32_t *global_id, const vt_item *items,
                    int32_t n_items, const vt_opts *opts, void *stream);

@@ -56,6 +56,10 @@ def test_argument_errors_are_synchronous():
     assert L.vt_build(ctypes.byref(ctx), ctypes.c_void_p(16), vt.VT_F32, None, items, 1, None, None) == 1
     # no items / null positions
     assert L.vt_build(ctypes.byref(ctx), None, vt.VT_F32, None, items, 1, None, None) == 1
+    assert L.vt_build(ctypes.byref(ctx), ctypes.c_void_p(16), vt.VT_F32, None, items, 0, None, None) == 1
+    # an empty world: a build needs at least one owned particle per item
+    items = vt._items([dict(offset=0, n_owned=0, n_ghost=0, periodic=False, lo=[0, 0, 0], hi=[1, 1, 1])])
+    assert L.vt_build(ctypes.byref(ctx), ctypes.c_void_p(16), vt.VT_F32, None, items, 1, None, None) == 1
     # calls on a context that was never built
     assert L.vt_cells(None, None, None, None, 0, None, None) == 7
     sizes = (ctypes.c_int64 * 3)()

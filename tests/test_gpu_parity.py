@@ -128,6 +128,40 @@ def test_bounded_world(vt, torch_cuda, oracle):
     assert abs(cells.volume.cpu().numpy().sum() - 1.0) < 1e-12
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 65, 257])
+def test_tiny_and_ragged_bounded_worlds(vt, torch_cuda, oracle, n):
+    """Degenerate and ragged sizes: a bounded world whose six faces are its own walls (a survey
+    volume's edge), from a single particle (its cell is the whole box, no neighbours) through counts
+    that leave a wavefront or a block partly empty; every cell against the oracle, none incomplete,
+    the volumes summing to the box."""
+    torch = torch_cuda
+    hi = [1.0, 0.7, 1.3]
+    p = np.random.default_rng(100 + n).random((n, 3)) * hi
+    t = torch.from_numpy(p).cuda()
+    ctx = vt.Context().vt_build(t, vt.whole_box(n, 0.0, hi, periodic=False, walls=63), want_faces=True)
+    assert ctx.vt_query()[0] == 0
+    cells = ctx.vt_cells()
+    ref = oracle.cells(p, 0.0, hi, periodic=False)
+    compare_rows(cells, ref, np.arange(n), 1e-12, "bounded n=%d" % n)
+    assert np.all(cells.status.cpu().numpy() == 0)
+    vol = cells.volume.cpu().numpy()
+    assert abs(vol.sum() - 0.91) <= 1e-12 * 0.91
+    if n == 1:
+        assert cells.nbr_off.cpu().numpy().tolist() == [0, 0] and abs(vol[0] - 0.91) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [1001, 4097])
+def test_ragged_periodic_all_cells(vt, torch_cuda, oracle, n):
+    """Periodic unit cube with counts that are not multiples of the wavefront, the block or the
+    Morton table's cells: every cell against the oracle."""
+    p = np.random.default_rng(7 + n).random((n, 3))
+    ctx, code, cells = run(vt, torch_cuda, p, 0.0, 1.0)
+    assert code == 0
+    ref = oracle.cells(p, 0.0, 1.0)
+    compare_rows(cells, ref, np.arange(n), 1e-12, "periodic n=%d" % n)
+    assert abs(cells.volume.cpu().numpy().sum() - 1.0) < 1e-12
+
+
 def test_large_cell_uses_big_kernel(vt, torch_cuda, oracle):
     # a particle at the centre of a Fibonacci sphere of 90 particles: its cell has 90 facets
     m = 90
