@@ -25,8 +25,18 @@
 // and its topology record holds VT_TOPO_FACES; fewer slots than 64 leave LDS for a fourth wave per SIMD.
 __host__ __device__ constexpr int clip_faces(int vpl) { return vpl == 1 ? VT_TOPO_FACES : 64 * vpl; }
 
+// The large kernel's sweeps cover their shell with boxes refined where they hold many particles
+// (cover_fine): two lists of boxes, the input and the output of a refinement round.
+#define VT_FINE_CAP 512
+struct FineLists {
+    uint64_t pk[2][VT_FINE_CAP];  // unwrapped box coordinates and level, packed (pack_box)
+    int32_t b[2][VT_FINE_CAP];    // particle range start
+    int32_t n[2][VT_FINE_CAP];    // range length; the prefix of the lengths once the list is final
+    float d[2][VT_FINE_CAP];      // squared distance of the box from the seed, rounded down
+};
+
 template <typename T, int VPL>
-struct ClipMem {
+struct ClipMemBase {
     union {
         struct {
             double cd[VT_CAND_MAX][3];   // candidate separations (FP64)
@@ -50,6 +60,25 @@ struct ClipMem {
     int32_t hist[64];                    // gather: d^2 histogram of the shell
     PolyMem<T, VPL, clip_faces(VPL)> P;
 };
+template <typename T, int VPL>
+struct ClipMem : ClipMemBase<T, VPL> {};
+template <typename T>
+struct ClipMem<T, 4> : ClipMemBase<T, 4> {
+    FineLists fine;
+};
+
+// a box of the Morton grid at `level` by its unwrapped integer coordinates (each within 2^17 of
+// the grid, 18 bits) and its level, in one word
+__device__ __forceinline__ uint64_t pack_box(const int u[3], int level) {
+    return ((uint64_t)(uint32_t)(u[0] + (1 << 17)) << 46) | ((uint64_t)(uint32_t)(u[1] + (1 << 17)) << 28) |
+           ((uint64_t)(uint32_t)(u[2] + (1 << 17)) << 10) | (uint64_t)(uint32_t)level;
+}
+__device__ __forceinline__ int unpack_box(uint64_t pk, int u[3]) {
+    u[0] = (int)((pk >> 46) & 0x3FFFFu) - (1 << 17);
+    u[1] = (int)((pk >> 28) & 0x3FFFFu) - (1 << 17);
+    u[2] = (int)((pk >> 10) & 0x3FFFFu) - (1 << 17);
+    return (int)(pk & 0x1Fu);
+}
 
 struct ClipArgs {
     const void *spos;
@@ -475,6 +504,221 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             }
             return S.rb[lo] + (f - S.rp[lo]);
         };
+        // The large kernel's sweeps: its cells lie next to dense halos, whose thousands of particles
+        // sit in a few covering boxes that some vertex's empty sphere reaches at their edge.  The
+        // boxes of the plain cover that hold more than 128 particles are split into their eight
+        // children, one Morton level finer, for up to three rounds while the list has room; a child
+        // is kept when it meets the shell [rmin, r), some vertex's empty sphere reaches it (the test
+        // of the plain cover: a particle cuts the cell only from inside such a sphere, and the cell
+        // only shrinks) and it holds particles.  The kept boxes are sorted by their distance from the
+        // seed, so the sweep takes the shell nearest first and stops at the first box beyond 2R.
+        // Returns the number of boxes (their ranges in S.fine.b / .n of list `fin`, .n the prefix of
+        // the lengths, .d the squared distances), or -1 for a shell that wraps around the period
+        // (the plain cover serves it).
+        int fin = 0;
+        auto cover_fine = [&](double r, double rmin, int &total) -> int {
+            if constexpr (RETRY && VPL > 1) {
+                int lvl = 0;
+                double c = it.S;
+                while (lvl < VT_MORTON_BITS && c >= r) {
+                    c *= 0.5;
+                    ++lvl;
+                }
+                const int sh = VT_MORTON_BITS - lvl;
+                const int ncl = 1 << lvl;
+                const double quantum = it.S / (double)(1 << VT_MORTON_BITS);
+                int a0[3], na[3];
+                for (int a = 0; a < 3; ++a) {
+                    int64_t i0 = (vt_qraw(xs[a] - r, it.lo[a], it.inv_res) - 1) >> sh;
+                    int64_t i1 = (vt_qraw(xs[a] + r, it.lo[a], it.inv_res) + 1) >> sh;
+                    if (it.periodic) {
+                        if (i1 - i0 + 1 >= ncl) return -1;
+                    } else {
+                        if (i0 < 0) i0 = 0;
+                        if (i1 > ncl - 1) i1 = ncl - 1;
+                    }
+                    a0[a] = (int)i0;
+                    na[a] = i1 >= i0 ? (int)(i1 - i0 + 1) : 0;
+                }
+                const double r2 = r * r, rmin2 = rmin * rmin;
+                double off_lo[3];
+                for (int a = 0; a < 3; ++a) off_lo[a] = it.lo[a] - quantum - xs[a];
+                uint64_t farv[VPL];
+#pragma unroll
+                for (int s_ = 0; s_ < VPL; ++s_)
+                    farv[s_] = __ballot((P.alive[s_] & mybit) && 2.0 * S.u.s.vr[s_ * 64 + lane] * (1.0 + 1e-7) >= rmin);
+                // box u at level l (unwrapped coordinates): does it meet the shell and is it reached
+                // by a vertex's empty sphere?  dmin2: its squared distance from the seed
+                auto box_test = [&](int l, const int u[3], double &dmin2) -> bool {
+                    const double cl = it.S / (double)(1 << l), cw = cl + 2.0 * quantum;
+                    double bl[3], bh[3], dmax2 = 0.0;
+                    dmin2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        bl[a] = fma((double)u[a], cl, off_lo[a]);
+                        bh[a] = bl[a] + cw;
+                        const double dn = fmax(0.0, fmax(bl[a], -bh[a]));
+                        const double df = fmax(fabs(bl[a]), fabs(bh[a]));
+                        dmin2 = fma(dn, dn, dmin2);
+                        dmax2 = fma(df, df, dmax2);
+                    }
+                    if (!(dmin2 < r2 && dmax2 >= rmin2)) return false;
+                    bool reached = false;
+#pragma unroll
+                    for (int s_ = 0; s_ < VPL; ++s_) {
+                        uint64_t m = farv[s_];
+                        while (m && !reached) {
+                            const int kv = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const double *v = S.u.s.vp[s_ * 64 + kv];
+                            const double ex = fmax(0.0, fmax(bl[0] - v[0], v[0] - bh[0]));
+                            const double ey = fmax(0.0, fmax(bl[1] - v[1], v[1] - bh[1]));
+                            const double ez = fmax(0.0, fmax(bl[2] - v[2], v[2] - bh[2]));
+                            const double rv = S.u.s.vr[s_ * 64 + kv];
+                            reached = ex * ex + ey * ey + ez * ez < rv * rv;
+                        }
+                    }
+                    return reached;
+                };
+                auto box_range = [&](int l, const int u[3], int32_t &b, int32_t &e) {
+                    const int n_l = 1 << l;
+                    uint32_t cc[3];
+                    for (int a = 0; a < 3; ++a) cc[a] = (uint32_t)(it.periodic ? (u[a] & (n_l - 1)) : u[a]);
+                    const uint64_t mc = l <= 10 ? (uint64_t)((spread3_10(cc[0]) << 2) | (spread3_10(cc[1]) << 1) |
+                                                             spread3_10(cc[2]))
+                                                : vt_morton(cc[0], cc[1], cc[2]);
+                    cell_range_m(A, it, bi, l, mc, b, e);
+                };
+                // the coarse window (at most 216 boxes)
+                int cur = 0, ncur = 0;
+                const int nbox = na[0] * na[1] * na[2], na01 = na[0] * na[1];
+                const float inv0 = 1.0f / (float)(na[0] > 0 ? na[0] : 1), inv01 = 1.0f / (float)(na01 > 0 ? na01 : 1);
+                for (int base = 0; base < nbox; base += WAVE) {
+                    const int k = base + lane;
+                    bool keep = false;
+                    int32_t b = 0, e = 0;
+                    int u[3] = {0, 0, 0};
+                    double dm = 0.0;
+                    if (k < nbox) {
+                        const int iz = (int)(((float)k + 0.5f) * inv01);
+                        const int rem = k - iz * na01;
+                        const int iy = (int)(((float)rem + 0.5f) * inv0);
+                        u[0] = a0[0] + rem - iy * na[0];
+                        u[1] = a0[1] + iy;
+                        u[2] = a0[2] + iz;
+                        keep = box_test(lvl, u, dm);
+                        if (keep) {
+                            box_range(lvl, u, b, e);
+                            keep = e > b;
+                        }
+                    }
+                    const uint64_t km = __ballot(keep);
+                    if (keep) {
+                        const int slot = ncur + __popcll(km & lt);
+                        S.fine.pk[0][slot] = pack_box(u, lvl);
+                        S.fine.b[0][slot] = b;
+                        S.fine.n[0][slot] = e - b;
+                        S.fine.d[0][slot] = __double2float_rd(dm);
+                    }
+                    ncur += __popcll(km);
+                }
+                wave_sync();
+                // refinement: eight lanes per box, one child each
+                for (int round = 0; round < 3; ++round) {
+                    int nnext = 0;
+                    bool split_any = false;
+                    for (int base = 0; base < ncur; base += 8) {
+                        const int i = base + (lane >> 3), ch = lane & 7;
+                        // room for this step's children and every later box unsplit
+                        const bool room = nnext + WAVE + (ncur - base - 8 > 0 ? ncur - base - 8 : 0) <= VT_FINE_CAP;
+                        bool keep = false, split = false;
+                        uint64_t pk = 0;
+                        int32_t b = 0, len = 0;
+                        float dd = 0.0f;
+                        if (i < ncur) {
+                            pk = S.fine.pk[cur][i];
+                            b = S.fine.b[cur][i];
+                            len = S.fine.n[cur][i];
+                            dd = S.fine.d[cur][i];
+                            int u[3];
+                            const int l = unpack_box(pk, u);
+                            split = room && len > 128 && l < VT_MORTON_BITS;
+                            if (!split) {
+                                keep = ch == 0;
+                            } else {
+                                const int uc[3] = {2 * u[0] + ((ch >> 2) & 1), 2 * u[1] + ((ch >> 1) & 1), 2 * u[2] + (ch & 1)};
+                                double dm = 0.0;
+                                keep = box_test(l + 1, uc, dm);
+                                if (keep) {
+                                    int32_t e;
+                                    box_range(l + 1, uc, b, e);
+                                    len = e - b;
+                                    keep = len > 0;
+                                    pk = pack_box(uc, l + 1);
+                                    dd = __double2float_rd(dm);
+                                }
+                            }
+                        }
+                        split_any |= __ballot(split) != 0;
+                        const uint64_t km = __ballot(keep);
+                        if (keep) {
+                            const int slot = nnext + __popcll(km & lt);
+                            S.fine.pk[cur ^ 1][slot] = pk;
+                            S.fine.b[cur ^ 1][slot] = b;
+                            S.fine.n[cur ^ 1][slot] = len;
+                            S.fine.d[cur ^ 1][slot] = dd;
+                        }
+                        nnext += __popcll(km);
+                    }
+                    wave_sync();
+                    cur ^= 1;
+                    ncur = nnext;
+                    if (!split_any) break;
+                }
+                // nearest boxes first (ties by position in the list), lengths -> prefix
+                uint64_t kk[VT_FINE_CAP / 64];
+#pragma unroll
+                for (int q = 0; q < VT_FINE_CAP / 64; ++q) {
+                    const int i = q * 64 + lane;
+                    kk[q] = i < ncur ? ((uint64_t)__float_as_uint(S.fine.d[cur][i]) << 32) | (uint64_t)i : ~0ull;
+                }
+                bitonic_u64<VT_FINE_CAP / 64>(kk);
+                int carry = 0;
+#pragma unroll
+                for (int q = 0; q < VT_FINE_CAP / 64; ++q) {
+                    const int i = q * 64 + lane, sl = (int)(kk[q] & 0xFFFFu);
+                    const bool ok = i < ncur;
+                    const int len = ok ? S.fine.n[cur][sl] : 0;
+                    int tot;
+                    const int pre = wave_excl_scan(len, &tot);
+                    if (ok) {
+                        S.fine.b[cur ^ 1][i] = S.fine.b[cur][sl];
+                        S.fine.n[cur ^ 1][i] = carry + pre;
+                        S.fine.d[cur ^ 1][i] = S.fine.d[cur][sl];
+                    }
+                    carry += tot;
+                }
+                wave_sync();
+                fin = cur ^ 1;
+                total = uni_i(carry);
+                return uni_i(ncur);
+            } else {
+                total = 0;
+                return -1;
+            }
+        };
+        // particle f of the refined cover -> its sorted index
+        auto locate_fine = [&](int f, int ncq) -> int32_t {
+            if constexpr (RETRY && VPL > 1) {
+                int lo = 0, hi = ncq - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (S.fine.n[fin][mid] <= f) lo = mid; else hi = mid - 1;
+                }
+                return S.fine.b[fin][lo] + (f - S.fine.n[fin][lo]);
+            } else {
+                return 0;
+            }
+        };
         // a loaded position -> separation from the seed (minimum image), d^2
         auto separation = [&](const PT4 &p, double &dx, double &dy, double &dz) -> double {
             dx = (double)p.x - sx;
@@ -496,23 +740,39 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             // stage the cell's vertices for the box pruning of the cover (and the first chunk)
             P.update_r2();
             stage_search();
-            const int ncq = cover(r_hi, r_lo, total, true);
-            bool dirty = false;
+            int ncq = -1;
+            if constexpr (RETRY) ncq = cover_fine(r_hi, r_lo, total);
+            const bool fine_ = RETRY && ncq >= 0;
+            if (!fine_) ncq = cover(r_hi, r_lo, total, true);
+            auto loc = [&](int f) -> int32_t { return fine_ ? locate_fine(f, ncq) : locate(f, ncq); };
+            bool dirty = false, r2stale = false;
+            int rr = 0;  // refined cover: box of the chunk's first particle
             // positions of the next 64 particles are loaded while the current 64 are tested
             int32_t jn = -1;
             PT4 pn{};
             if (lane < total) {
-                jn = locate(lane, ncq);
+                jn = loc(lane);
                 pn = ((const PT4 *)A.spos)[jn];
             }
             for (int base = 0; base < total && !overflow && !corrupt; base += WAVE) {
+                if constexpr (RETRY && VPL > 1) {
+                    if (fine_) {
+                        // boxes nearest first: once the chunk's first box lies beyond 2R, so do all later ones
+                        while (rr + 1 < ncq && S.fine.n[fin][rr + 1] <= base) ++rr;
+                        if (r2stale) {
+                            P.update_r2();
+                            r2stale = false;
+                        }
+                        if ((double)S.fine.d[fin][rr] >= 4.0 * P.R2) break;
+                    }
+                }
                 const int f = base + lane;
                 bool keep = false;
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
                 const int32_t j = jn;
                 const PT4 pc = pn;
                 if (f + WAVE < total) {
-                    jn = locate(f + WAVE, ncq);
+                    jn = loc(f + WAVE);
                     pn = ((const PT4 *)A.spos)[jn];
                 }
                 if (f < total) {
@@ -592,6 +852,7 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                     const int rc = P.clip(S.P, p64, tag);
                     if (rc == CLIP_CUT) {
                         dirty = true;
+                        r2stale = true;
                         ++ncut;
                     } else if (rc == CLIP_OVERFLOW) {
                         overflow = true;
