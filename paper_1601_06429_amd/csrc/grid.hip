@@ -588,8 +588,13 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
             };
             // Items are classified 64 at a time: hs (e - ny y - nz z), positive where the face lies
             // above X, is affine over R, so its extremes are at R's corners; a face entirely below X
-            // over R adds nothing.  The others are queued and integrated 64 at a time, so the lanes
-            // of an integration pass all have an item.
+            // over R adds nothing.  A plane with the face entirely above it over R needs no item of
+            // its own: G there is an affine function of X over the same region, G(X) = G(X0) +
+            // (X0 - X) A, with X0 the plane below the face's x minimum, whose item (pi == 0)
+            // integrates A and G(X0) and also emits these planes' contributions (they are the planes
+            // from the lowest up to the first that cuts the face over R, as the bound above falls
+            // with X).  The others are queued and integrated 64 at a time, so the lanes of an
+            // integration pass all have an item.
             int head = 0, qn = 0;
             for (int base = 0; base < nitem; base += 64) {
                 const int item = base + lane;
@@ -608,7 +613,8 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
                     const ItemGeo g = geometry(q, pi, rj, rk);
                     const double cy_ = -g.hs * S.fn[q][1] * h[1], cz_ = -g.hs * S.fn[q][2] * h[2];
                     const double above_max = g.hs * g.e + fmax(0.0, cy_) + fmax(0.0, cz_);
-                    need = pi == 0 || above_max > 0.0;
+                    const double above_min = g.hs * g.e + fmin(0.0, cy_) + fmin(0.0, cz_);
+                    need = pi == 0 || (above_max > 0.0 && above_min < 0.0);
                     desc = (uint64_t)q | ((uint64_t)pi << 8) | ((uint64_t)rj << 24) | ((uint64_t)rk << 44);
                 }
                 const uint64_t nb = __ballot(need);
@@ -639,6 +645,20 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
                                 const int64_t iend = g.mm < i0[0] + bx ? g.mm : i0[0] + bx;
                                 for (int64_t i = i0[0]; i < iend; ++i) emit(i, g.jj, g.kk, hs * h[0] * Rg.A);
                                 emit(g.mm, g.jj, g.kk, G);
+                                // the planes with the face entirely above them over R (classified
+                                // with the same geometry and bound, so none is queued as well)
+                                const int npl = S.fpl[q][1];
+#pragma unroll 1
+                                for (int p = 1; p <= npl; ++p) {
+                                    // geometry(q, p, rj, rk)'s X and e, the same expressions
+                                    const int64_t mp = (int64_t)S.fpl[q][0] + p - 1;
+                                    const double Xp = mp * h[0] + del[0] - g0[0];
+                                    const double ep = S.fn[q][3] - S.fn[q][0] * Xp - S.fn[q][1] * g.Y0 - S.fn[q][2] * g.Z0;
+                                    if (hs * ep + fmin(0.0, cy_) + fmin(0.0, cz_) < 0.0) break;
+                                    const double Gp = hs * (Rg.G + (g.X - Xp) * Rg.A);
+                                    emit(mp - 1, g.jj, g.kk, -Gp);
+                                    emit(mp, g.jj, g.kk, Gp);
+                                }
                             }
                         } else {
                             emit(g.mm - 1, g.jj, g.kk, -G);
