@@ -631,8 +631,19 @@ def main():
             torch.cuda.synchronize()
             tb = time.perf_counter()
             code2 = c2.vt_query()[0]
+            # the fast clip kernel of this precision against its own vector peak: the same cells, so
+            # the same algorithmic flops as the benchmarked build (its cost model above)
+            kms = 0.0
+            for _ in range(3):
+                c2.vt_build(pos, items, precision=p, want_faces=False, timing=True, **opts)
+                kms += c2.vt_timings()[1] / 3
+            dt = "f64" if p == vt.PREC_FP64 else "f32"
             var[name] = {"fwd_cells_per_s": N * reps / (tb - ta), "status": vt.STATUS_NAMES.get(code2),
-                         "launch_options": opts or "defaults"}
+                         "launch_options": opts or "defaults",
+                         "clip_roofline": {"kernel": "k_clip fast", "bound": "alu", "launch_ms": kms,
+                                           "achieved": alg_flops / (kms * 1e-3) / 1e12, "peak": PEAK_TFLOPS[dt],
+                                           "unit": "TFLOP/s",
+                                           "frac": alg_flops / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[dt]}}
             del c2
         out["precision_variants"] = var
 
