@@ -450,11 +450,15 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                         bool reached = false;
 #pragma unroll
                         for (int s_ = 0; s_ < VPL; ++s_) {
+                            // two vertices per step, their loads issued together
                             uint64_t m = farv[s_];
                             while (m && !reached) {
-                                const int kv = __builtin_ctzll(m);
+                                const int k0 = __builtin_ctzll(m);
                                 m &= m - 1;
-                                reached = reaches(s_ * 64 + kv);
+                                const int k1 = m ? __builtin_ctzll(m) : k0;
+                                m &= m - 1;
+                                const bool r0 = reaches(s_ * 64 + k0), r1 = reaches(s_ * 64 + k1);
+                                reached = r0 || r1;
                             }
                         }
                         keep = reached;
@@ -1025,11 +1029,15 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                             };
 #pragma unroll
                             for (int s = 0; s < VPL; ++s) {
+                                // two vertices per step, their loads issued together
                                 uint64_t m = farv[s];
                                 while (m && !act) {
-                                    const int k = __builtin_ctzll(m);
+                                    const int k0 = __builtin_ctzll(m);
                                     m &= m - 1;
-                                    act = cuts_v(s * 64 + k);
+                                    const int k1 = m ? __builtin_ctzll(m) : k0;
+                                    m &= m - 1;
+                                    const bool c0 = cuts_v(s * 64 + k0), c1 = cuts_v(s * 64 + k1);
+                                    act = c0 || c1;
                                 }
                             }
                         }
