@@ -8,7 +8,7 @@ the security radius proves it; pinned against the brute force in the CPU tests).
   large clip kernel computed, against the oracle: neighbour lists bit-exact, volumes and densities
   within 1e-12 (FP64) / 2e-5 (mixed); density gradients of 512 seeded and the retried cells within
   the same bars, scaled by max(|grad|, rho / V^(1/3));
-* lattice+halos 16M (FP32, mixed and FP64 paths): 4096 sampled cells against the oracle, plus
+* lattice+halos 16M (FP32, mixed and FP64 paths): the 65,536-particle sampled subset against the oracle, plus
   volume conservation over the whole box;
 * clustered 2M at 256^3 (the benchmark's deposit): a field that is zero except on 96 sampled
   cells (random ones and cells the large kernels handle), every voxel against the oracle's
@@ -65,8 +65,18 @@ def clustered2m_tree(clustered2m):
     return cKDTree(w.pos.astype(np.float64) - w.box_lo, boxsize=w.box_len)
 
 
+@pytest.fixture(scope="module")
+def lattice16m_ref(oracle, lattice16m, lattice16m_tree):
+    """The oracle's cells of the workload's 65,536-particle sampled subset (one computation for
+    both precisions)."""
+    w = lattice16m
+    rng = np.random.default_rng(3003)
+    sample = np.sort(rng.choice(w.n, 65536, replace=False))
+    return sample, oracle.local_cells(w.pos.astype(np.float64), w.box_lo, w.box_hi, sample, tree=lattice16m_tree)
+
+
 @pytest.mark.parametrize("precision", [1, 0])
-def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, lattice16m_tree, precision):
+def test_lattice_halos_16m_sampled(vt, torch_cuda, lattice16m, lattice16m_ref, precision):
     w = lattice16m
     t = torch_cuda.from_numpy(w.pos).cuda()
     ctx = vt.Context().vt_build(t, vt.whole_box(w.n, w.box_lo, w.box_hi), precision=precision)
@@ -79,14 +89,12 @@ def test_lattice_halos_16m_sampled(vt, torch_cuda, oracle, lattice16m, lattice16
     ids = cells.nbr_ids.cpu().numpy()
     del ctx, cells, t
     torch_cuda.cuda.empty_cache()
-    rng = np.random.default_rng(3003)
-    sample = np.sort(rng.choice(w.n, 4096, replace=False))
-    ref = oracle.local_cells(w.pos.astype(np.float64), w.box_lo, w.box_hi, sample, tree=lattice16m_tree)
+    sample, ref = lattice16m_ref
     worst = 0.0
     for q, i in enumerate(sample):
         assert np.array_equal(ids[off[i]:off[i + 1]], ref.neighbours(q)), i
         worst = max(worst, abs(vol[i] - ref.volume[q]) / ref.volume[q])
-    print("lattice+halos 16M, precision %d: 4096 cells, worst volume error %.2e" % (precision, worst))
+    print("lattice+halos 16M, precision %d: %d sampled cells, worst volume error %.2e" % (precision, len(sample), worst))
     assert worst <= TOL[precision]
 
 
