@@ -506,6 +506,11 @@ def main():
     counters = clip_counters() if prec == vt.PREC_FP64 else None
     bench_vol, bench_off = vol.cpu().numpy(), off.cpu().numpy()
     bench_ids, bench_rho = ids[: int(bench_off[-1])].cpu().numpy(), rho.cpu().numpy()
+    bench_grad = None if args.fwd_only else grad.cpu().numpy()
+    # the deposit conserves mass: the voxel averages times the voxel volume sum to the total mass
+    grid_mass_err = None if args.fwd_only else float(
+        abs(float(grid.sum()) * float(np.prod(w.box_len)) / float(np.prod(grid_dims)) - float(w.mass.sum())) /
+        float(w.mass.sum()))
 
     out = {
         "metric": METRIC,
@@ -532,6 +537,7 @@ def main():
                      "sort": build_ms[0], "clip": build_ms[1], "clip_large": build_ms[2]},
         "nnz": nnz,
         "retried_cells": retried,
+        "grid_mass_rel_err": grid_mass_err,
         "roofline": {"kernel": "k_clip fast (cells up to 64 vertices)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype],
                      "traffic": measured_traffic() if prec == vt.PREC_FP64 else None,
@@ -689,8 +695,31 @@ def main():
         same = all(np.array_equal(bench_ids[bench_off[i]:bench_off[i + 1]], ref.neighbours(q))
                    for q, i in enumerate(sample))
         rel = np.abs(bench_vol[sample] - ref.volume) / ref.volume
+        drel = np.abs(bench_rho[sample] - dens) / dens
         out["parity_on_sample"] = {"neighbours_bit_exact": bool(same), "max_rel_volume_err": float(rel.max()),
-                                   "max_rel_density_err": float(np.max(np.abs(bench_rho[sample] - dens) / dens))}
+                                   "p99_rel_volume_err": float(np.percentile(rel, 99)),
+                                   "max_rel_density_err": float(drel.max()),
+                                   "p99_rel_density_err": float(np.percentile(drel, 99))}
+        if bench_grad is not None:
+            # density gradients of the sample's first 256 cells: the oracle's densities of those
+            # cells and of all their neighbours (the others from its local-world cells), its
+            # least-squares formula; error scaled by max(|grad|, rho / V^(1/3))
+            ng = min(256, len(sample))
+            grows = sample[:ng]
+            nb = np.unique(np.concatenate([ref.neighbours(q) for q in range(ng)]))
+            need = np.setdiff1d(nb, sample)
+            refn = oracle.local_cells(p64, w.box_lo, w.box_hi, need, workers=nthr)
+            rho_ref = np.full(N, np.nan)
+            rho_ref[sample] = w.mass[sample] / ref.volume
+            rho_ref[need] = w.mass[need] / refn.volume
+            goff = np.zeros(ng + 1, np.int64)
+            goff[1:] = np.cumsum([ref.nnb[q] for q in range(ng)])
+            gids = np.concatenate([ref.neighbours(q) for q in range(ng)])
+            gref = oracle.gradient(p64, w.box_lo, w.box_hi, True, goff, gids, rho_ref, rows=grows)
+            scale = np.maximum(np.linalg.norm(gref, axis=1), rho_ref[grows] / np.cbrt(ref.volume[:ng]))
+            gerr = np.linalg.norm(bench_grad[grows] - gref, axis=1) / scale
+            out["parity_on_sample"]["gradient_cells"] = int(ng)
+            out["parity_on_sample"]["max_scaled_gradient_err"] = float(gerr.max())
     print(json.dumps(out))
 
 
