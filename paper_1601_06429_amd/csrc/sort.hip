@@ -246,20 +246,61 @@ __global__ void k_sorted_gather(const PT *pos, const int32_t *gid, const uint32_
     sorig[j] = (int32_t)p;
 }
 
-// level-T table: tab[off + c] = first sorted index whose level-T cell is >= c
-__global__ void k_level_table(const uint64_t *skey, int64_t n, const DevItem *items, int n_items, int32_t *tab) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int b = find_item(items, n_items, j);
-    const DevItem &it = items[b];
-    const int sh = 3 * (VT_MORTON_BITS - it.T);
+// level-T table: tab[off + c] = first sorted index whose level-T cell is >= c.  The entries from
+// particle j's predecessor's cell (exclusive) to its own take j, and the last particle of an item
+// also fills the rest of the item's table.  A wavefront's 64 consecutive particles own one
+// contiguous stretch of the table, which its lanes write together, entry by entry (the value of an
+// entry is the first of the 64 whose cell reaches it, found by a binary search over their cells),
+// so the writes are coalesced however unevenly the particles fill the cells.  A wavefront whose
+// particles span two items writes each particle's entries from its own lane.
+__global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64_t n, const DevItem *items,
+                                                     int n_items, int32_t *tab) {
+    __shared__ int64_t cells[4][64];
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int64_t jw = (int64_t)blockIdx.x * blockDim.x + wv * 64;  // the wavefront's first particle
+    if (jw >= n) return;
+    const int64_t j = jw + lane;
+    const bool valid = j < n;
     const uint64_t lmask = (1ull << VT_LOCAL_KEY_BITS) - 1;
-    int64_t c = (int64_t)((skey[j] & lmask) >> sh);
-    int64_t cprev = (j == it.start) ? -1 : (int64_t)((skey[j - 1] & lmask) >> sh);
-    for (int64_t x = cprev + 1; x <= c; ++x) tab[it.tab_off + x] = (int32_t)j;
-    if (j == it.start + it.count - 1) {
-        int64_t ncell = 1ll << (3 * it.T);
-        for (int64_t x = c + 1; x <= ncell; ++x) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
+    int b = valid ? find_item(items, n_items, j) : -1;
+    int64_t c = INT64_MAX, cprev = -1;
+    if (valid) {
+        const DevItem &it = items[b];
+        const int sh = 3 * (VT_MORTON_BITS - it.T);
+        c = (int64_t)((skey[j] & lmask) >> sh);
+        cprev = (j == it.start) ? -1 : (int64_t)((skey[j - 1] & lmask) >> sh);
+    }
+    const int b0 = __shfl(b, 0);
+    if (__ballot(valid && b != b0) != 0) {
+        // the wavefront spans two items
+        if (valid) {
+            const DevItem &it = items[b];
+            for (int64_t x = cprev + 1; x <= c; ++x) tab[it.tab_off + x] = (int32_t)j;
+            if (j == it.start + it.count - 1) {
+                const int64_t ncell = 1ll << (3 * it.T);
+                for (int64_t x = c + 1; x <= ncell; ++x) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
+            }
+        }
+        return;
+    }
+    const DevItem &it = items[b0];
+    cells[wv][lane] = c;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t vm = __ballot(valid);
+    const int last = 63 - __builtin_clzll(vm);
+    const int64_t x0 = (int64_t)__shfl((long long)cprev, 0) + 1, x1 = (int64_t)__shfl((long long)c, last);
+    for (int64_t x = x0 + lane; x <= x1; x += 64) {
+        int lo = 0, hi = last;  // the first particle whose cell is >= x (cells ascend; the last one's is x1)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cells[wv][mid] >= x) hi = mid; else lo = mid + 1;
+        }
+        tab[it.tab_off + x] = (int32_t)(jw + lo);
+    }
+    if (jw + last == it.start + it.count - 1) {
+        const int64_t ncell = 1ll << (3 * it.T);
+        for (int64_t x = x1 + 1 + lane; x <= ncell; x += 64) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
     }
 }
 
