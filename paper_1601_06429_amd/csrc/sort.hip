@@ -174,16 +174,29 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t *key
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter.  Keys of a tile are ranked in index order: round-major, then
-// wave, then lane.  Lanes holding the same digit are found with eight ballots.
+// Stable scatter.  Keys of a tile are ranked in index order: round-major, then wave, then lane;
+// lanes holding the same digit are found with eight ballots.  The tile is first reordered by digit
+// in LDS (its digit counts are the histogram pass's, their prefix the digits' starts in the tile),
+// then written out in that order: consecutive threads write consecutive slots of each digit's run
+// (16 keys per digit on average), not one scattered slot each.
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
                                                                 uint64_t *kout, uint32_t *vout, int64_t n,
-                                                                int shift, const int32_t *offs, int nblocks) {
-    __shared__ int32_t running[256];
+                                                                int shift, const int32_t *counts,
+                                                                const int32_t *offs, int nblocks) {
+    __shared__ int32_t running[256];   // next slot of each digit in the reordered tile
+    __shared__ int64_t gbase[256];     // the digit's global offset minus its start in the tile
     __shared__ int32_t wcnt[SORT_THREADS / 64][256];
+    __shared__ int32_t scan_lds[SORT_THREADS];
+    __shared__ uint64_t lkey[SORT_TILE];
+    __shared__ uint32_t lval[SORT_TILE];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    running[t] = offs[(int64_t)t * nblocks + blockIdx.x];
-    int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    {
+        int32_t tot;
+        const int32_t start = block_exclusive_scan<int32_t>(counts[(int64_t)t * nblocks + blockIdx.x], scan_lds, &tot);
+        running[t] = start;
+        gbase[t] = (int64_t)offs[(int64_t)t * nblocks + blockIdx.x] - start;
+    }
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int i = 0; i < SORT_ITEMS; ++i) {
         for (int ww = 0; ww < SORT_THREADS / 64; ++ww) wcnt[ww][t] = 0;
@@ -204,15 +217,23 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *
         int pre = 0;
         for (int ww = 0; ww < w; ++ww) pre += wcnt[ww][d];
         if (valid) {
-            int64_t pos = (int64_t)running[d] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            const int slot = running[d] + pre + rank;
+            lkey[slot] = key;
+            lval[slot] = val;
         }
         __syncthreads();
         int add = 0;
         for (int ww = 0; ww < SORT_THREADS / 64; ++ww) add += wcnt[ww][t];
         running[t] += add;
         __syncthreads();
+    }
+    const int64_t left = n - base;
+    const int cnt = left < (int64_t)SORT_TILE ? (int)left : SORT_TILE;
+    for (int idx = t; idx < cnt; idx += SORT_THREADS) {
+        const uint64_t key = lkey[idx];
+        const int64_t pos = gbase[(uint32_t)(key >> shift) & 255u] + idx;
+        kout[pos] = key;
+        vout[pos] = lval[idx];
     }
 }
 
@@ -337,7 +358,7 @@ hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid) {
         hipError_t e = vt_launch_scan_i32(c->hist, c->hist + (int64_t)256 * nb, (int64_t)256 * nb, c->scan_tmp, s);
         if (e != hipSuccess) return e;
         k_radix_scatter<<<nb, SORT_THREADS, 0, s>>>(c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], n,
-                                                   shift, c->hist + (int64_t)256 * nb, nb);
+                                                   shift, c->hist, c->hist + (int64_t)256 * nb, nb);
         cur ^= 1;
     }
     c->skey = c->keys[cur];
