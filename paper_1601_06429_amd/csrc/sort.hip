@@ -270,12 +270,42 @@ __global__ void k_sorted_gather(const PT *pos, const int32_t *gid, const uint32_
 // level-T table: tab[off + c] = first sorted index whose level-T cell is >= c.  The entries from
 // particle j's predecessor's cell (exclusive) to its own take j, and the last particle of an item
 // also fills the rest of the item's table.  A wavefront's 64 consecutive particles own one
-// contiguous stretch of the table, which its lanes write together, entry by entry (the value of an
-// entry is the first of the 64 whose cell reaches it, found by a binary search over their cells),
-// so the writes are coalesced however unevenly the particles fill the cells.  A wavefront whose
-// particles span two items writes each particle's entries from its own lane.
+// contiguous stretch of the table.  When the stretch is short its lanes write it together, entry
+// by entry (the value of an entry is the first of the 64 whose cell reaches it, found by a binary
+// search over their cells), so the writes are coalesced however unevenly the particles fill the
+// cells.  Otherwise (empty regions: voids, the part of a cuboid item's Morton cube outside the item,
+// the end of an item's table) each lane writes its own run if it is short, and lists a long run
+// as pieces of at most VT_TAB_PIECE entries, which k_level_fill writes a wavefront per piece; a run
+// that finds the list full is written by its own lane.
+#define VT_TAB_STRETCH 2048
+#define VT_TAB_SHORT 64
+#define VT_TAB_PIECE 4096
+__device__ __forceinline__ void tab_run(int32_t *tab, int64_t lo, int64_t len, int32_t v, uint64_t *pieces,
+                                        int64_t piece_cap, uint32_t *counters) {
+    if (len <= 0) return;
+    if (len > VT_TAB_SHORT) {
+        const int64_t np = (len + VT_TAB_PIECE - 1) / VT_TAB_PIECE;
+        const uint32_t k = atomicAdd(&counters[CTR_TAB_PIECES], (uint32_t)np);
+        if ((int64_t)k + np <= piece_cap) {
+            for (int64_t q = 0; q < np; ++q) {
+                const int64_t a = q * VT_TAB_PIECE, m = len - a < VT_TAB_PIECE ? len - a : VT_TAB_PIECE;
+                pieces[2 * ((int64_t)k + q)] = (uint64_t)(lo + a);
+                pieces[2 * ((int64_t)k + q) + 1] = ((uint64_t)m << 32) | (uint64_t)(uint32_t)v;
+            }
+            return;
+        }
+        // the list is full: slots this reservation holds below the capacity become empty pieces
+        for (int64_t q = k; q < piece_cap; ++q) {
+            pieces[2 * q] = 0;
+            pieces[2 * q + 1] = 0;
+        }
+    }
+    for (int64_t x = 0; x < len; ++x) tab[lo + x] = v;
+}
+
 __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64_t n, const DevItem *items,
-                                                     int n_items, int32_t *tab) {
+                                                     int n_items, int32_t *tab, uint64_t *pieces, int64_t piece_cap,
+                                                     uint32_t *counters) {
     __shared__ int64_t cells[4][64];
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
     const int64_t jw = (int64_t)blockIdx.x * blockDim.x + wv * 64;  // the wavefront's first particle
@@ -292,14 +322,18 @@ __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64
         cprev = (j == it.start) ? -1 : (int64_t)((skey[j - 1] & lmask) >> sh);
     }
     const int b0 = __shfl(b, 0);
-    if (__ballot(valid && b != b0) != 0) {
-        // the wavefront spans two items
+    const uint64_t vm = __ballot(valid);
+    const int last = 63 - __builtin_clzll(vm);
+    const int64_t x0 = (int64_t)__shfl((long long)cprev, 0) + 1, x1 = (int64_t)__shfl((long long)c, last);
+    if (__ballot(valid && b != b0) != 0 || x1 - x0 + 1 > VT_TAB_STRETCH) {
+        // the wavefront spans two items, or its stretch is long: each lane its own run
         if (valid) {
             const DevItem &it = items[b];
-            for (int64_t x = cprev + 1; x <= c; ++x) tab[it.tab_off + x] = (int32_t)j;
+            tab_run(tab, it.tab_off + cprev + 1, c - cprev, (int32_t)j, pieces, piece_cap, counters);
             if (j == it.start + it.count - 1) {
                 const int64_t ncell = 1ll << (3 * it.T);
-                for (int64_t x = c + 1; x <= ncell; ++x) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
+                tab_run(tab, it.tab_off + c + 1, ncell - c, (int32_t)(it.start + it.count), pieces, piece_cap,
+                        counters);
             }
         }
         return;
@@ -308,9 +342,6 @@ __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64
     cells[wv][lane] = c;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t vm = __ballot(valid);
-    const int last = 63 - __builtin_clzll(vm);
-    const int64_t x0 = (int64_t)__shfl((long long)cprev, 0) + 1, x1 = (int64_t)__shfl((long long)c, last);
     for (int64_t x = x0 + lane; x <= x1; x += 64) {
         int lo = 0, hi = last;  // the first particle whose cell is >= x (cells ascend; the last one's is x1)
         while (lo < hi) {
@@ -319,9 +350,24 @@ __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64
         }
         tab[it.tab_off + x] = (int32_t)(jw + lo);
     }
-    if (jw + last == it.start + it.count - 1) {
+    if (jw + last == it.start + it.count - 1 && lane == last) {
         const int64_t ncell = 1ll << (3 * it.T);
-        for (int64_t x = x1 + 1 + lane; x <= ncell; x += 64) tab[it.tab_off + x] = (int32_t)(it.start + it.count);
+        tab_run(tab, it.tab_off + x1 + 1, ncell - x1, (int32_t)(it.start + it.count), pieces, piece_cap, counters);
+    }
+}
+
+// the listed pieces, a wavefront per piece
+__global__ void __launch_bounds__(256) k_level_fill(const uint64_t *pieces, int64_t piece_cap, const uint32_t *counters,
+                                                    int32_t *tab) {
+    const int64_t np = min((int64_t)counters[CTR_TAB_PIECES], piece_cap);
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < np; p += nw) {
+        const int64_t lo = (int64_t)pieces[2 * p];
+        const uint64_t w = pieces[2 * p + 1];
+        const int64_t m = (int64_t)(w >> 32);
+        const int32_t v = (int32_t)(uint32_t)w;
+        for (int64_t x = lane; x < m; x += 64) tab[lo + x] = v;
     }
 }
 
@@ -369,7 +415,11 @@ hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid) {
         k_sorted_gather<double, double4><<<grid, tpb, 0, s>>>((const double *)pos, gid, c->vals[cur], n, c->items,
                                                               c->n_items, (double4 *)c->spos, c->sgid, c->srow,
                                                               c->sorig);
-    k_level_table<<<grid, tpb, 0, s>>>(c->skey, n, c->items, c->n_items, c->tab);
+    // long runs of the table are listed in the spare key buffer (free until the compaction below)
+    uint64_t *pieces = c->keys[cur ^ 1];
+    const int64_t piece_cap = (n + 1) / 2;
+    k_level_table<<<grid, tpb, 0, s>>>(c->skey, n, c->items, c->n_items, c->tab, pieces, piece_cap, c->counters);
+    k_level_fill<<<1024, tpb, 0, s>>>(pieces, piece_cap, c->counters, c->tab);
     // owned cells in Morton order (flags -> scan -> compact); the flag array reuses vals[cur^1]
     int32_t *flag = (int32_t *)c->vals[cur ^ 1];
     int32_t *scan = (int32_t *)c->keys[cur ^ 1];

@@ -39,7 +39,8 @@
 #define CTR_REC_REJECT 12  // topology records that failed their checks (a clip-kernel fault; 0 expected)
 #define CTR_SEG0 13        // fast clip kernel: work counters of the XCD segments (VT_XCD_SEGMENTS words)
 #define VT_XCD_SEGMENTS 8  // XCDs of an MI355X; workgroups are dealt to them round-robin
-#define CTR_COUNT (CTR_SEG0 + VT_XCD_SEGMENTS)
+#define CTR_TAB_PIECES (CTR_SEG0 + VT_XCD_SEGMENTS)  // level table: pieces of long runs listed for k_level_fill
+#define CTR_COUNT (CTR_TAB_PIECES + 1)
 
 // per-item description on the device
 struct DevItem {
