@@ -275,32 +275,55 @@ __global__ void k_sorted_gather(const PT *pos, const int32_t *gid, const uint32_
 // search over their cells), so the writes are coalesced however unevenly the particles fill the
 // cells.  Otherwise (empty regions: voids, the part of a cuboid item's Morton cube outside the item,
 // the end of an item's table) each lane writes its own run if it is short, and lists a long run
-// as pieces of at most VT_TAB_PIECE entries, which k_level_fill writes a wavefront per piece; a run
-// that finds the list full is written by its own lane.
+// as pieces of at most VT_TAB_PIECE entries (slots reserved once per wavefront), which k_level_fill
+// writes a wavefront per piece; runs that find the list full are written by their own lane.
 #define VT_TAB_STRETCH 2048
 #define VT_TAB_SHORT 64
 #define VT_TAB_PIECE 4096
-__device__ __forceinline__ void tab_run(int32_t *tab, int64_t lo, int64_t len, int32_t v, uint64_t *pieces,
-                                        int64_t piece_cap, uint32_t *counters) {
-    if (len <= 0) return;
-    if (len > VT_TAB_SHORT) {
-        const int64_t np = (len + VT_TAB_PIECE - 1) / VT_TAB_PIECE;
-        const uint32_t k = atomicAdd(&counters[CTR_TAB_PIECES], (uint32_t)np);
-        if ((int64_t)k + np <= piece_cap) {
-            for (int64_t q = 0; q < np; ++q) {
-                const int64_t a = q * VT_TAB_PIECE, m = len - a < VT_TAB_PIECE ? len - a : VT_TAB_PIECE;
-                pieces[2 * ((int64_t)k + q)] = (uint64_t)(lo + a);
-                pieces[2 * ((int64_t)k + q) + 1] = ((uint64_t)m << 32) | (uint64_t)(uint32_t)v;
-            }
-            return;
-        }
-        // the list is full: slots this reservation holds below the capacity become empty pieces
-        for (int64_t q = k; q < piece_cap; ++q) {
+__device__ __forceinline__ int64_t tab_pieces(int64_t len) {
+    return len > VT_TAB_SHORT ? (len + VT_TAB_PIECE - 1) / VT_TAB_PIECE : 0;
+}
+
+// Each lane's runs (its own and, for an item's last particle, the tail): short ones written here,
+// long ones listed in slots reserved for the whole wavefront with one atomic; a lane whose slots do
+// not all fit writes its runs itself and leaves its slots below the capacity as empty pieces.
+__device__ __forceinline__ void tab_runs(int32_t *tab, int64_t loA, int64_t lenA, int32_t vA, int64_t loB, int64_t lenB,
+                                         int32_t vB, uint64_t *pieces, int64_t piece_cap, uint32_t *counters) {
+    const int64_t pa = tab_pieces(lenA), pb = tab_pieces(lenB), mine = pa + pb;
+    // inclusive prefix of the lanes' piece counts, then one reservation for the wavefront
+    const int lane = (int)(threadIdx.x & 63);
+    int64_t pre = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = (int64_t)__shfl_up((long long)pre, o);
+        if (lane >= o) pre += y;
+    }
+    const int64_t total = (int64_t)__shfl((long long)pre, 63);
+    pre -= mine;
+    int64_t base = 0;
+    if (total > 0) {
+        if (lane == 0) base = (int64_t)atomicAdd(&counters[CTR_TAB_PIECES], (uint32_t)total);
+        base = (int64_t)__shfl((long long)base, 0);
+    }
+    const int64_t k0 = base + pre;
+    const bool fits = k0 + mine <= piece_cap;
+    if (!fits)
+        for (int64_t q = k0; q < k0 + mine && q < piece_cap; ++q) {
             pieces[2 * q] = 0;
             pieces[2 * q + 1] = 0;
         }
-    }
-    for (int64_t x = 0; x < len; ++x) tab[lo + x] = v;
+    auto put = [&](int64_t lo, int64_t len, int32_t v, int64_t np, int64_t k) {
+        if (np == 0 || !fits) {
+            for (int64_t x = 0; x < len; ++x) tab[lo + x] = v;
+            return;
+        }
+        for (int64_t q = 0; q < np; ++q) {
+            const int64_t a = q * VT_TAB_PIECE, m = len - a < VT_TAB_PIECE ? len - a : VT_TAB_PIECE;
+            pieces[2 * (k + q)] = (uint64_t)(lo + a);
+            pieces[2 * (k + q) + 1] = ((uint64_t)m << 32) | (uint64_t)(uint32_t)v;
+        }
+    };
+    if (lenA > 0) put(loA, lenA, vA, pa, k0);
+    if (lenB > 0) put(loB, lenB, vB, pb, k0 + pa);
 }
 
 __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64_t n, const DevItem *items,
@@ -326,16 +349,20 @@ __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64
     const int last = 63 - __builtin_clzll(vm);
     const int64_t x0 = (int64_t)__shfl((long long)cprev, 0) + 1, x1 = (int64_t)__shfl((long long)c, last);
     if (__ballot(valid && b != b0) != 0 || x1 - x0 + 1 > VT_TAB_STRETCH) {
-        // the wavefront spans two items, or its stretch is long: each lane its own run
+        // the wavefront spans two items, or its stretch is long: each lane its own runs
+        int64_t loA = 0, lenA = 0, loB = 0, lenB = 0;
+        int32_t vB = 0;
         if (valid) {
             const DevItem &it = items[b];
-            tab_run(tab, it.tab_off + cprev + 1, c - cprev, (int32_t)j, pieces, piece_cap, counters);
+            loA = it.tab_off + cprev + 1;
+            lenA = c - cprev;
             if (j == it.start + it.count - 1) {
-                const int64_t ncell = 1ll << (3 * it.T);
-                tab_run(tab, it.tab_off + c + 1, ncell - c, (int32_t)(it.start + it.count), pieces, piece_cap,
-                        counters);
+                loB = it.tab_off + c + 1;
+                lenB = (1ll << (3 * it.T)) - c;
+                vB = (int32_t)(it.start + it.count);
             }
         }
+        tab_runs(tab, loA, lenA, (int32_t)j, loB, lenB, vB, pieces, piece_cap, counters);
         return;
     }
     const DevItem &it = items[b0];
@@ -350,9 +377,11 @@ __global__ void __launch_bounds__(256) k_level_table(const uint64_t *skey, int64
         }
         tab[it.tab_off + x] = (int32_t)(jw + lo);
     }
-    if (jw + last == it.start + it.count - 1 && lane == last) {
-        const int64_t ncell = 1ll << (3 * it.T);
-        tab_run(tab, it.tab_off + x1 + 1, ncell - x1, (int32_t)(it.start + it.count), pieces, piece_cap, counters);
+    if (jw + last == it.start + it.count - 1) {
+        // the item's tail, from the lane of its last particle
+        const bool mine = lane == last;
+        tab_runs(tab, 0, 0, 0, mine ? it.tab_off + x1 + 1 : 0, mine ? (1ll << (3 * it.T)) - x1 : 0,
+                 (int32_t)(it.start + it.count), pieces, piece_cap, counters);
     }
 }
 
