@@ -137,6 +137,22 @@ def clip_counters():
         return None
 
 
+SORT_FILE = os.path.join(ROOT, "profiles", "sort_clustered2m_traffic.md")
+SORT_SOURCES = ["paper_1601_06429_amd/csrc/sort.hip", "paper_1601_06429_amd/csrc/vt_internal.h"]
+
+
+def sort_traffic():
+    """HBM bytes of one build's sort pass from the committed counter summary, while the sort's
+    sources are the ones they were taken from; else None."""
+    kv = _summary(SORT_FILE)
+    if kv.get("sort_source_sha1") != sources_sha1(SORT_SOURCES):
+        return None
+    try:
+        return float(kv["sort_hbm_bytes_per_build"])
+    except (KeyError, ValueError):
+        return None
+
+
 def grid_counters():
     """The same for the grid deposit kernel: VALU issue and lane use against the VALU issue
     peak (one wavefront instruction per SIMD every 4 cycles)."""
@@ -549,6 +565,16 @@ def main():
                      "mean_planes": float(npl.mean()), "mean_vertices": float(nv.mean()),
                      "mean_tested": float(ntest.to(torch.float64).mean())},
     }
+    # the sort pass against HBM: the algorithmic bytes of a counting sort, about 40 B per particle
+    # (positions read, keys written and read, the permutation and the sorted arrays written), over
+    # its event-timed duration; `traffic` the bytes the counters measured for the radix sort used
+    sort_alg = 40.0 * N
+    st_b = sort_traffic() if w.name.startswith("clustered") else None
+    out["sort_roofline"] = {"kernel": "sort pass (keys, six 8-bit radix passes, sorted gather, level table, owned list)",
+                            "bound": "hbm", "achieved": sort_alg / (build_ms[0] * 1e-3) / 1e9, "peak": 8000.0,
+                            "unit": "GB/s", "frac": sort_alg / (build_ms[0] * 1e-3) / 1e9 / 8000.0,
+                            "alg_bytes_per_build": sort_alg, "launch_ms": build_ms[0], "traffic": st_b,
+                            "traffic_GB_per_s": st_b / (build_ms[0] * 1e-3) / 1e9 if st_b else None}
     gc = grid_counters()
     if gc and not args.fwd_only:
         out["grid_roofline"] = dict(gc, kernel="k_grid_fused (256^3 deposit)", bound="alu",
