@@ -236,14 +236,15 @@ def batched_forms(torch, vt, reps=5):
     return res
 
 
-def decomposed_form(torch, vt, w, nt=(4, 4, 4), border_factor=1.5, reps=3):
+def decomposed_form(torch, vt, w, nt=(4, 4, 4), border_factor=1.5, reps=3, opts=None):
     """The workload as nt tasks with AUTOBORDER buffers (section 2), in the library
     (vt_decomposed_build): thicknesses, all tasks packed and built as one batch, incomplete cells
     built again with wider buffers, results stitched in particle order.  An untimed run checks the
     result against the whole-box cells; the timed runs repeat the whole call plus vt_cells."""
     pos = torch.from_numpy(w.pos).cuda()
     n = w.n
-    res = vt.decomposed_build(pos, w.box_lo, w.box_hi, nt, border_factor=border_factor)
+    opts = dict(opts or {})
+    res = vt.decomposed_build(pos, w.box_lo, w.box_hi, nt, border_factor=border_factor, **opts)
     whole = vt.Context().vt_build(pos, vt.whole_box(n, w.box_lo, w.box_hi)).vt_cells()
     same_nbrs = bool(np.array_equal(res["nbr_off"], whole.nbr_off.cpu().numpy()) and
                      np.array_equal(res["nbr_ids"], whole.nbr_ids.cpu().numpy()))
@@ -257,7 +258,7 @@ def decomposed_form(torch, vt, w, nt=(4, 4, 4), border_factor=1.5, reps=3):
     ids = torch.empty(nnz, dtype=torch.int32, device="cuda")
 
     def run():
-        ctx.vt_decomposed_build(pos, w.box_lo, w.box_hi, nt, border_factor=border_factor)
+        ctx.vt_decomposed_build(pos, w.box_lo, w.box_hi, nt, border_factor=border_factor, **opts)
         ctx.vt_cells_into(vol, off, ids)
 
     run()
@@ -270,7 +271,8 @@ def decomposed_form(torch, vt, w, nt=(4, 4, 4), border_factor=1.5, reps=3):
     ms = (tb - ta) * 1e3 / reps
     s = float(np.cbrt(np.prod(w.box_len) / n))
     grow = res["thick"] / (border_factor * s)
-    return {"workload": w.name, "tasks": list(nt), "border_factor": border_factor, "ms": ms,
+    return {"workload": w.name, "tasks": list(nt), "border_factor": border_factor, "launch_options": opts or "defaults",
+            "ms": ms,
             "cells_per_s": n / (ms * 1e-3),
             "step": "vt_decomposed_build (thicknesses, packing, builds of every pass, stitching) + vt_cells",
             "faces_widened": float(np.mean(grow > 1.0 + 1e-12)), "max_widening": float(grow.max()),
@@ -686,7 +688,7 @@ def main():
 
     if not args.no_decomposed and not args.fwd_only and w.name.startswith("clustered"):
         torch.cuda.empty_cache()
-        out["decomposed"] = decomposed_form(torch, vt, w)
+        out["decomposed"] = decomposed_form(torch, vt, w, opts=tuned if prec == vt.PREC_FP64 else None)
 
     if not args.no_extra:
         torch.cuda.empty_cache()

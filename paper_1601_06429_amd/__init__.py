@@ -497,7 +497,7 @@ class Context:
 
     def vt_decomposed_build(self, pos, box_lo, box_hi, nt, border_factor=1.5, periodic=True, max_reruns=0,
                             widen=0.0, growth=0.0, n_steps=0, precision=PREC_FP64, radius_factor=0.0,
-                            waves_per_cu=0, stream=None):
+                            waves_per_cu=0, k_init=0, pts_per_grid_cell=0.0, cell_mapping=0, stream=None):
         """The whole AUTOBORDER procedure in the library; afterwards vt_cells / vt_density /
         vt_query answer in particle order.  Returns (first-pass thicknesses n_tasks x 6,
         per-pass [tasks, particles packed, cells built, cells left incomplete])."""
@@ -508,6 +508,9 @@ class Context:
         o.precision = int(precision)
         o.radius_factor = float(radius_factor)
         o.waves_per_cu = int(waves_per_cu)
+        o.k_init = int(k_init)
+        o.pts_per_grid_cell = float(pts_per_grid_cell)
+        o.cell_mapping = int(cell_mapping)
         n_tasks = int(np.prod(nt))
         thick = np.zeros(6 * n_tasks)
         stats = np.zeros((16, 4), np.int64)
