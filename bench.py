@@ -688,7 +688,7 @@ def main():
 
     if not args.no_decomposed and not args.fwd_only and w.name.startswith("clustered"):
         torch.cuda.empty_cache()
-        out["decomposed"] = decomposed_form(torch, vt, w, opts=tuned if prec == vt.PREC_FP64 else None)
+        out["decomposed"] = decomposed_form(torch, vt, w)
 
     if not args.no_extra:
         torch.cuda.empty_cache()
