@@ -174,15 +174,15 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t *key
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter.  Keys of a tile are ranked in index order: round-major, then wave, then lane;
+// Stable scatter of one tile.  Keys are ranked in index order: round-major, then wave, then lane;
 // lanes holding the same digit are found with eight ballots.  The tile is first reordered by digit
-// in LDS (its digit counts are the histogram pass's, their prefix the digits' starts in the tile),
-// then written out in that order: consecutive threads write consecutive slots of each digit's run
-// (16 keys per digit on average), not one scattered slot each.
-__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
-                                                                uint64_t *kout, uint32_t *vout, int64_t n,
-                                                                int shift, const int32_t *counts,
-                                                                const int32_t *offs, int nblocks) {
+// in LDS (its digit counts are the histogram's, their prefix the digits' starts in the tile), then
+// written out in that order: consecutive threads write consecutive slots of each digit's run (16
+// keys per digit on average), not one scattered slot each.  Thread t brings digit t's count in the
+// tile and its global offset.
+__device__ __forceinline__ void radix_scatter_tile(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                                                   uint32_t *vout, int64_t n, int shift, int64_t base,
+                                                   int32_t count_t, int64_t offset_t) {
     __shared__ int32_t running[256];   // next slot of each digit in the reordered tile
     __shared__ int64_t gbase[256];     // the digit's global offset minus its start in the tile
     __shared__ int32_t wcnt[SORT_THREADS / 64][256];
@@ -192,11 +192,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     {
         int32_t tot;
-        const int32_t start = block_exclusive_scan<int32_t>(counts[(int64_t)t * nblocks + blockIdx.x], scan_lds, &tot);
+        const int32_t start = block_exclusive_scan<int32_t>(count_t, scan_lds, &tot);
         running[t] = start;
-        gbase[t] = (int64_t)offs[(int64_t)t * nblocks + blockIdx.x] - start;
+        gbase[t] = offset_t - start;
     }
-    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int i = 0; i < SORT_ITEMS; ++i) {
         for (int ww = 0; ww < SORT_THREADS / 64; ++ww) wcnt[ww][t] = 0;
@@ -234,6 +233,48 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *
         const int64_t pos = gbase[(uint32_t)(key >> shift) & 255u] + idx;
         kout[pos] = key;
         vout[pos] = lval[idx];
+    }
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
+                                                                uint64_t *kout, uint32_t *vout, int64_t n,
+                                                                int shift, const int32_t *counts,
+                                                                const int32_t *offs, int nblocks) {
+    const int t = threadIdx.x;
+    radix_scatter_tile(kin, vin, kout, vout, n, shift, (int64_t)blockIdx.x * SORT_TILE,
+                       counts[(int64_t)t * nblocks + blockIdx.x], (int64_t)offs[(int64_t)t * nblocks + blockIdx.x]);
+}
+
+// The whole sort of at most one tile (SORT_TILE keys) in one block: every pass's histogram, digit
+// offsets and scatter, the passes ping-ponging between the two buffers (a pass reads what the
+// block wrote in the one before, after a block barrier).  Small inputs then take one launch
+// instead of five per pass.
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_tile(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                                                             int64_t n, int key_bits) {
+    __shared__ int32_t h[256];
+    __shared__ int32_t scan_h[SORT_THREADS];
+    const int t = threadIdx.x;
+    uint64_t *kin = k0, *kout = k1;
+    uint32_t *vin = v0, *vout = v1;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        h[t] = 0;
+        __syncthreads();
+        for (int i = 0; i < SORT_ITEMS; ++i) {
+            const int64_t k = (int64_t)i * SORT_THREADS + t;
+            if (k < n) atomicAdd(&h[(kin[k] >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        const int32_t cnt = h[t];
+        int32_t tot;
+        const int32_t off = block_exclusive_scan<int32_t>(cnt, scan_h, &tot);
+        radix_scatter_tile(kin, vin, kout, vout, n, shift, 0, cnt, (int64_t)off);
+        __syncthreads();
+        uint64_t *tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t *tv = vin;
+        vin = vout;
+        vout = tv;
     }
 }
 
@@ -428,7 +469,12 @@ hipError_t vt_launch_sort(vt_ctx *c, const void *pos, const int32_t *gid) {
     else
         k_keys<double><<<grid, tpb, 0, s>>>((const double *)pos, n, c->items, c->n_items, c->keys[0], c->vals[0]);
     int cur = 0;
-    for (int shift = 0; shift < c->key_bits; shift += 8) {
+    if (nb == 1) {
+        // one tile: the whole radix sort in one block
+        k_radix_tile<<<1, SORT_THREADS, 0, s>>>(c->keys[0], c->vals[0], c->keys[1], c->vals[1], n, c->key_bits);
+        cur = ((c->key_bits + 7) / 8) & 1;
+    }
+    for (int shift = 0; nb > 1 && shift < c->key_bits; shift += 8) {
         k_radix_hist<<<nb, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift, c->hist, nb);
         hipError_t e = vt_launch_scan_i32(c->hist, c->hist + (int64_t)256 * nb, (int64_t)256 * nb, c->scan_tmp, s);
         if (e != hipSuccess) return e;
