@@ -104,11 +104,37 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const T *in, T *out,
     if (write_total && blockIdx.x == 0 && threadIdx.x == 0) out[n] = (T)sums[nb];
 }
 
+// a scan of at most one tile: the block's own prefix, and the total, in one launch
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_single(const T *in, T *out, int64_t n) {
+    __shared__ int64_t lds[SCAN_THREADS];
+    const int t = threadIdx.x;
+    int64_t acc = 0;
+    T loc[SCAN_ITEMS];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = (int64_t)t * SCAN_ITEMS + i;
+        loc[i] = k < n ? in[k] : T(0);
+        acc += (int64_t)loc[i];
+    }
+    int64_t tot;
+    int64_t off = block_exclusive_scan<int64_t>(acc, lds, &tot);
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = (int64_t)t * SCAN_ITEMS + i;
+        if (k < n) out[k] = (T)off;
+        off += (int64_t)loc[i];
+    }
+    if (t == 0) out[n] = (T)tot;
+}
+
 template <typename T>
 static hipError_t scan_impl(const T *in, T *out, int64_t n, int64_t *tmp, hipStream_t s) {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) nb = 1;
     if (nb > SCAN_THREADS * 64) return hipErrorInvalidValue;
+    if (nb == 1) {
+        k_scan_single<T><<<1, SCAN_THREADS, 0, s>>>(in, out, n);
+        return hipGetLastError();
+    }
     k_scan_reduce<T><<<nb, SCAN_THREADS, 0, s>>>(in, n, tmp);
     k_scan_top<<<1, SCAN_THREADS, 0, s>>>(tmp, nb);
     k_scan_down<T><<<nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp, 1, nb);
