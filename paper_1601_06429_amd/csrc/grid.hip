@@ -37,7 +37,8 @@ struct GridMem {
     int32_t fpl[FMAX][2];    // planes strictly inside the face's x range: m0, count
     int32_t ipre[FMAX + 1];  // prefix of work items per face
     int32_t fid[FMAX];       // compacted face slots
-    uint64_t iq[128];        // work items queued for integration (face, plane, rectangle offsets)
+    uint64_t iq[2][128];     // work items queued for integration (face, plane, rectangle offsets):
+                             // [0] the faces' lowest planes (pi == 0), [1] planes that cut a face
     double acc[ACC];         // the cell's contributions per voxel of its box
     PolyMem<double, VPL> P;
 };
@@ -161,9 +162,9 @@ __device__ __forceinline__ void slab(double a, double b, double ib, double lo, d
 // rnx = 1 / n_x.  One pass over Omega's edges clips each edge to R ∩ H and, for
 // every edge, restricts R's four edges and the chord to its inner side; those
 // segments are integrated after the pass.
-template <int VPL>
+template <int VPL, bool useH>
 __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, int m, double Y0, double Z0, double hy, double hz,
-                                bool useH, double hs, double e, double ny, double nz, double X, double rnx) {
+                                double hs, double e, double ny, double nz, double X, double rnx) {
     Reg D = {0.0, 0.0};
     auto gH = [&](double y, double z) { return hs * (e - ny * y - nz * z); };
     const double Oy = S.lp[o][1] - Y0, Oz = S.lp[o][2] - Z0, gO = S.lp[o][0] - X;
@@ -179,7 +180,7 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
     // the chord x = X: a segment through the point of the line nearest R's centre, long
     // enough to cross R, directed with H on its left (x - X = 0 on it), clipped to R
     double cy0 = 0.0, cz0 = 0.0, cy1 = 0.0, cz1 = 0.0, ct0 = 0.0, ct1 = 0.0;
-    if (useH) {
+    if constexpr (useH) {
         const double nn = ny * ny + nz * nz;
         const double cy = 0.5 * hy, cz = 0.5 * hz;
         const double sft = (ny * cy + nz * cz - e) / nn;
@@ -212,7 +213,7 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
             double t0 = 0.0, t1 = 1.0;
             slab(y0, dy, iby, 0.0, hy, t0, t1);
             slab(z0, dz, ibz, 0.0, hz, t0, t1);
-            if (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
+            if constexpr (useH) cyrus_beck(gH(y0, z0), gH(y1, z1), t0, t1);
             if (t0 < t1) tri(y0 + t0 * dy, z0 + t0 * dz, xa + t0 * dx, y0 + t1 * dy, z0 + t1 * dz, xa + t1 * dx);
         }
         // (b) crossings with z = 0 (edge 0, t = y / hy), y = hy (edge 1, t = z / hz),
@@ -240,7 +241,7 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
             crossed[3] |= (rt3 || lf3) ? 1 : 0;
         }
         // (c) the chord restricted to the inner side of this edge
-        cyrus_beck(dy * (cz0 - z0) - dz * (cy0 - y0), dy * (cz1 - z0) - dz * (cy1 - y0), ct0, ct1);
+        if constexpr (useH) cyrus_beck(dy * (cz0 - z0) - dz * (cy0 - y0), dy * (cz1 - z0) - dz * (cy1 - y0), ct0, ct1);
         y0 = y1;
         z0 = z1;
         xa = xb;
@@ -255,7 +256,7 @@ __device__ __forceinline__ Reg region_integrals(const GridMem<VPL> &S, int o, in
     for (int r = 0; r < 4; ++r) {
         const double qy0 = ry[r], qz0 = rz[r], qy1 = ry[r + 1], qz1 = rz[r + 1];
         double t0 = rt0[r], t1 = rt1[r];
-        if (useH) cyrus_beck(gH(qy0, qz0), gH(qy1, qz1), t0, t1);
+        if constexpr (useH) cyrus_beck(gH(qy0, qz0), gH(qy1, qz1), t0, t1);
         if (t0 < t1) {
             const double dy = qy1 - qy0, dz = qz1 - qz0;
             const double ya = qy0 + t0 * dy, za = qz0 + t0 * dz, yb = qy0 + t1 * dy, zb = qz0 + t1 * dz;
@@ -595,51 +596,28 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
             // from the lowest up to the first that cuts the face over R, as the bound above falls
             // with X).  The others are queued and integrated 64 at a time, so the lanes of an
             // integration pass all have an item.
-            int head = 0, qn = 0;
-            for (int base = 0; base < nitem; base += 64) {
-                const int item = base + lane;
-                bool need = false;
-                uint64_t desc = 0;
-                if (item < nitem) {
-                    int lo = 0, hi = nf - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
-                    }
-                    const int q = lo;
-                    int pi, rj;
-                    const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
-                    const int rk = divmod_small(r, S.frect[q][1], rj);
-                    const ItemGeo g = geometry(q, pi, rj, rk);
-                    const double cy_ = -g.hs * S.fn[q][1] * h[1], cz_ = -g.hs * S.fn[q][2] * h[2];
-                    const double above_max = g.hs * g.e + fmax(0.0, cy_) + fmax(0.0, cz_);
-                    const double above_min = g.hs * g.e + fmin(0.0, cy_) + fmin(0.0, cz_);
-                    need = pi == 0 || (above_max > 0.0 && above_min < 0.0);
-                    desc = (uint64_t)q | ((uint64_t)pi << 8) | ((uint64_t)rj << 24) | ((uint64_t)rk << 44);
-                }
-                const uint64_t nb = __ballot(need);
-                if (need) S.iq[(head + qn + __popcll(nb & lt)) & 127] = desc;
-                qn += __popcll(nb);
-                const bool last = base + 64 >= nitem;
-                while (qn >= 64 || (last && qn > 0)) {
+            // The two kinds of item go to rings of their own and are integrated 64 at a time, each
+            // kind by its own specialisation: a face's lowest plane (pi == 0) never clips the face
+            // with H, and a queued plane above it (pi > 0) always does, since it is queued only
+            // when the face lies on both sides of it over R (above_min < 0).
+            int head[2] = {0, 0}, qn[2] = {0, 0};
+            auto integrate = [&](auto kind, bool last) {
+                constexpr bool useH = decltype(kind)::value;
+                constexpr int w = useH ? 1 : 0;
+                while (qn[w] >= 64 || (last && qn[w] > 0)) {
                     wave_sync();
-                    const int take = qn < 64 ? qn : 64;
+                    const int take = qn[w] < 64 ? qn[w] : 64;
                     if (lane < take) {
-                        const uint64_t d = S.iq[(head + lane) & 127];
+                        const uint64_t d = S.iq[w][(head[w] + lane) & 127];
                         const int q = (int)(d & 0xFFull), pi = (int)((d >> 8) & 0xFFFFull);
                         const int rj = (int)((d >> 24) & 0xFFFFFull), rk = (int)((d >> 44) & 0xFFFFFull);
                         const ItemGeo g = geometry(q, pi, rj, rk);
                         const double nx_ = S.fn[q][0], ny_ = S.fn[q][1], nz_ = S.fn[q][2];
                         const double hs = g.hs, rnx = 1.0 / nx_;
                         const int o = S.loff[q], m = S.loff[q + 1] - o;
-                        // a face entirely above X over R is not clipped by H
-                        const double cy_ = -hs * ny_ * h[1], cz_ = -hs * nz_ * h[2];
-                        const double above_min = hs * g.e + fmin(0.0, cy_) + fmin(0.0, cz_);
-                        const bool useH = pi > 0 && above_min < 0.0;
-                        const Reg Rg =
-                            region_integrals<VPL>(S, o, m, g.Y0, g.Z0, h[1], h[2], useH, hs, g.e, ny_, nz_, g.X, rnx);
+                        const Reg Rg = region_integrals<VPL, useH>(S, o, m, g.Y0, g.Z0, h[1], h[2], hs, g.e, ny_, nz_, g.X, rnx);
                         const double G = hs * Rg.G;
-                        if (pi == 0) {
+                        if constexpr (!useH) {
                             if (Rg.A != 0.0) {
                                 // full voxels below the face's x minimum, within the cell's own range
                                 const int64_t iend = g.mm < i0[0] + bx ? g.mm : i0[0] + bx;
@@ -647,6 +625,7 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
                                 emit(g.mm, g.jj, g.kk, G);
                                 // the planes with the face entirely above them over R (classified
                                 // with the same geometry and bound, so none is queued as well)
+                                const double cy_ = -hs * ny_ * h[1], cz_ = -hs * nz_ * h[2];
                                 const int npl = S.fpl[q][1];
 #pragma unroll 1
                                 for (int p = 1; p <= npl; ++p) {
@@ -665,10 +644,44 @@ __device__ __forceinline__ void grid_body(const GridArgs &A, char *smem, int wid
                             emit(g.mm, g.jj, g.kk, G);
                         }
                     }
-                    head += take;
-                    qn -= take;
+                    head[w] += take;
+                    qn[w] -= take;
                     wave_sync();
                 }
+            };
+            for (int base = 0; base < nitem; base += 64) {
+                const int item = base + lane;
+                bool need = false;
+                int kind = 0;
+                uint64_t desc = 0;
+                if (item < nitem) {
+                    int lo = 0, hi = nf - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (S.ipre[mid] <= item) lo = mid; else hi = mid - 1;
+                    }
+                    const int q = lo;
+                    int pi, rj;
+                    const int r = divmod_small(item - S.ipre[q], 1 + S.fpl[q][1], pi);
+                    const int rk = divmod_small(r, S.frect[q][1], rj);
+                    const ItemGeo g = geometry(q, pi, rj, rk);
+                    const double cy_ = -g.hs * S.fn[q][1] * h[1], cz_ = -g.hs * S.fn[q][2] * h[2];
+                    const double above_max = g.hs * g.e + fmax(0.0, cy_) + fmax(0.0, cz_);
+                    const double above_min = g.hs * g.e + fmin(0.0, cy_) + fmin(0.0, cz_);
+                    need = pi == 0 || (above_max > 0.0 && above_min < 0.0);
+                    kind = pi == 0 ? 0 : 1;
+                    desc = (uint64_t)q | ((uint64_t)pi << 8) | ((uint64_t)rj << 24) | ((uint64_t)rk << 44);
+                }
+                const uint64_t n0 = __ballot(need && kind == 0), n1 = __ballot(need && kind == 1);
+                if (need) {
+                    const uint64_t nb = kind == 0 ? n0 : n1;
+                    S.iq[kind][(head[kind] + qn[kind] + __popcll(nb & lt)) & 127] = desc;
+                }
+                qn[0] += __popcll(n0);
+                qn[1] += __popcll(n1);
+                const bool last = base + 64 >= nitem;
+                integrate(std::integral_constant<bool, false>(), last);
+                integrate(std::integral_constant<bool, true>(), last);
             }
             wave_sync();
             for (int t = lane; t < nacc; t += 64) {
