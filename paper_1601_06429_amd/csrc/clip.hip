@@ -498,15 +498,19 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             total = uni_i(carry);
             return uni_i(count);
         };
-        // particle f of the flattened cover -> sorted index, separation, d^2
-        // particle f of the flattened cover -> its sorted index
-        auto locate = [&](int f, int ncq) -> int32_t {
-            int lo = 0, hi = ncq - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (S.rp[mid] <= f) lo = mid; else hi = mid - 1;
-            }
-            return S.rb[lo] + (f - S.rp[lo]);
+        // Particles f = nb + lane of a cover, chunk by chunk in order (nb = 0, 64, ...): its ranges
+        // start at pre[0..ncq) (strictly increasing from pre[0] = 0, no range empty) at sorted
+        // indices rbase[], and rcur holds the range of the previous chunk's last particle (0 before
+        // the first chunk).  The starts of the next 64 ranges, as bits of the chunk, give each lane
+        // its range by a population count: one LDS round trip and a wave OR per chunk, instead of a
+        // binary search per particle.
+        auto chunk_loc = [&](const int32_t *pre, const int32_t *rbase, int ncq, int &rcur, int nb) -> int32_t {
+            const int k = rcur + 1 + lane;
+            const int32_t s_ = k < ncq ? pre[k] - nb : 64;
+            const uint64_t starts = wave_or_u64(s_ >= 0 && s_ < 64 ? 1ull << s_ : 0ull);
+            const int r = rcur + __popcll(starts & ((2ull << lane) - 1ull));
+            rcur = uni_i(__builtin_amdgcn_readlane(r, 63));
+            return rbase[r] + (nb + lane - pre[r]);
         };
         // The large kernel's sweeps: its cells lie next to dense halos, whose thousands of particles
         // sit in a few covering boxes that some vertex's empty sphere reaches at their edge.  The
@@ -710,19 +714,6 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 return -1;
             }
         };
-        // particle f of the refined cover -> its sorted index
-        auto locate_fine = [&](int f, int ncq) -> int32_t {
-            if constexpr (RETRY && VPL > 1) {
-                int lo = 0, hi = ncq - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (S.fine.n[fin][mid] <= f) lo = mid; else hi = mid - 1;
-                }
-                return S.fine.b[fin][lo] + (f - S.fine.n[fin][lo]);
-            } else {
-                return 0;
-            }
-        };
         // a loaded position -> separation from the seed (minimum image), d^2
         auto separation = [&](const PT4 &p, double &dx, double &dy, double &dz) -> double {
             dx = (double)p.x - sx;
@@ -748,15 +739,25 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             if constexpr (RETRY) ncq = cover_fine(r_hi, r_lo, total);
             const bool fine_ = RETRY && ncq >= 0;
             if (!fine_) ncq = cover(r_hi, r_lo, total, true);
-            auto loc = [&](int f) -> int32_t { return fine_ ? locate_fine(f, ncq) : locate(f, ncq); };
+            const int32_t *lpre = S.rp, *lrb = S.rb;
+            if constexpr (RETRY && VPL > 1) {
+                if (fine_) {
+                    lpre = S.fine.n[fin];
+                    lrb = S.fine.b[fin];
+                }
+            }
+            int rcur = 0;
             bool dirty = false, r2stale = false;
             int rr = 0;  // refined cover: box of the chunk's first particle
             // positions of the next 64 particles are loaded while the current 64 are tested
             int32_t jn = -1;
             PT4 pn{};
-            if (lane < total) {
-                jn = loc(lane);
-                pn = ((const PT4 *)A.spos)[jn];
+            if (total > 0) {
+                const int32_t j_ = chunk_loc(lpre, lrb, ncq, rcur, 0);
+                if (lane < total) {
+                    jn = j_;
+                    pn = ((const PT4 *)A.spos)[jn];
+                }
             }
             for (int base = 0; base < total && !overflow && !corrupt; base += WAVE) {
                 if constexpr (RETRY && VPL > 1) {
@@ -775,9 +776,12 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
                 const int32_t j = jn;
                 const PT4 pc = pn;
-                if (f + WAVE < total) {
-                    jn = loc(f + WAVE);
-                    pn = ((const PT4 *)A.spos)[jn];
+                if (base + WAVE < total) {
+                    const int32_t j_ = chunk_loc(lpre, lrb, ncq, rcur, base + WAVE);
+                    if (f + WAVE < total) {
+                        jn = j_;
+                        pn = ((const PT4 *)A.spos)[jn];
+                    }
                 }
                 if (f < total) {
                     d2 = separation(pc, dx, dy, dz);
@@ -888,9 +892,13 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
             int n = 0;
             int32_t jn = -1;
             PT4 pn{};
-            if (lane < total) {
-                jn = locate(lane, ncq);
-                pn = ((const PT4 *)A.spos)[jn];
+            int rcur = 0;
+            if (total > 0) {
+                const int32_t j_ = chunk_loc(S.rp, S.rb, ncq, rcur, 0);
+                if (lane < total) {
+                    jn = j_;
+                    pn = ((const PT4 *)A.spos)[jn];
+                }
             }
             for (int base = 0; base < total; base += WAVE) {
                 const int f = base + lane;
@@ -898,9 +906,12 @@ __device__ __forceinline__ void clip_cells(const ClipArgs &A) {
                 double dx = 0, dy = 0, dz = 0, d2 = 0;
                 const int32_t j = jn;
                 const PT4 pc = pn;
-                if (f + WAVE < total) {
-                    jn = locate(f + WAVE, ncq);
-                    pn = ((const PT4 *)A.spos)[jn];
+                if (base + WAVE < total) {
+                    const int32_t j_ = chunk_loc(S.rp, S.rb, ncq, rcur, base + WAVE);
+                    if (f + WAVE < total) {
+                        jn = j_;
+                        pn = ((const PT4 *)A.spos)[jn];
+                    }
                 }
                 if (f < total) {
                     d2 = separation(pc, dx, dy, dz);

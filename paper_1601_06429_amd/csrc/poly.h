@@ -128,6 +128,20 @@ __device__ __forceinline__ double wave_ext_d(double v) {
 }
 __device__ __forceinline__ double wave_max_x(double v) { return wave_ext_d<true>(v); }
 __device__ __forceinline__ double wave_min_x(double v) { return wave_ext_d<false>(v); }
+// bitwise OR over the wave by the same steps (moves only; the result in every lane)
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+    auto D = [](uint64_t x) { return __longlong_as_double((long long)x); };
+    auto U = [](double x) { return (uint64_t)__double_as_longlong(x); };
+    v |= U(dpp_d<DPP_XOR1>(D(v)));
+    v |= U(dpp_d<DPP_XOR2>(D(v)));
+    v |= U(dpp_d<DPP_HALF_MIRROR>(D(v)));
+    v |= U(dpp_d<DPP_MIRROR>(D(v)));
+    double a, b;
+    row_swap_d<false>(D(v), a, b);
+    v = U(a) | U(b);
+    row_swap_d<true>(D(v), a, b);
+    return U(a) | U(b);
+}
 
 // The value of lane l ^ J, without LDS: DPP for J < 16 (neighbour and pair swaps within quads;
 // for 4 and 8, shifts within the row whose bank mask picks the lanes that read upwards or
